@@ -1,0 +1,565 @@
+/*
+ * CPU oracle for the multi-scale LFK community growth sweep.
+ *
+ * TEST INFRASTRUCTURE, NOT PRODUCT CODE.  Only the test suite, the smoke
+ * check and the benchmark's CPU-baseline leg build, load or call this file.
+ * The HIP library shares nothing with it: no header, helper, table or
+ * constant.
+ *
+ * Source: E. Le Martelot and C. Hankin, "Fast Multi-Scale Community
+ * Detection based on Local Criteria within a Multi-Threaded Algorithm"
+ * (arXiv:1301.0955).
+ *
+ *   f_c   = k_in / (k_in + k_out)^alpha               Sec. 2, Eq. (1)
+ *   f_c^i = f_{c+i} - f_{c-i}; a node joins or leaves   Sec. 2, Eq. (2)
+ *           c only if that raises f_c
+ *   growth: max priority queue ranked by              Sec. 2, Algorithm 1
+ *           2 d_in / (d_in + d_out)^alpha, then passes
+ *           that drop members whose removal raises f_c
+ *   chain:  the result at one scale is the start of    Sec. 2 (method); Sec. 3
+ *           the next, scales ordered by coarseness      (Algorithm 2, growth half)
+ *
+ * Readings of points the paper leaves open (each is also stated where used):
+ *   R1 k_in counts every internal edge from both ends (so adding node n
+ *      raises it by 2 d_in(n)) and k_in + k_out is the community volume
+ *      V = sum of member degrees.  All of K = k_in, V, d_in, degrees are
+ *      exact integers (edge weights are positive integers).
+ *   R2 "n improves Q_c" is decided in the log domain:
+ *        t = (L(K') - L(K)) - alpha * (L(V') - L(V)),  improve <=> t > 2^-40
+ *      with K' = 0 never improving and K = 0 (< K') always improving.  L is
+ *      lcdo_log below, a fully specified natural log of a positive integer,
+ *      evaluated with IEEE double operations in a fixed order (no FMA).
+ *   R3 rank R(d, k) = L(2d) - alpha * L(k); equal ranks pop the smaller id.
+ *   R4 a popped node that does not improve Q_c is re-queued only when a
+ *      later addition changes its d_in (the queue update of Algorithm 1).
+ *   R5 removal passes visit the members present at the start of the pass in
+ *      ascending id and apply each removal at once; at most k_prune passes
+ *      (0 = until a pass removes nothing); no pass if nothing was added.
+ *   R6 without the merge phase, "while changes can be made" is the
+ *      fixpoint of the growth function at each scale.
+ *   R7 the reported criterion value is f = K / pow(V, alpha) (0 when K = 0).
+ *
+ * Work counters (the definition the GPU must reproduce):
+ *   G  one per criterion evaluation: each queue pop and each member visited
+ *      by a removal pass;
+ *   R  one per rank (re)computation: each node put in the queue when it is
+ *      built and each non-member neighbour of an added node;
+ *   M  one per node added or removed;
+ *   C  one per call of the growth function.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* R2: L(x), natural log of an integer 1 <= x < 2^53.                        */
+/* x = m * 2^e with m in (sqrt(2)/2, sqrt(2)]; ln m = 2 atanh(s),            */
+/* s = (m - 1) / (m + 1), summed as 2 s (1 + z/3 + ... + z^11/23), z = s^2;   */
+/* ln 2 is split in a high part with trailing zero bits and a low part       */
+/* (Cody and Waite) so that e * ln2_hi is exact.                             */
+/* ------------------------------------------------------------------------ */
+#define LCDO_SQRT2 0x1.6a09e667f3bcdp+0
+#define LCDO_LN2_HI 6.93147180369123816490e-01
+#define LCDO_LN2_LO 1.90821492927058770002e-10
+
+double lcdo_log(uint64_t x)
+{
+    int e = 63;
+    while (!((x >> e) & 1u))
+        --e;
+    double m = (double)x;
+    double scale = 1.0;
+    for (int i = 0; i < e; ++i)
+        scale *= 0.5;               /* exact: a power of two */
+    m = m * scale;                  /* exact */
+    if (m > LCDO_SQRT2) {
+        m = m * 0.5;
+        e = e + 1;
+    }
+    double s = (m - 1.0) / (m + 1.0);
+    double z = s * s;
+    double p = 1.0 / 23.0;
+    p = p * z + 1.0 / 21.0;
+    p = p * z + 1.0 / 19.0;
+    p = p * z + 1.0 / 17.0;
+    p = p * z + 1.0 / 15.0;
+    p = p * z + 1.0 / 13.0;
+    p = p * z + 1.0 / 11.0;
+    p = p * z + 1.0 / 9.0;
+    p = p * z + 1.0 / 7.0;
+    p = p * z + 1.0 / 5.0;
+    p = p * z + 1.0 / 3.0;
+    p = p * z + 1.0;
+    double h = s * p;
+    double lnm = h + h;
+    double de = (double)e;
+    return de * LCDO_LN2_HI + (de * LCDO_LN2_LO + lnm);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tracing hook for the audits in the test suite.                            */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t K, V, Kp, Vp;
+    double alpha, t;
+    int32_t kind;      /* 0 = add test, 1 = removal test */
+    int32_t result;    /* 1 = improves */
+    int32_t node;      /* the node tested */
+    int32_t pad;
+    uint64_t mask;     /* member set after the decision, bit u (n <= 64) */
+} lcdo_trace_rec;
+
+typedef struct {
+    lcdo_trace_rec *rec;
+    int64_t cap;
+    int64_t count;     /* may exceed cap: records past cap are dropped */
+} lcdo_trace;
+
+/* R2: "is f(K', V') > f(K, V)" at scale alpha. */
+static int lcdo_improves(int64_t Kp, int64_t Vp, int64_t K, int64_t V,
+                         double alpha, double *t_out)
+{
+    if (Kp == 0) {
+        *t_out = NAN;
+        return 0;
+    }
+    if (K == 0) {
+        *t_out = INFINITY;
+        return 1;
+    }
+    double a = lcdo_log((uint64_t)Kp) - lcdo_log((uint64_t)K);
+    double b = lcdo_log((uint64_t)Vp) - lcdo_log((uint64_t)V);
+    double c = alpha * b;
+    double t = a - c;
+    *t_out = t;
+    return t > 0x1p-40;
+}
+
+double lcdo_rank(int64_t d, int64_t k, double alpha)
+{
+    double c = alpha * lcdo_log((uint64_t)k);
+    return lcdo_log((uint64_t)(2 * d)) - c;
+}
+
+int lcdo_improves_export(int64_t Kp, int64_t Vp, int64_t K, int64_t V,
+                         double alpha, double *t_out)
+{
+    return lcdo_improves(Kp, Vp, K, V, alpha, t_out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Graph and per-community working state                                     */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double r;
+    int32_t u;
+    uint32_t ver;
+} lcdo_qent;
+
+typedef struct {
+    int32_t n;
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const uint8_t *w;      /* NULL: all weights 1 */
+    int64_t *k;            /* weighted degree of every node */
+    /* state of the community being grown; every array indexed by node id */
+    int64_t *d;            /* d_in: weight from the node into c */
+    uint8_t *in_c;
+    uint8_t *queued;
+    uint32_t *ver;
+    uint8_t *seen;
+    int32_t *touched;      /* nodes whose entries above may be non-zero */
+    int64_t n_touched;
+    int32_t *members;      /* scratch for one removal pass */
+    lcdo_qent *heap;
+    int64_t heap_n, heap_cap;
+    int64_t K, V;
+    int32_t size;
+    uint64_t G, R, M;
+    lcdo_trace *trace;
+} lcdo_ctx;
+
+static int64_t lcdo_w(const lcdo_ctx *g, int64_t j)
+{
+    return g->w ? (int64_t)g->w[j] : 1;
+}
+
+lcdo_ctx *lcdo_ctx_new(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                       const uint8_t *w)
+{
+    lcdo_ctx *g = (lcdo_ctx *)calloc(1, sizeof(lcdo_ctx));
+    if (!g)
+        return NULL;
+    g->n = n;
+    g->row_ptr = row_ptr;
+    g->col = col;
+    g->w = w;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    g->k = (int64_t *)calloc(nn, sizeof(int64_t));
+    g->d = (int64_t *)calloc(nn, sizeof(int64_t));
+    g->in_c = (uint8_t *)calloc(nn, 1);
+    g->queued = (uint8_t *)calloc(nn, 1);
+    g->ver = (uint32_t *)calloc(nn, sizeof(uint32_t));
+    g->seen = (uint8_t *)calloc(nn, 1);
+    g->touched = (int32_t *)malloc(nn * sizeof(int32_t));
+    g->members = (int32_t *)malloc(nn * sizeof(int32_t));
+    g->heap_cap = 1024;
+    g->heap = (lcdo_qent *)malloc((size_t)g->heap_cap * sizeof(lcdo_qent));
+    if (!g->k || !g->d || !g->in_c || !g->queued || !g->ver || !g->seen ||
+        !g->touched || !g->members || !g->heap)
+        return NULL;
+    for (int32_t u = 0; u < n; ++u) {
+        int64_t s = 0;
+        for (int64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j)
+            s += lcdo_w(g, j);
+        g->k[u] = s;
+    }
+    return g;
+}
+
+void lcdo_ctx_free(lcdo_ctx *g)
+{
+    if (!g)
+        return;
+    free(g->k);
+    free(g->d);
+    free(g->in_c);
+    free(g->queued);
+    free(g->ver);
+    free(g->seen);
+    free(g->touched);
+    free(g->members);
+    free(g->heap);
+    free(g);
+}
+
+const int64_t *lcdo_degrees(const lcdo_ctx *g) { return g->k; }
+
+static void lcdo_touch(lcdo_ctx *g, int32_t u)
+{
+    if (!g->seen[u]) {
+        g->seen[u] = 1;
+        g->touched[g->n_touched++] = u;
+    }
+}
+
+/* --- max priority queue: higher rank first, equal rank -> smaller id --- */
+static int lcdo_before(const lcdo_qent *a, const lcdo_qent *b)
+{
+    return a->r > b->r || (a->r == b->r && a->u < b->u);
+}
+
+static void lcdo_push(lcdo_ctx *g, double r, int32_t u, uint32_t ver)
+{
+    if (g->heap_n == g->heap_cap) {
+        g->heap_cap *= 2;
+        g->heap = (lcdo_qent *)realloc(g->heap, (size_t)g->heap_cap * sizeof(lcdo_qent));
+    }
+    int64_t i = g->heap_n++;
+    lcdo_qent e = {r, u, ver};
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (!lcdo_before(&e, &g->heap[p]))
+            break;
+        g->heap[i] = g->heap[p];
+        i = p;
+    }
+    g->heap[i] = e;
+}
+
+static lcdo_qent lcdo_pop(lcdo_ctx *g)
+{
+    lcdo_qent top = g->heap[0];
+    lcdo_qent last = g->heap[--g->heap_n];
+    int64_t i = 0;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, b = i;
+        const lcdo_qent *best = &last;
+        if (l < g->heap_n && lcdo_before(&g->heap[l], best)) {
+            b = l;
+            best = &g->heap[l];
+        }
+        if (r < g->heap_n && lcdo_before(&g->heap[r], best)) {
+            b = r;
+            best = &g->heap[r];
+        }
+        if (b == i)
+            break;
+        g->heap[i] = g->heap[b];
+        i = b;
+    }
+    if (g->heap_n > 0)
+        g->heap[i] = last;
+    return top;
+}
+
+/* Put u in the queue, or move it to its new rank if it is there already. */
+static void lcdo_queue(lcdo_ctx *g, int32_t u, double alpha)
+{
+    g->ver[u] += 1;
+    g->queued[u] = 1;
+    lcdo_push(g, lcdo_rank(g->d[u], g->k[u], alpha), u, g->ver[u]);
+    g->R += 1;
+}
+
+static uint64_t lcdo_mask(const lcdo_ctx *g)
+{
+    uint64_t m = 0;
+    if (g->n > 64)
+        return 0;
+    for (int32_t u = 0; u < g->n; ++u)
+        if (g->in_c[u])
+            m |= (uint64_t)1 << u;
+    return m;
+}
+
+static int lcdo_decide(lcdo_ctx *g, int kind, int32_t node, int64_t Kp, int64_t Vp,
+                       double alpha)
+{
+    double t;
+    int r = lcdo_improves(Kp, Vp, g->K, g->V, alpha, &t);
+    if (g->trace) {
+        lcdo_trace *tr = g->trace;
+        if (tr->count < tr->cap) {
+            lcdo_trace_rec *x = &tr->rec[tr->count];
+            x->K = g->K;
+            x->V = g->V;
+            x->Kp = Kp;
+            x->Vp = Vp;
+            x->alpha = alpha;
+            x->t = t;
+            x->kind = kind;
+            x->result = r;
+            x->node = node;
+            x->pad = 0;
+            x->mask = 0;
+        }
+        tr->count += 1;
+    }
+    return r;
+}
+
+static void lcdo_trace_mask(lcdo_ctx *g)
+{
+    if (g->trace && g->trace->count <= g->trace->cap && g->trace->count > 0)
+        g->trace->rec[g->trace->count - 1].mask = lcdo_mask(g);
+}
+
+static void lcdo_add(lcdo_ctx *g, int32_t u, double alpha)
+{
+    g->in_c[u] = 1;
+    g->K += 2 * g->d[u];
+    g->V += g->k[u];
+    g->size += 1;
+    g->M += 1;
+    for (int64_t j = g->row_ptr[u]; j < g->row_ptr[u + 1]; ++j) {
+        int32_t v = g->col[j];
+        g->d[v] += lcdo_w(g, j);
+        lcdo_touch(g, v);
+        if (!g->in_c[v])
+            lcdo_queue(g, v, alpha);   /* R4: update or (re)insert */
+    }
+}
+
+static void lcdo_remove(lcdo_ctx *g, int32_t u)
+{
+    g->in_c[u] = 0;
+    g->K -= 2 * g->d[u];
+    g->V -= g->k[u];
+    g->size -= 1;
+    g->M += 1;
+    for (int64_t j = g->row_ptr[u]; j < g->row_ptr[u + 1]; ++j)
+        g->d[g->col[j]] -= lcdo_w(g, j);
+}
+
+static int lcdo_cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Algorithm 1: one call of the growth function at scale alpha.
+ * Returns the number of nodes added or removed. */
+static int64_t lcdo_grow(lcdo_ctx *g, double alpha, uint32_t k_prune)
+{
+    int64_t moves = 0;
+    int added = 0;
+    g->heap_n = 0;
+    /* build the queue from every non-member with a link into c */
+    for (int64_t i = 0; i < g->n_touched; ++i) {
+        int32_t u = g->touched[i];
+        g->queued[u] = 0;
+        if (!g->in_c[u] && g->d[u] > 0)
+            lcdo_queue(g, u, alpha);
+    }
+    while (g->heap_n > 0) {
+        lcdo_qent e = lcdo_pop(g);
+        int32_t u = e.u;
+        if (!g->queued[u] || e.ver != g->ver[u])
+            continue;               /* superseded entry */
+        g->queued[u] = 0;
+        g->G += 1;
+        if (lcdo_decide(g, 0, u, g->K + 2 * g->d[u], g->V + g->k[u], alpha)) {
+            lcdo_add(g, u, alpha);
+            lcdo_trace_mask(g);
+            moves += 1;
+            added = 1;
+        }
+    }
+    if (added) {
+        for (uint32_t pass = 0; k_prune == 0 || pass < k_prune; ++pass) {
+            int32_t m = 0;
+            for (int64_t i = 0; i < g->n_touched; ++i)
+                if (g->in_c[g->touched[i]])
+                    g->members[m++] = g->touched[i];
+            qsort(g->members, (size_t)m, sizeof(int32_t), lcdo_cmp_i32);
+            int removed = 0;
+            for (int32_t i = 0; i < m; ++i) {
+                int32_t u = g->members[i];
+                g->G += 1;
+                if (lcdo_decide(g, 1, u, g->K - 2 * g->d[u], g->V - g->k[u], alpha)) {
+                    lcdo_remove(g, u);
+                    lcdo_trace_mask(g);
+                    moves += 1;
+                    removed = 1;
+                }
+            }
+            if (!removed)
+                break;
+        }
+    }
+    return moves;
+}
+
+static void lcdo_reset(lcdo_ctx *g)
+{
+    for (int64_t i = 0; i < g->n_touched; ++i) {
+        int32_t u = g->touched[i];
+        g->d[u] = 0;
+        g->in_c[u] = 0;
+        g->queued[u] = 0;
+        g->seen[u] = 0;
+    }
+    g->n_touched = 0;
+    g->heap_n = 0;
+    g->K = g->V = 0;
+    g->size = 0;
+}
+
+/*
+ * Grow one initial community (Algorithm 2: "a set of initial communities"
+ * or a seed) through every scale in order.
+ *
+ * seeds[0..ns)      distinct node ids forming the initial community
+ * scales[0..S)      alpha values, finest first (decreasing alpha)
+ * k_prune           removal passes per growth call, 0 = unbounded (R5)
+ * out_members       members of scale s, ascending, at
+ *                   [out_off[s], out_off[s+1]); out_off has S+1 entries
+ * members_cap       capacity of out_members; on overflow returns -1 and
+ *                   out_off[S] still holds the size needed
+ * out_K, out_V      K and V per scale; out_f the reported f (R7)
+ * out_ctr           per scale: G, R, M, C (4 entries each)
+ */
+int lcdo_run_set(lcdo_ctx *g, const int32_t *seeds, int32_t ns,
+                 const double *scales, int32_t S, uint32_t k_prune,
+                 int32_t *out_members, int64_t members_cap, int64_t *out_off,
+                 int64_t *out_K, int64_t *out_V, double *out_f,
+                 uint64_t *out_ctr, lcdo_trace *trace)
+{
+    lcdo_reset(g);
+    g->trace = trace;
+    /* initial community: add the seed nodes without any test */
+    for (int32_t i = 0; i < ns; ++i) {
+        int32_t u = seeds[i];
+        lcdo_touch(g, u);
+        g->in_c[u] = 1;
+        g->K += 2 * g->d[u];
+        g->V += g->k[u];
+        g->size += 1;
+        for (int64_t j = g->row_ptr[u]; j < g->row_ptr[u + 1]; ++j) {
+            g->d[g->col[j]] += lcdo_w(g, j);
+            lcdo_touch(g, g->col[j]);
+        }
+    }
+    int64_t off = 0;
+    int overflow = 0;
+    for (int32_t s = 0; s < S; ++s) {
+        double alpha = scales[s];
+        g->G = g->R = g->M = 0;
+        uint64_t calls = 0;
+        for (;;) {                   /* R6: grow until nothing changes */
+            calls += 1;
+            if (lcdo_grow(g, alpha, k_prune) == 0)
+                break;
+        }
+        out_ctr[4 * s + 0] = g->G;
+        out_ctr[4 * s + 1] = g->R;
+        out_ctr[4 * s + 2] = g->M;
+        out_ctr[4 * s + 3] = calls;
+        out_K[s] = g->K;
+        out_V[s] = g->V;
+        out_f[s] = g->K == 0 ? 0.0 : (double)g->K / pow((double)g->V, alpha);
+        out_off[s] = off;
+        int32_t m = 0;
+        for (int64_t i = 0; i < g->n_touched; ++i)
+            if (g->in_c[g->touched[i]])
+                g->members[m++] = g->touched[i];
+        qsort(g->members, (size_t)m, sizeof(int32_t), lcdo_cmp_i32);
+        if (off + m <= members_cap)
+            memcpy(out_members + off, g->members, (size_t)m * sizeof(int32_t));
+        else
+            overflow = 1;
+        off += m;
+    }
+    out_off[S] = off;
+    g->trace = NULL;
+    return overflow ? -1 : 0;
+}
+
+/*
+ * Many independent initial communities.  Set j is seed_nodes[seed_ptr[j] ..
+ * seed_ptr[j+1]).  Records are indexed j * S + s; the members of record r
+ * are out_members[out_off[r] .. out_off[r] + out_cnt[r]).  Returns 0, or -1
+ * when members_cap was too small (*needed then holds the size required).
+ */
+int lcdo_run_sets(lcdo_ctx *g, const int32_t *seed_ptr, const int32_t *seed_nodes,
+                  int32_t n_sets, const double *scales, int32_t S, uint32_t k_prune,
+                  int32_t *out_members, int64_t members_cap, int64_t *needed,
+                  int64_t *out_off, int32_t *out_cnt, int64_t *out_K, int64_t *out_V,
+                  double *out_f, uint64_t *out_ctr)
+{
+    int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(S + 1));
+    if (!off)
+        return -2;
+    int64_t base = 0;
+    int status = 0;
+    for (int32_t j = 0; j < n_sets; ++j) {
+        int64_t room = members_cap - base;
+        if (room < 0)
+            room = 0;
+        int rc = lcdo_run_set(g, seed_nodes + seed_ptr[j], seed_ptr[j + 1] - seed_ptr[j],
+                              scales, S, k_prune,
+                              out_members ? out_members + (room > 0 ? base : 0) : NULL,
+                              out_members ? room : 0, off,
+                              out_K + (int64_t)j * S, out_V + (int64_t)j * S,
+                              out_f + (int64_t)j * S, out_ctr + (int64_t)j * S * 4, NULL);
+        if (rc != 0)
+            status = -1;
+        for (int32_t s = 0; s < S; ++s) {
+            out_off[(int64_t)j * S + s] = base + off[s];
+            out_cnt[(int64_t)j * S + s] = (int32_t)(off[s + 1] - off[s]);
+        }
+        base += off[S];
+    }
+    *needed = base;
+    free(off);
+    return status;
+}
+
+/* L(x) over an array (for the accuracy pins and the device comparison). */
+void lcdo_log_many(const uint64_t *x, double *out, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = lcdo_log(x[i]);
+}

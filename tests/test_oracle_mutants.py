@@ -1,0 +1,54 @@
+"""The pins must catch plausible mistakes in the oracle.
+
+Each case plants one mistake in a copy of the oracle's C source (on the
+CPU), builds it, and runs the pin tests against that build in a child
+process; every mutant must make at least one pin fail."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "lcd_oracle.c")
+
+MUTANTS = {
+    "k_in_single_count": ("g->K += 2 * g->d[u];\n    g->V += g->k[u];\n    g->size += 1;\n    g->M += 1;",
+                          "g->K += g->d[u];\n    g->V += g->k[u];\n    g->size += 1;\n    g->M += 1;"),
+    "removal_single_count": ("g->K -= 2 * g->d[u];", "g->K -= g->d[u];"),
+    "alpha_on_wrong_log": ("double c = alpha * lcdo_log((uint64_t)k);\n    return lcdo_log((uint64_t)(2 * d)) - c;",
+                           "double c = alpha * lcdo_log((uint64_t)(2 * d));\n    return c - lcdo_log((uint64_t)k);"),
+    "tie_larger_id_first": ("(a->r == b->r && a->u < b->u)", "(a->r == b->r && a->u > b->u)"),
+    "criterion_sign": ("double t = a - c;", "double t = a + c;"),
+    "no_requeue_after_reject": ("        if (!g->in_c[v])\n            lcdo_queue(g, v, alpha);",
+                                "        if (!g->in_c[v] && g->queued[v])\n            lcdo_queue(g, v, alpha);"),
+    "prune_descending": ("return (x > y) - (x < y);", "return (x < y) - (x > y);"),
+    "no_prune": ("    if (added) {\n        for (uint32_t pass", "    if (0 && added) {\n        for (uint32_t pass"),
+    "volume_misses_new_node": ("g->V += g->k[u];\n    g->size += 1;\n    g->M += 1;",
+                               "g->size += 1;\n    g->M += 1;"),
+    "margin_dropped": ("return t > 0x1p-40;", "return t >= 0.0;"),
+    "rank_uses_d_out": ("lcdo_push(g, lcdo_rank(g->d[u], g->k[u], alpha), u, g->ver[u]);",
+                        "lcdo_push(g, lcdo_rank(g->d[u], g->k[u] - g->d[u] + 1, alpha), u, g->ver[u]);"),
+}
+
+PINS = ["tests/test_oracle_bruteforce.py", "tests/test_oracle_replay.py",
+        "tests/test_oracle_limits.py", "tests/test_oracle_audit.py"]
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(tmp_path, name):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    mut = tmp_path / "mutant.c"
+    mut.write_text(src.replace(old, new))
+    so = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
+                    str(mut), "-o", str(so), "-lm"], check=True)
+    env = dict(os.environ, LCDO_LIB=str(so))
+    # a mutant that makes the growth loop run away is caught by the per-test
+    # time limit (the thread method also stops a hang inside the C code)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        "--timeout", "20", "--timeout-method", "thread", *PINS],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
+    assert r.returncode != 0, "mutant %s survived the pins:\n%s" % (name, r.stdout[-2000:])
