@@ -1,0 +1,197 @@
+/*
+ * lcd.h — C ABI of the MI355X multi-scale local community sweep.
+ *
+ * The library grows communities under the LFK fitness
+ *     f_c = k_in / (k_in + k_out)^alpha                (paper Sec. 2, Eq. 1)
+ * by the growth function of Algorithm 1 (priority-queue additions ranked by
+ * 2 d_in / (d_in + d_out)^alpha, then removal passes), repeated until
+ * nothing changes at one scale and chained from each scale to the next
+ * coarser one (Sec. 2 and the growth half of Algorithm 2).  Seed sets are
+ * independent communities; the overlap-merge phase of Algorithm 2 is not
+ * part of this library.
+ *
+ * Exact semantics (shared with the test oracle, written independently):
+ *   - k_in counts internal edges from both ends: adding node n raises it by
+ *     2 d_in(n); k_in + k_out is the volume V (sum of member degrees).
+ *     Weights are integers 1..255 (or all 1), so every term is an exact
+ *     integer.
+ *   - "n improves f_c" is  t = (L(K')-L(K)) - alpha (L(V')-L(V)) > 2^-40
+ *     in IEEE double, where L is the integer natural log given in the
+ *     design notes; K' = 0 never improves, K = 0 < K' always does.
+ *   - queue rank R = L(2 d_in) - alpha L(k); equal ranks pop the smaller id;
+ *     a node that was popped and rejected returns to the queue only when a
+ *     later addition changes its d_in.
+ *   - removal passes visit the members present at the start of the pass in
+ *     ascending id; at most k_prune passes (0 = until nothing is removed);
+ *     no pass when the call added nothing.
+ *
+ * Conventions for every call:
+ *   - Every function returns an lcd_status; nothing aborts or throws across
+ *     the ABI.  lcd_last_error() gives a thread-local message for the last
+ *     non-OK status of the calling thread.
+ *   - Input arrays stay owned by the caller and are copied before the call
+ *     returns; the library never keeps a caller pointer.
+ *   - mem_kind says where caller arrays live: LCD_MEM_HOST (pageable or
+ *     pinned host memory) or LCD_MEM_DEVICE (device memory of the current
+ *     HIP device).
+ *   - stream is a hipStream_t (NULL = the null stream).  Work is queued on
+ *     it; calls documented as blocking synchronise that stream before they
+ *     return.
+ *   - Handles are owned by the library and freed by their *_free call.
+ */
+#ifndef LCD_H
+#define LCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LCD_OK = 0,
+    LCD_EINVAL = 1,     /* an argument breaks its documented contract */
+    LCD_ENOMEM = 2,     /* device or host allocation failed */
+    LCD_EDEVICE = 3,    /* a HIP call failed or a kernel reported an error */
+    LCD_EAGAIN = 4,     /* result not ready yet (server poll) */
+    LCD_ECAPACITY = 5,  /* a caller buffer or a fixed capacity is too small */
+    LCD_ESTATE = 6      /* the handle is not in a state that allows the call */
+} lcd_status;
+
+enum { LCD_MEM_HOST = 0, LCD_MEM_DEVICE = 1 };
+
+/* lcd_params.mode */
+enum {
+    LCD_PERSISTENT = 0,     /* all scales and seed sets in one persistent launch */
+    LCD_PER_SCALE_LOOP = 1  /* one launch per scale, state re-read from memory */
+};
+
+typedef struct lcd_graph lcd_graph;
+typedef struct lcd_result lcd_result;
+
+typedef struct {
+    uint32_t k_prune;        /* removal passes per growth call; 0 = unbounded */
+    int32_t mode;            /* LCD_PERSISTENT or LCD_PER_SCALE_LOOP */
+    int32_t lds_capacity;    /* table entries per community held in LDS; 0 = default */
+    int32_t waves_per_block; /* communities (one wave each) per workgroup; 0 = default */
+    int32_t blocks_per_cu;   /* resident workgroups per compute unit; 0 = default */
+    int32_t use_graph;       /* 1: capture the launch sequence in a hipGraph and replay it */
+    int64_t pool_hint;       /* initial member-pool size in entries; 0 = estimate */
+} lcd_params;
+
+/* Timing and bookkeeping of one sweep (filled by lcd_result_stats). */
+typedef struct {
+    double ms_total;          /* device time of the whole sweep (hipEvents on the caller's stream) */
+    double ms_main;           /* device time of the LDS-resident sweep kernel(s) */
+    double ms_spill;          /* device time of the global-memory tiers */
+    int64_t n_spilled;        /* seed sets finished by a global-memory tier */
+    int64_t n_spilled_big;    /* ... of which by the largest tier */
+    int64_t pool_used;        /* member-pool entries written */
+    int32_t reruns;           /* relaunches after the member pool had to grow */
+    int32_t lds_capacity;     /* table entries per community in LDS actually used */
+    int32_t waves_per_block;
+    int32_t grid_blocks;      /* workgroups of the LDS-resident launch */
+    int32_t launches;         /* kernel launches of the sweep (excluding readout) */
+    int32_t pad;
+} lcd_sweep_stats;
+
+/* Fill *p with the defaults (k_prune 0, persistent mode, autotuned sizes). */
+void lcd_params_default(lcd_params *p);
+
+/*
+ * Upload an undirected graph in symmetric CSR form and keep it resident.
+ *   n        nodes, 0 <= n < 2^31
+ *   nnz      directed entries (twice the undirected edges), < 2^31
+ *   row_ptr  int32[n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz
+ *   col      int32[nnz], each row strictly ascending, ids in [0, n), no
+ *            self-loops; symmetric (v in row u <=> u in row v)
+ *   w        uint8[nnz] weights >= 1, equal on both directions, or NULL for
+ *            all weights 1
+ * Validation (host side, before any device work) returns LCD_EINVAL when
+ * any rule above is broken, or the weighted degree exceeds 2^27.
+ * Blocking.  Derived data built on the device: weighted degrees and the
+ * table L(x) for x <= 2 * max weighted degree.
+ */
+lcd_status lcd_graph_upload(int32_t n, int64_t nnz, const int32_t *row_ptr,
+                            const int32_t *col, const uint8_t *w, int32_t mem_kind,
+                            void *stream, lcd_graph **out);
+
+/* n, nnz, max weighted degree and total volume (sum of weighted degrees). */
+lcd_status lcd_graph_info(const lcd_graph *g, int32_t *n, int64_t *nnz,
+                          int64_t *max_degree, int64_t *volume);
+
+lcd_status lcd_graph_free(lcd_graph *g);
+
+/*
+ * Grow every seed set through every scale.
+ *   scales      double[n_scales], finite, >= 0, <= 1000, strictly decreasing
+ *               (finest first: large alpha = small communities)
+ *   seed_ptr    int32[n_sets+1] offsets into seed_nodes; set j is
+ *               seed_nodes[seed_ptr[j] .. seed_ptr[j+1]) (non-empty, ids in
+ *               range, no repeats inside a set).  n_sets may be 0.
+ *   params      NULL for defaults
+ * The result holds, for each record r = j * n_scales + s: the sorted member
+ * list, K = k_in, V = k_in + k_out, f = K / pow(V, alpha_s) and the work
+ * counters (criterion evaluations G, rank updates R, moves M, growth calls C).
+ * Blocking: returns after the sweep has finished on the stream.
+ */
+lcd_status lcd_sweep(const lcd_graph *g, const double *scales, int32_t n_scales,
+                     const int32_t *seed_ptr, const int32_t *seed_nodes, int32_t n_sets,
+                     int32_t mem_kind, const lcd_params *params, void *stream,
+                     lcd_result **out);
+
+/* Sweep shape and the total number of members listed at one scale. */
+lcd_status lcd_result_shape(const lcd_result *r, int32_t *n_sets, int32_t *n_scales);
+lcd_status lcd_result_sizes(const lcd_result *r, int32_t scale_idx, int64_t *total_members);
+
+/*
+ * Communities at one scale, in caller buffers (all in mem_kind memory):
+ *   comm_ptr int32[n_sets+1]    offsets into members
+ *   members  int32[total]       each community ascending
+ *   k_in, vol int64[n_sets], f double[n_sets]   (each may be NULL)
+ * Blocking.
+ */
+lcd_status lcd_result_membership(const lcd_result *r, int32_t scale_idx, int32_t *comm_ptr,
+                                 int32_t *members, int64_t *k_in, int64_t *vol, double *f,
+                                 int32_t mem_kind, void *stream);
+
+/*
+ * Overlap at one scale: for every node, the seed sets whose community holds
+ * it (the paper's per-node membership sets).
+ *   node_ptr  int32[n+1], node_sets int32[total members], ascending per node.
+ * Blocking.
+ */
+lcd_status lcd_result_overlap(const lcd_result *r, int32_t scale_idx, int32_t *node_ptr,
+                              int32_t *node_sets, int32_t mem_kind, void *stream);
+
+/*
+ * Work counters: totals[4] = sums of G, R, M, C over all records (host
+ * memory); per_record (n_sets * n_scales * 4, in mem_kind memory) may be NULL.
+ * Blocking.
+ */
+lcd_status lcd_result_counters(const lcd_result *r, uint64_t *totals, uint64_t *per_record,
+                               int32_t mem_kind, void *stream);
+
+lcd_status lcd_result_stats(const lcd_result *r, lcd_sweep_stats *out);
+lcd_status lcd_result_free(lcd_result *r);
+
+/*
+ * The library's integer logarithm L(x) evaluated on the device, for
+ * x in [1, 2^53): x and out are device arrays of n entries.  Blocking.
+ * Exposed so the decision arithmetic can be checked bit for bit.
+ */
+lcd_status lcd_log_device(const uint64_t *x, double *out, int64_t n, void *stream);
+
+/* Device properties used for launch sizing: compute units and LDS per CU. */
+lcd_status lcd_device_info(int32_t *compute_units, int64_t *lds_per_cu,
+                           int64_t *lds_per_block, char *arch, int32_t arch_len);
+
+const char *lcd_last_error(void);
+const char *lcd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LCD_H */

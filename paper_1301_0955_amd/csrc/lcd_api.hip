@@ -1,0 +1,886 @@
+// Host side of the C ABI declared in include/lcd.h: validation, device
+// memory, launch sizing, the launch sequence of a sweep and the readout.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lcd.h"
+#include "lcd_internal.h"
+
+using namespace lcd;
+
+namespace {
+
+thread_local std::string t_err;
+
+lcd_status fail(lcd_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(LCD_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+template <typename T>
+lcd_status dev_alloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0)
+        count = 1;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(LCD_ENOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T),
+                    hipGetErrorString(e));
+    }
+    return LCD_OK;
+}
+
+template <typename T>
+void dev_free(T *&p) {
+    if (p)
+        (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+#define CHK(expr)                      \
+    do {                               \
+        lcd_status s_ = (expr);        \
+        if (s_ != LCD_OK)              \
+            return s_;                 \
+    } while (0)
+
+// Copy n elements from caller memory (host or device) to host vector.
+template <typename T>
+lcd_status fetch(std::vector<T> &dst, const T *src, size_t n, int32_t mem_kind, hipStream_t st) {
+    dst.resize(n);
+    if (n == 0)
+        return LCD_OK;
+    if (!src)
+        return fail(LCD_EINVAL, "null input array");
+    if (mem_kind == LCD_MEM_DEVICE) {
+        HIPCHK(hipMemcpyAsync(dst.data(), src, n * sizeof(T), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    } else {
+        std::memcpy(dst.data(), src, n * sizeof(T));
+    }
+    return LCD_OK;
+}
+
+int next_pow2_bits(int64_t x) {
+    int b = 0;
+    while (((int64_t)1 << b) < x)
+        ++b;
+    return b;
+}
+
+struct DevInfo {
+    int device = -1;
+    int cus = 0;
+    int64_t lds_cu = 0;
+    int64_t lds_block = 0;
+    char arch[64] = {0};
+};
+
+lcd_status device_info(DevInfo &d) {
+    HIPCHK(hipGetDevice(&d.device));
+    int v = 0;
+    HIPCHK(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, d.device));
+    d.cus = v;
+    HIPCHK(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, d.device));
+    d.lds_cu = v;
+    HIPCHK(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, d.device));
+    d.lds_block = v;
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, d.device));
+    std::snprintf(d.arch, sizeof(d.arch), "%s", prop.gcnArchName);
+    if (d.lds_cu <= 0)
+        d.lds_cu = 65536;
+    if (d.lds_block <= 0)
+        d.lds_block = 65536;
+    return LCD_OK;
+}
+
+// Global-memory table workspace of one spill tier.
+struct Slab {
+    char *buf = nullptr;
+    int64_t stride = 0;
+    int32_t cap = 0;
+    int32_t hbits = 0;
+    int32_t slots = 0;
+    bool dirty = false;
+};
+
+}  // namespace
+
+struct lcd_graph {
+    int32_t n = 0;
+    int64_t nnz = 0;
+    int64_t maxk = 0;
+    int64_t volume = 0;
+    int device = -1;
+    int32_t *row_ptr = nullptr;
+    int32_t *col = nullptr;
+    uint8_t *w = nullptr;
+    int32_t *kdeg = nullptr;
+    double *logtab = nullptr;
+    int32_t logtab_n = 0;
+    DevInfo dev;
+    Slab slab[2];
+    int64_t pool_hint = 0;
+};
+
+struct lcd_result {
+    const lcd_graph *g = nullptr;
+    int32_t n_sets = 0;
+    int32_t S = 0;
+    lcd_params prm;
+    double *scales = nullptr;
+    int32_t *seed_ptr = nullptr;
+    int32_t *seed_nodes = nullptr;
+    int64_t n_seed_nodes = 0;
+    Records rec{};
+    int32_t *pool = nullptr;
+    int64_t pool_cap = 0;
+    Counters *ctl = nullptr;          // one per launch group
+    int32_t n_ctl = 0;
+    unsigned long long *cursor = nullptr;
+    uint32_t *err = nullptr;
+    int32_t *work[2] = {nullptr, nullptr};
+    std::vector<double> scales_h;
+    lcd_sweep_stats stats{};
+};
+
+namespace {
+
+struct TierPlan {
+    int32_t cap0, hbits0, wpb0, blocks0;
+    bool use1, use2;
+};
+
+lcd_status ensure_slab(lcd_graph *g, int which, int32_t cap, int32_t slots, hipStream_t st) {
+    Slab &sl = g->slab[which];
+    const int32_t hbits = next_pow2_bits(2 * (int64_t)cap);
+    const int64_t stride = (table_bytes(cap, hbits) + 255) / 256 * 256;
+    if (sl.buf && sl.cap == cap && sl.slots == slots && !sl.dirty)
+        return LCD_OK;
+    if (!(sl.buf && sl.cap == cap && sl.slots == slots)) {
+        dev_free(sl.buf);
+        CHK(dev_alloc(&sl.buf, (size_t)(stride * slots)));
+    }
+    sl.stride = stride;
+    sl.cap = cap;
+    sl.hbits = hbits;
+    sl.slots = slots;
+    // all-ones bytes: every hash slot empty (-1); other arrays need no init
+    HIPCHK(launch_fill_i32((int32_t *)sl.buf, -1, stride * slots / 4, st));
+    sl.dirty = false;
+    return LCD_OK;
+}
+
+lcd_status plan_tiers(lcd_graph *g, const lcd_params &p, TierPlan &tp, hipStream_t st) {
+    int32_t cap = p.lds_capacity > 0 ? p.lds_capacity : 1024;
+    if (cap % 64 != 0 || cap < 64 || cap > 8192)
+        return fail(LCD_EINVAL, "lds_capacity must be a multiple of 64 in [64, 8192]");
+    tp.cap0 = cap;
+    tp.hbits0 = next_pow2_bits(2 * (int64_t)cap);
+    const int64_t tb = table_bytes(cap, tp.hbits0);
+    int32_t wpb = p.waves_per_block > 0 ? p.waves_per_block
+                                        : (int32_t)std::max<int64_t>(1, std::min<int64_t>(4, g->dev.lds_block / tb));
+    if (wpb > 4)
+        return fail(LCD_EINVAL, "waves_per_block must be at most 4");
+    if (wpb * tb > g->dev.lds_block)
+        return fail(LCD_EINVAL, "LDS table of %lld bytes x %d waves exceeds %lld bytes per block",
+                    (long long)tb, wpb, (long long)g->dev.lds_block);
+    int32_t bpc = p.blocks_per_cu > 0 ? p.blocks_per_cu
+                                      : (int32_t)std::max<int64_t>(1, g->dev.lds_cu / (wpb * tb));
+    bpc = std::min(bpc, 32);
+    tp.wpb0 = wpb;
+    tp.blocks0 = g->dev.cus * bpc;
+    // spill tiers: a 16k-entry tier with many tables, then one that holds
+    // every node of the graph
+    const int64_t need = std::max<int64_t>(64, g->n);
+    const int32_t cap1 = (int32_t)std::min<int64_t>(16384, ((int64_t)1 << next_pow2_bits(need)));
+    const int32_t cap2 = (int32_t)((int64_t)1 << next_pow2_bits(need));
+    tp.use1 = cap1 > cap && g->n > cap;
+    tp.use2 = cap2 > std::max(cap, cap1) && g->n > cap1;
+    if (tp.use1)
+        CHK(ensure_slab(g, 0, cap1, 1024, st));
+    if (tp.use2) {
+        const int64_t tb2 = table_bytes(cap2, next_pow2_bits(2 * (int64_t)cap2));
+        int64_t slots = ((int64_t)4 << 30) / tb2;
+        slots = std::max<int64_t>(4, std::min<int64_t>(256, slots));
+        CHK(ensure_slab(g, 1, cap2, (int32_t)slots, st));
+    }
+    return LCD_OK;
+}
+
+lcd_status run_group(lcd_result *r, const TierPlan &tp, int32_t s_begin, int32_t s_end, int32_t gi,
+                     hipStream_t st, hipEvent_t *ev) {
+    lcd_graph *g = const_cast<lcd_graph *>(r->g);
+    SweepArgs a{};
+    a.g.row_ptr = g->row_ptr;
+    a.g.col = g->col;
+    a.g.w = g->w;
+    a.g.kdeg = g->kdeg;
+    a.g.logtab = g->logtab;
+    a.g.n = g->n;
+    a.g.logtab_n = g->logtab_n;
+    a.scales = r->scales;
+    a.S = r->S;
+    a.s_begin = s_begin;
+    a.s_end = s_end;
+    a.seed_ptr = r->seed_ptr;
+    a.seed_nodes = r->seed_nodes;
+    a.n_sets = r->n_sets;
+    a.k_prune = r->prm.k_prune;
+    a.resume = s_begin > 0 ? 1 : 0;
+    a.rec = r->rec;
+    a.pool = r->pool;
+    a.pool_cap = r->pool_cap;
+    a.ctl = r->ctl + gi;
+    a.pool_cursor = r->cursor;
+    a.err = r->err;
+
+    if (ev)
+        HIPCHK(hipEventRecord(ev[0], st));
+    a.tier = 0;
+    a.work_in = nullptr;
+    a.work_out = tp.use1 ? r->work[0] : (tp.use2 ? r->work[1] : nullptr);
+    a.cap = tp.cap0;
+    a.hbits = tp.hbits0;
+    a.gtab = nullptr;
+    a.gtab_stride = 0;
+    a.n_slots = 0;
+    HIPCHK(launch_sweep(a, tp.blocks0, tp.wpb0, st));
+    r->stats.launches += 1;
+    if (ev)
+        HIPCHK(hipEventRecord(ev[1], st));
+    // spill tiers read their item count from the previous tier's counter
+    int prev = 0;
+    for (int k = 0; k < 2; ++k) {
+        const bool use = k == 0 ? tp.use1 : tp.use2;
+        if (!use)
+            continue;
+        Slab &sl = g->slab[k];
+        SweepArgs b = a;
+        b.tier = k + 1;
+        // ovf_count index = tier that pushed the items
+        b.work_in = r->work[k];
+        if (k == 1 && !tp.use1) {
+            b.work_in = r->work[1];
+        }
+        b.work_out = (k == 0 && tp.use2) ? r->work[1] : nullptr;
+        b.cap = sl.cap;
+        b.hbits = sl.hbits;
+        b.gtab = sl.buf;
+        b.gtab_stride = sl.stride;
+        b.n_slots = sl.slots;
+        // when tier 1 is skipped, tier 2 reads tier 0's pushes: shift the tier
+        // index so ovf_count[tier-1] is the right counter
+        if (k == 1 && !tp.use1)
+            b.tier = 1;
+        (void)prev;
+        HIPCHK(launch_sweep(b, (sl.slots + 3) / 4, 4, st));
+        r->stats.launches += 1;
+        sl.dirty = false;
+    }
+    if (ev)
+        HIPCHK(hipEventRecord(ev[2], st));
+    return LCD_OK;
+}
+
+lcd_status run_sweep(lcd_result *r, hipStream_t st) {
+    lcd_graph *g = const_cast<lcd_graph *>(r->g);
+    TierPlan tp;
+    CHK(plan_tiers(g, r->prm, tp, st));
+    r->stats = lcd_sweep_stats{};
+    r->stats.lds_capacity = tp.cap0;
+    r->stats.waves_per_block = tp.wpb0;
+    r->stats.grid_blocks = tp.blocks0;
+    hipEvent_t ev[4];
+    for (auto &e : ev)
+        HIPCHK(hipEventCreate(&e));
+    lcd_status status = LCD_OK;
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        r->stats.launches = 0;
+        // zero the work queues, the pool cursor and the error word
+        HIPCHK(launch_zero_bytes(r->ctl, (int64_t)sizeof(Counters) * r->n_ctl, st));
+        HIPCHK(launch_zero_bytes(r->cursor, 16, st));
+        HIPCHK(hipEventRecord(ev[3], st));
+        float ms_main = 0.f, ms_spill = 0.f;
+        if (r->n_sets > 0) {
+            if (r->prm.mode == LCD_PER_SCALE_LOOP) {
+                for (int32_t s = 0; s < r->S; ++s) {
+                    CHK(run_group(r, tp, s, s + 1, s, st, nullptr));
+                }
+                HIPCHK(hipEventRecord(ev[2], st));
+            } else {
+                CHK(run_group(r, tp, 0, r->S, 0, st, ev));
+            }
+        } else {
+            HIPCHK(hipEventRecord(ev[2], st));
+        }
+        HIPCHK(hipEventSynchronize(ev[2]));
+        unsigned long long cur[2] = {0, 0};
+        HIPCHK(hipMemcpy(cur, r->cursor, 16, hipMemcpyDeviceToHost));
+        std::vector<Counters> ctl(r->n_ctl);
+        HIPCHK(hipMemcpy(ctl.data(), r->ctl, sizeof(Counters) * r->n_ctl, hipMemcpyDeviceToHost));
+        float ms_total = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms_total, ev[3], ev[2]));
+        if (r->n_sets > 0 && r->prm.mode != LCD_PER_SCALE_LOOP) {
+            HIPCHK(hipEventElapsedTime(&ms_main, ev[0], ev[1]));
+            HIPCHK(hipEventElapsedTime(&ms_spill, ev[1], ev[2]));
+        }
+        const uint32_t err = (uint32_t)(cur[1] & 0xffffffffu);
+        if (err) {
+            g->slab[0].dirty = g->slab[1].dirty = true;
+            status = fail(err & ERR_CAPACITY ? LCD_ECAPACITY : LCD_EDEVICE,
+                          "sweep kernel reported error bits 0x%x", err);
+            break;
+        }
+        r->stats.ms_total = ms_total;
+        r->stats.ms_main = ms_main;
+        r->stats.ms_spill = ms_spill;
+        int64_t sp = 0, spb = 0;
+        for (auto &c : ctl) {
+            sp += c.ovf_count[0];
+            spb += tp.use1 && tp.use2 ? c.ovf_count[1] : 0;
+        }
+        r->stats.n_spilled = sp;
+        r->stats.n_spilled_big = spb;
+        r->stats.pool_used = (int64_t)cur[0];
+        if ((int64_t)cur[0] <= r->pool_cap)
+            break;
+        // the pool was too small: grow it and run again
+        r->stats.reruns += 1;
+        int64_t want = std::max<int64_t>((int64_t)cur[0] + (int64_t)cur[0] / 8 + 1024, 2 * r->pool_cap);
+        dev_free(r->pool);
+        r->pool_cap = 0;
+        CHK(dev_alloc(&r->pool, (size_t)want));
+        r->pool_cap = want;
+        if (attempt == 7)
+            status = fail(LCD_ECAPACITY, "member pool did not converge");
+    }
+    for (auto &e : ev)
+        (void)hipEventDestroy(e);
+    if (status == LCD_OK)
+        g->pool_hint = std::max(g->pool_hint, r->stats.pool_used);
+    return status;
+}
+
+void result_release(lcd_result *r) {
+    if (!r)
+        return;
+    dev_free(r->scales);
+    dev_free(r->seed_ptr);
+    dev_free(r->seed_nodes);
+    dev_free(r->rec.off);
+    dev_free(r->rec.cnt);
+    dev_free(r->rec.K);
+    dev_free(r->rec.V);
+    dev_free(r->rec.f);
+    dev_free(r->rec.ctr);
+    dev_free(r->pool);
+    dev_free(r->ctl);
+    dev_free(r->cursor);
+    dev_free(r->work[0]);
+    dev_free(r->work[1]);
+    delete r;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lcd_params_default(lcd_params *p) {
+    if (!p)
+        return;
+    std::memset(p, 0, sizeof(*p));
+    p->mode = LCD_PERSISTENT;
+}
+
+const char *lcd_last_error(void) { return t_err.c_str(); }
+
+const char *lcd_version(void) { return "lcd-mi355x 0.1 (gfx950)"; }
+
+lcd_status lcd_device_info(int32_t *compute_units, int64_t *lds_per_cu, int64_t *lds_per_block,
+                           char *arch, int32_t arch_len) {
+    DevInfo d;
+    CHK(device_info(d));
+    if (compute_units)
+        *compute_units = d.cus;
+    if (lds_per_cu)
+        *lds_per_cu = d.lds_cu;
+    if (lds_per_block)
+        *lds_per_block = d.lds_block;
+    if (arch && arch_len > 0)
+        std::snprintf(arch, (size_t)arch_len, "%s", d.arch);
+    return LCD_OK;
+}
+
+lcd_status lcd_graph_upload(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col,
+                            const uint8_t *w, int32_t mem_kind, void *stream, lcd_graph **out) {
+    if (!out)
+        return fail(LCD_EINVAL, "out is null");
+    *out = nullptr;
+    if (n < 0 || nnz < 0 || nnz >= ((int64_t)1 << 31))
+        return fail(LCD_EINVAL, "n and nnz must be in [0, 2^31)");
+    if (mem_kind != LCD_MEM_HOST && mem_kind != LCD_MEM_DEVICE)
+        return fail(LCD_EINVAL, "unknown mem_kind %d", mem_kind);
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int32_t> rp, cl;
+    std::vector<uint8_t> ww;
+    CHK(fetch(rp, row_ptr, (size_t)n + 1, mem_kind, st));
+    CHK(fetch(cl, col, (size_t)nnz, mem_kind, st));
+    if (w)
+        CHK(fetch(ww, w, (size_t)nnz, mem_kind, st));
+    // --- validation ---
+    if (rp[0] != 0 || rp[n] != nnz)
+        return fail(LCD_EINVAL, "row_ptr must start at 0 and end at nnz");
+    int64_t maxk = 0, vol = 0;
+    for (int32_t u = 0; u < n; ++u) {
+        const int32_t b = rp[u], e = rp[u + 1];
+        if (e < b)
+            return fail(LCD_EINVAL, "row_ptr decreases at node %d", u);
+        int64_t k = 0;
+        for (int32_t j = b; j < e; ++j) {
+            const int32_t v = cl[j];
+            if (v < 0 || v >= n)
+                return fail(LCD_EINVAL, "neighbour id %d of node %d out of range", v, u);
+            if (v == u)
+                return fail(LCD_EINVAL, "self-loop at node %d", u);
+            if (j > b && cl[j - 1] >= v)
+                return fail(LCD_EINVAL, "row %d is not strictly ascending", u);
+            const int wt = w ? (int)ww[j] : 1;
+            if (wt < 1)
+                return fail(LCD_EINVAL, "zero weight on edge %d-%d", u, v);
+            // symmetry: u must appear in row v with the same weight
+            const int32_t *rb = cl.data() + rp[v];
+            const int32_t *re = cl.data() + rp[v + 1];
+            const int32_t *it = std::lower_bound(rb, re, u);
+            if (it == re || *it != u)
+                return fail(LCD_EINVAL, "edge %d-%d has no reverse entry", u, v);
+            if (w && ww[it - cl.data()] != ww[j])
+                return fail(LCD_EINVAL, "edge %d-%d has unequal weights", u, v);
+            k += wt;
+        }
+        maxk = std::max(maxk, k);
+        vol += k;
+    }
+    if (maxk >= ((int64_t)1 << 27))
+        return fail(LCD_EINVAL, "weighted degree %lld exceeds 2^27", (long long)maxk);
+    // --- device copies ---
+    lcd_graph *g = new (std::nothrow) lcd_graph();
+    if (!g)
+        return fail(LCD_ENOMEM, "host allocation failed");
+    auto bail = [&](lcd_status s) {
+        dev_free(g->row_ptr);
+        dev_free(g->col);
+        dev_free(g->w);
+        dev_free(g->kdeg);
+        dev_free(g->logtab);
+        delete g;
+        return s;
+    };
+    lcd_status s;
+    if ((s = device_info(g->dev)) != LCD_OK)
+        return bail(s);
+    g->n = n;
+    g->nnz = nnz;
+    g->maxk = maxk;
+    g->volume = vol;
+    g->device = g->dev.device;
+    g->logtab_n = (int32_t)(2 * maxk + 2);
+    if ((s = dev_alloc(&g->row_ptr, (size_t)n + 1)) != LCD_OK ||
+        (s = dev_alloc(&g->col, (size_t)nnz)) != LCD_OK ||
+        (s = dev_alloc(&g->kdeg, (size_t)std::max(n, 1))) != LCD_OK ||
+        (s = dev_alloc(&g->logtab, (size_t)g->logtab_n)) != LCD_OK)
+        return bail(s);
+    if (w && (s = dev_alloc(&g->w, (size_t)nnz)) != LCD_OK)
+        return bail(s);
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->row_ptr, rp.data(), sizeof(int32_t) * ((size_t)n + 1),
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && nnz)
+        e = hipMemcpyAsync(g->col, cl.data(), sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && w && nnz)
+        e = hipMemcpyAsync(g->w, ww.data(), (size_t)nnz, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = launch_degrees(g->row_ptr, g->w, g->kdeg, n, st);
+    if (e == hipSuccess)
+        e = launch_logtab(g->logtab, g->logtab_n, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess)
+        return bail(fail(LCD_EDEVICE, "graph upload: %s", hipGetErrorString(e)));
+    *out = g;
+    return LCD_OK;
+}
+
+lcd_status lcd_graph_info(const lcd_graph *g, int32_t *n, int64_t *nnz, int64_t *max_degree,
+                          int64_t *volume) {
+    if (!g)
+        return fail(LCD_EINVAL, "null graph");
+    if (n)
+        *n = g->n;
+    if (nnz)
+        *nnz = g->nnz;
+    if (max_degree)
+        *max_degree = g->maxk;
+    if (volume)
+        *volume = g->volume;
+    return LCD_OK;
+}
+
+lcd_status lcd_graph_free(lcd_graph *g) {
+    if (!g)
+        return LCD_OK;
+    dev_free(g->row_ptr);
+    dev_free(g->col);
+    dev_free(g->w);
+    dev_free(g->kdeg);
+    dev_free(g->logtab);
+    dev_free(g->slab[0].buf);
+    dev_free(g->slab[1].buf);
+    delete g;
+    return LCD_OK;
+}
+
+lcd_status lcd_sweep(const lcd_graph *g, const double *scales, int32_t n_scales,
+                     const int32_t *seed_ptr, const int32_t *seed_nodes, int32_t n_sets,
+                     int32_t mem_kind, const lcd_params *params, void *stream, lcd_result **out) {
+    if (!out)
+        return fail(LCD_EINVAL, "out is null");
+    *out = nullptr;
+    if (!g)
+        return fail(LCD_EINVAL, "null graph");
+    if (n_scales < 1)
+        return fail(LCD_EINVAL, "n_scales must be >= 1");
+    if (n_sets < 0)
+        return fail(LCD_EINVAL, "n_sets must be >= 0");
+    if (mem_kind != LCD_MEM_HOST && mem_kind != LCD_MEM_DEVICE)
+        return fail(LCD_EINVAL, "unknown mem_kind %d", mem_kind);
+    if ((int64_t)n_sets * n_scales >= ((int64_t)1 << 40))
+        return fail(LCD_EINVAL, "too many records");
+    lcd_params prm;
+    lcd_params_default(&prm);
+    if (params)
+        prm = *params;
+    if (prm.mode != LCD_PERSISTENT && prm.mode != LCD_PER_SCALE_LOOP)
+        return fail(LCD_EINVAL, "unknown mode %d", prm.mode);
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<double> sc;
+    CHK(fetch(sc, scales, (size_t)n_scales, mem_kind, st));
+    for (int32_t s = 0; s < n_scales; ++s) {
+        if (!std::isfinite(sc[s]) || sc[s] < 0.0 || sc[s] > 1000.0)
+            return fail(LCD_EINVAL, "scale %d must be finite and in [0, 1000]", s);
+        if (s > 0 && !(sc[s] < sc[s - 1]))
+            return fail(LCD_EINVAL, "scales must be strictly decreasing (finest first)");
+    }
+    std::vector<int32_t> sp, sn;
+    CHK(fetch(sp, seed_ptr, (size_t)n_sets + 1, mem_kind, st));
+    if (sp[0] != 0)
+        return fail(LCD_EINVAL, "seed_ptr[0] must be 0");
+    for (int32_t j = 0; j < n_sets; ++j)
+        if (sp[j + 1] <= sp[j])
+            return fail(LCD_EINVAL, "seed set %d is empty or seed_ptr decreases", j);
+    const int64_t total = sp[n_sets];
+    CHK(fetch(sn, seed_nodes, (size_t)total, mem_kind, st));
+    {
+        std::vector<int32_t> stamp((size_t)std::max(g->n, 1), -1);
+        for (int32_t j = 0; j < n_sets; ++j)
+            for (int32_t q = sp[j]; q < sp[j + 1]; ++q) {
+                const int32_t u = sn[q];
+                if (u < 0 || u >= g->n)
+                    return fail(LCD_EINVAL, "seed node %d of set %d out of range", u, j);
+                if (stamp[u] == j)
+                    return fail(LCD_EINVAL, "seed node %d repeated in set %d", u, j);
+                stamp[u] = j;
+            }
+    }
+    lcd_result *r = new (std::nothrow) lcd_result();
+    if (!r)
+        return fail(LCD_ENOMEM, "host allocation failed");
+    r->g = g;
+    r->n_sets = n_sets;
+    r->S = n_scales;
+    r->prm = prm;
+    r->scales_h = sc;
+    r->n_seed_nodes = total;
+    const size_t R = (size_t)n_sets * (size_t)n_scales;
+    r->n_ctl = prm.mode == LCD_PER_SCALE_LOOP ? n_scales : 1;
+    int64_t est = std::max<int64_t>(1 << 16, (int64_t)n_sets * (n_scales / 4 + 2) * 32);
+    est = std::max(est, g->pool_hint + g->pool_hint / 16);
+    if (prm.pool_hint > 0)
+        est = prm.pool_hint;
+    lcd_status s = LCD_OK;
+    if ((s = dev_alloc(&r->scales, (size_t)n_scales)) != LCD_OK ||
+        (s = dev_alloc(&r->seed_ptr, (size_t)n_sets + 1)) != LCD_OK ||
+        (s = dev_alloc(&r->seed_nodes, (size_t)total)) != LCD_OK ||
+        (s = dev_alloc(&r->rec.off, R)) != LCD_OK || (s = dev_alloc(&r->rec.cnt, R)) != LCD_OK ||
+        (s = dev_alloc(&r->rec.K, R)) != LCD_OK || (s = dev_alloc(&r->rec.V, R)) != LCD_OK ||
+        (s = dev_alloc(&r->rec.f, R)) != LCD_OK || (s = dev_alloc(&r->rec.ctr, 4 * R)) != LCD_OK ||
+        (s = dev_alloc(&r->pool, (size_t)est)) != LCD_OK ||
+        (s = dev_alloc(&r->ctl, (size_t)r->n_ctl)) != LCD_OK ||
+        (s = dev_alloc(&r->cursor, 2)) != LCD_OK ||
+        (s = dev_alloc(&r->work[0], (size_t)std::max(n_sets, 1))) != LCD_OK ||
+        (s = dev_alloc(&r->work[1], (size_t)std::max(n_sets, 1))) != LCD_OK) {
+        result_release(r);
+        return s;
+    }
+    r->pool_cap = est;
+    r->err = (uint32_t *)(r->cursor + 1);
+    hipError_t e = hipMemcpyAsync(r->scales, sc.data(), sizeof(double) * n_scales,
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(r->seed_ptr, sp.data(), sizeof(int32_t) * ((size_t)n_sets + 1),
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && total)
+        e = hipMemcpyAsync(r->seed_nodes, sn.data(), sizeof(int32_t) * (size_t)total,
+                           hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) {
+        result_release(r);
+        return fail(LCD_EDEVICE, "input copy: %s", hipGetErrorString(e));
+    }
+    s = run_sweep(r, st);
+    if (s != LCD_OK) {
+        result_release(r);
+        return s;
+    }
+    *out = r;
+    return LCD_OK;
+}
+
+lcd_status lcd_result_shape(const lcd_result *r, int32_t *n_sets, int32_t *n_scales) {
+    if (!r)
+        return fail(LCD_EINVAL, "null result");
+    if (n_sets)
+        *n_sets = r->n_sets;
+    if (n_scales)
+        *n_scales = r->S;
+    return LCD_OK;
+}
+
+lcd_status lcd_result_sizes(const lcd_result *r, int32_t scale_idx, int64_t *total_members) {
+    if (!r || !total_members)
+        return fail(LCD_EINVAL, "null argument");
+    if (scale_idx < 0 || scale_idx >= r->S)
+        return fail(LCD_EINVAL, "scale index %d out of range", scale_idx);
+    int32_t *cp = nullptr;
+    CHK(dev_alloc(&cp, (size_t)r->n_sets + 1));
+    hipError_t e = launch_scale_scan(r->rec, r->S, scale_idx, r->n_sets, cp, nullptr);
+    int32_t tot = 0;
+    if (e == hipSuccess)
+        e = hipMemcpy(&tot, cp + r->n_sets, sizeof(int32_t), hipMemcpyDeviceToHost);
+    dev_free(cp);
+    if (e != hipSuccess)
+        return fail(LCD_EDEVICE, "sizes: %s", hipGetErrorString(e));
+    *total_members = tot;
+    return LCD_OK;
+}
+
+lcd_status lcd_result_membership(const lcd_result *r, int32_t scale_idx, int32_t *comm_ptr,
+                                 int32_t *members, int64_t *k_in, int64_t *vol, double *f,
+                                 int32_t mem_kind, void *stream) {
+    if (!r)
+        return fail(LCD_EINVAL, "null result");
+    if (scale_idx < 0 || scale_idx >= r->S)
+        return fail(LCD_EINVAL, "scale index %d out of range", scale_idx);
+    if (mem_kind != LCD_MEM_HOST && mem_kind != LCD_MEM_DEVICE)
+        return fail(LCD_EINVAL, "unknown mem_kind %d", mem_kind);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t ns = (size_t)r->n_sets;
+    const bool host = mem_kind == LCD_MEM_HOST;
+    int32_t *cp = comm_ptr;
+    int32_t *tmp_cp = nullptr, *tmp_m = nullptr;
+    int64_t *tmp_k = nullptr, *tmp_v = nullptr;
+    double *tmp_f = nullptr;
+    if (host || !comm_ptr) {
+        CHK(dev_alloc(&tmp_cp, ns + 1));
+        cp = tmp_cp;
+    }
+    HIPCHK(launch_scale_scan(r->rec, r->S, scale_idx, r->n_sets, cp, st));
+    int32_t tot = 0;
+    HIPCHK(hipMemcpyAsync(&tot, cp + ns, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int32_t *m = members;
+    int64_t *kk = k_in, *vv = vol;
+    double *ff = f;
+    lcd_status s = LCD_OK;
+    if (host) {
+        if (members && (s = dev_alloc(&tmp_m, (size_t)tot)) != LCD_OK)
+            goto done;
+        if (k_in && (s = dev_alloc(&tmp_k, ns)) != LCD_OK)
+            goto done;
+        if (vol && (s = dev_alloc(&tmp_v, ns)) != LCD_OK)
+            goto done;
+        if (f && (s = dev_alloc(&tmp_f, ns)) != LCD_OK)
+            goto done;
+        m = members ? tmp_m : nullptr;
+        kk = k_in ? tmp_k : nullptr;
+        vv = vol ? tmp_v : nullptr;
+        ff = f ? tmp_f : nullptr;
+    }
+    {
+        hipError_t e = launch_scale_gather(r->rec, r->pool, r->scales, r->S, scale_idx, r->n_sets, cp,
+                                           m, kk, vv, ff, st);
+        if (e == hipSuccess && host) {
+            if (comm_ptr)
+                e = hipMemcpyAsync(comm_ptr, cp, sizeof(int32_t) * (ns + 1), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess && members && tot)
+                e = hipMemcpyAsync(members, m, sizeof(int32_t) * (size_t)tot, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess && k_in && ns)
+                e = hipMemcpyAsync(k_in, kk, sizeof(int64_t) * ns, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess && vol && ns)
+                e = hipMemcpyAsync(vol, vv, sizeof(int64_t) * ns, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess && f && ns)
+                e = hipMemcpyAsync(f, ff, sizeof(double) * ns, hipMemcpyDeviceToHost, st);
+        }
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess)
+            s = fail(LCD_EDEVICE, "membership: %s", hipGetErrorString(e));
+    }
+done:
+    dev_free(tmp_cp);
+    dev_free(tmp_m);
+    dev_free(tmp_k);
+    dev_free(tmp_v);
+    dev_free(tmp_f);
+    return s;
+}
+
+lcd_status lcd_result_overlap(const lcd_result *r, int32_t scale_idx, int32_t *node_ptr,
+                              int32_t *node_sets, int32_t mem_kind, void *stream) {
+    if (!r)
+        return fail(LCD_EINVAL, "null result");
+    if (scale_idx < 0 || scale_idx >= r->S)
+        return fail(LCD_EINVAL, "scale index %d out of range", scale_idx);
+    if (mem_kind != LCD_MEM_HOST && mem_kind != LCD_MEM_DEVICE)
+        return fail(LCD_EINVAL, "unknown mem_kind %d", mem_kind);
+    if (!node_ptr || !node_sets)
+        return fail(LCD_EINVAL, "null output");
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t n = r->g->n;
+    const size_t ns = (size_t)r->n_sets;
+    int32_t *cp = nullptr, *mem = nullptr, *cnt = nullptr, *bs = nullptr, *np = nullptr, *nsets = nullptr;
+    lcd_status s = LCD_OK;
+    int32_t tot = 0;
+    const int nb = (int)(((int64_t)n + 1 + 1023) / 1024);
+    hipError_t e;
+    if ((s = dev_alloc(&cp, ns + 1)) != LCD_OK)
+        goto done;
+    e = launch_scale_scan(r->rec, r->S, scale_idx, r->n_sets, cp, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&tot, cp + ns, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        s = fail(LCD_EDEVICE, "overlap: %s", hipGetErrorString(e));
+        goto done;
+    }
+    if ((s = dev_alloc(&mem, (size_t)tot)) != LCD_OK || (s = dev_alloc(&cnt, (size_t)n + 1)) != LCD_OK ||
+        (s = dev_alloc(&bs, (size_t)nb + 1)) != LCD_OK)
+        goto done;
+    np = node_ptr;
+    nsets = node_sets;
+    if (mem_kind == LCD_MEM_HOST) {
+        if ((s = dev_alloc(&np, (size_t)n + 1)) != LCD_OK || (s = dev_alloc(&nsets, (size_t)tot)) != LCD_OK)
+            goto done;
+    }
+    e = launch_scale_gather(r->rec, r->pool, r->scales, r->S, scale_idx, r->n_sets, cp, mem, nullptr,
+                            nullptr, nullptr, st);
+    if (e == hipSuccess)
+        e = launch_overlap(cp, mem, tot, r->n_sets, n, np, nsets, cnt, bs, st);
+    if (e == hipSuccess && mem_kind == LCD_MEM_HOST) {
+        e = hipMemcpyAsync(node_ptr, np, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && tot)
+            e = hipMemcpyAsync(node_sets, nsets, sizeof(int32_t) * (size_t)tot, hipMemcpyDeviceToHost, st);
+    }
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess)
+        s = fail(LCD_EDEVICE, "overlap: %s", hipGetErrorString(e));
+done:
+    dev_free(cp);
+    dev_free(mem);
+    dev_free(cnt);
+    dev_free(bs);
+    if (mem_kind == LCD_MEM_HOST) {
+        dev_free(np);
+        dev_free(nsets);
+    }
+    return s;
+}
+
+lcd_status lcd_result_counters(const lcd_result *r, uint64_t *totals, uint64_t *per_record,
+                               int32_t mem_kind, void *stream) {
+    if (!r)
+        return fail(LCD_EINVAL, "null result");
+    if (mem_kind != LCD_MEM_HOST && mem_kind != LCD_MEM_DEVICE)
+        return fail(LCD_EINVAL, "unknown mem_kind %d", mem_kind);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t R = (int64_t)r->n_sets * r->S;
+    if (totals) {
+        unsigned long long *tot = nullptr;
+        CHK(dev_alloc(&tot, 4));
+        hipError_t e = launch_zero_bytes(tot, 32, st);
+        if (e == hipSuccess)
+            e = launch_counter_sum(r->rec.ctr, R, tot, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(totals, tot, 32, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        dev_free(tot);
+        if (e != hipSuccess)
+            return fail(LCD_EDEVICE, "counters: %s", hipGetErrorString(e));
+    }
+    if (per_record && R) {
+        HIPCHK(hipMemcpyAsync(per_record, r->rec.ctr, sizeof(uint64_t) * 4 * (size_t)R,
+                              mem_kind == LCD_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                              st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    return LCD_OK;
+}
+
+lcd_status lcd_result_stats(const lcd_result *r, lcd_sweep_stats *out) {
+    if (!r || !out)
+        return fail(LCD_EINVAL, "null argument");
+    *out = r->stats;
+    return LCD_OK;
+}
+
+lcd_status lcd_result_free(lcd_result *r) {
+    result_release(r);
+    return LCD_OK;
+}
+
+lcd_status lcd_log_device(const uint64_t *x, double *out, int64_t n, void *stream) {
+    if (n < 0 || (n > 0 && (!x || !out)))
+        return fail(LCD_EINVAL, "bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(launch_log(x, out, n, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return LCD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+// Internal interface between the host API (lcd_api.hip) and the kernels
+// (lcd_kernels.hip).  Not installed; the public ABI is include/lcd.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lcd {
+
+// Graph resident in device memory.
+struct GraphDev {
+    const int32_t *row_ptr;   // [n+1]
+    const int32_t *col;       // [nnz]
+    const uint8_t *w;         // [nnz] or nullptr (all weights 1)
+    const int32_t *kdeg;      // [n] weighted degree
+    const double *logtab;     // [logtab_n] L(x) for x < logtab_n
+    int32_t n;
+    int32_t logtab_n;
+};
+
+// Per-record outputs; record r = set * S + s.
+struct Records {
+    int64_t *off;             // member-pool offset of the sorted member list
+    int32_t *cnt;             // number of members
+    int64_t *K;               // k_in
+    int64_t *V;               // k_in + k_out
+    double *f;                // K / pow(V, alpha)
+    uint64_t *ctr;            // G, R, M, C
+};
+
+// Error bits written by the kernels.
+enum : uint32_t {
+    ERR_PROBE = 1u,           // hash probe exceeded the table size
+    ERR_MISSING = 2u,         // a neighbour of a member was absent from the table
+    ERR_LIMIT = 4u,           // move or growth-call limit of one (set, scale) hit
+    ERR_CAPACITY = 8u         // the largest tier ran out of entries
+};
+
+// Work-queue state of one launch group (all tiers of one scale range),
+// zeroed before the group runs.
+struct Counters {
+    uint32_t work_next[4];    // per tier: next work item
+    uint32_t ovf_count[4];    // per tier: items pushed to the next tier
+};
+
+struct SweepArgs {
+    GraphDev g;
+    const double *scales;
+    int32_t S;                // records per set
+    int32_t s_begin, s_end;   // scale range of this launch
+    const int32_t *seed_ptr;
+    const int32_t *seed_nodes;
+    int32_t n_sets;
+    uint32_t k_prune;
+    int32_t resume;           // 1: start from the records of scale s_begin - 1
+    Records rec;
+    int32_t *pool;
+    int64_t pool_cap;
+    Counters *ctl;
+    unsigned long long *pool_cursor;   // entries claimed in the pool (may pass pool_cap)
+    uint32_t *err;                     // ERR_* bits
+    int32_t tier;             // 0 = LDS; 1.. = global-memory tiers
+    const int32_t *work_in;   // tier > 0: set ids pushed by the previous tier
+    int32_t *work_out;        // sets pushed to the next tier (nullptr for the last)
+    int32_t cap;              // table entries per community
+    int32_t hbits;            // hash slots = 2^hbits >= 2 * cap
+    char *gtab;               // global tiers: table workspace
+    int64_t gtab_stride;      // bytes per table
+    int32_t n_slots;          // global tiers: number of tables
+};
+
+// Bytes per table entry (dense arrays + scratch) and per hash slot.
+constexpr int kEntryBytes = 4 /*node*/ + 4 /*d|flags*/ + 4 /*k*/ + 8 /*rank*/ + 4 /*scratch*/;
+constexpr int kSlotBytes = 4;
+
+__host__ __device__ inline int64_t table_bytes(int32_t cap, int32_t hbits) {
+    return (int64_t)cap * kEntryBytes + ((int64_t)1 << hbits) * kSlotBytes;
+}
+
+hipError_t launch_degrees(const int32_t *row_ptr, const uint8_t *w, int32_t *kdeg, int32_t n,
+                          hipStream_t st);
+hipError_t launch_logtab(double *tab, int32_t m, hipStream_t st);
+hipError_t launch_log(const uint64_t *x, double *out, int64_t n, hipStream_t st);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
+hipError_t launch_zero_bytes(void *p, int64_t bytes, hipStream_t st);
+hipError_t launch_sweep(const SweepArgs &a, int32_t blocks, int32_t waves_per_block,
+                        hipStream_t st);
+// readout
+hipError_t launch_scale_scan(const Records &rec, int32_t S, int32_t s, int32_t n_sets,
+                             int32_t *comm_ptr, hipStream_t st);
+hipError_t launch_scale_gather(const Records &rec, const int32_t *pool, const double *scales,
+                               int32_t S, int32_t s, int32_t n_sets, const int32_t *comm_ptr,
+                               int32_t *members, int64_t *k_in, int64_t *vol, double *f,
+                               hipStream_t st);
+// node_ptr[n+1] and node_sets[total] from one scale's member lists; cnt has
+// n+1 entries of scratch, block_sums ceil((n+1)/1024)+1.
+hipError_t launch_overlap(const int32_t *comm_ptr, const int32_t *members, int64_t total,
+                          int32_t n_sets, int32_t n, int32_t *node_ptr, int32_t *node_sets,
+                          int32_t *cnt, int32_t *block_sums, hipStream_t st);
+hipError_t launch_counter_sum(const uint64_t *ctr, int64_t n_rec, unsigned long long *tot,
+                              hipStream_t st);
+
+}  // namespace lcd

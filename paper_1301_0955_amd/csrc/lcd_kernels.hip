@@ -1,0 +1,1073 @@
+// Kernels of the multi-scale local community sweep for gfx950 (CDNA4, wave64).
+//
+// One wavefront grows one community through every scale (paper Sec. 2,
+// Algorithm 1, chained over scales as in Algorithm 2).  Per community the
+// wave keeps a table of every node it has touched:
+//   open-addressing hash  node id -> dense index   (int32 slots, 2^hbits >= 2 cap)
+//   dense arrays          node id, d_in | flags, weighted degree k, rank R
+// held in LDS (tier 0) or, for communities that outgrow the LDS table, in a
+// per-wave slab of global memory (tiers 1 and 2, same code).
+//
+// The sequential priority queue of Algorithm 1 is emulated exactly:
+//   * every live (queued) entry is tested against the current (K, V); the
+//     highest-ranked improving entry e* is the one the queue would add next,
+//     and every live entry ranked above e* would have been popped and
+//     rejected against the same state first.  Those pops are applied lazily:
+//     the next pass drops a live entry ranked above the previous e* unless
+//     the addition of e* touched it (flag FRESH), which is exactly the
+//     queue's "update or add the neighbours of n".
+//   * the number of pops G is counted where entries enter the queue (every
+//     entry that enters is popped exactly once before the queue empties).
+//   * a removal pass visits members in ascending id: each step finds the
+//     smallest removable id above the cursor with a wave min-reduction.
+// Decisions use only exact integer sums and the integer log L below, in
+// the same IEEE operation order as the specification, so the result is
+// bit-identical to a sequential evaluation.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lcd_internal.h"
+
+namespace lcd {
+
+namespace {
+
+constexpr double kMargin = 0x1p-40;   // improvement threshold on the log-fitness gain
+constexpr double kFilter = 1e-9;      // certified pre-test margin (see improves_add)
+constexpr uint32_t kDMask = (1u << 28) - 1;
+constexpr uint32_t kMember = 1u << 31;
+constexpr uint32_t kLive = 1u << 30;
+constexpr uint32_t kFresh = 1u << 29;
+
+// ---------------------------------------------------------------------------
+// L(x): natural log of an integer 1 <= x < 2^53.  x = m 2^e with m in
+// (sqrt(2)/2, sqrt(2)]; ln m = 2 atanh(s), s = (m-1)/(m+1), by the series
+// 2 s (1 + z/3 + ... + z^11/23) with z = s^2; ln 2 as a Cody-Waite pair so
+// that e * ln2_hi is exact.  Plain IEEE operations, no contraction.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double ilog(uint64_t x) {
+    int e = 63 - __builtin_clzll(x);
+    double m = (double)x * __longlong_as_double((long long)(1023 - e) << 52);
+    if (m > 0x1.6a09e667f3bcdp+0) {
+        m = m * 0.5;
+        e = e + 1;
+    }
+    double s = (m - 1.0) / (m + 1.0);
+    double z = s * s;
+    double p = 1.0 / 23.0;
+    p = p * z + 1.0 / 21.0;
+    p = p * z + 1.0 / 19.0;
+    p = p * z + 1.0 / 17.0;
+    p = p * z + 1.0 / 15.0;
+    p = p * z + 1.0 / 13.0;
+    p = p * z + 1.0 / 11.0;
+    p = p * z + 1.0 / 9.0;
+    p = p * z + 1.0 / 7.0;
+    p = p * z + 1.0 / 5.0;
+    p = p * z + 1.0 / 3.0;
+    p = p * z + 1.0;
+    double h = s * p;
+    double lnm = h + h;
+    double de = (double)e;
+    return de * 6.93147180369123816490e-01 + (de * 1.90821492927058770002e-10 + lnm);
+}
+
+__device__ __forceinline__ uint64_t lanes_below(int lane) {
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Ordering point between table phases of one wave.  LDS operations of a
+// wave execute in order, so only the compiler must be fenced; global
+// tables additionally wait for outstanding memory operations.
+template <bool GLOBAL>
+__device__ __forceinline__ void wsync() {
+    if constexpr (GLOBAL)
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    else
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint32_t hash_of(int32_t u, int hbits) {
+    return ((uint32_t)u * 2654435761u) >> (32 - hbits);
+}
+
+// true when (r, u) pops before (pr, pu): higher rank, then smaller id
+__device__ __forceinline__ bool before(double r, int32_t u, double pr, int32_t pu) {
+    return r > pr || (r == pr && u < pu);
+}
+
+struct Tab {
+    double *rk;
+    int32_t *node;
+    uint32_t *dv;
+    int32_t *kv;
+    int32_t *scr;
+    int32_t *hs;
+    uint32_t hmask;
+    int hbits;
+    int cap;
+};
+
+__device__ __forceinline__ Tab carve(char *base, int cap, int hbits) {
+    Tab t;
+    t.rk = (double *)base;
+    t.node = (int32_t *)(base + (size_t)cap * 8);
+    t.dv = (uint32_t *)(base + (size_t)cap * 12);
+    t.kv = (int32_t *)(base + (size_t)cap * 16);
+    t.scr = (int32_t *)(base + (size_t)cap * 20);
+    t.hs = (int32_t *)(base + (size_t)cap * 24);
+    t.hbits = hbits;
+    t.hmask = (1u << hbits) - 1;
+    t.cap = cap;
+    return t;
+}
+
+template <bool GLOBAL>
+__device__ __forceinline__ int32_t hs_load(const int32_t *p) {
+    if constexpr (GLOBAL)
+        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        return *p;
+}
+
+template <bool GLOBAL>
+__device__ __forceinline__ void hs_store(int32_t *p, int32_t v) {
+    if constexpr (GLOBAL)
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        *p = v;
+}
+
+// Per-wave state.  Every field except the lane partial counters holds the
+// same value in all lanes.
+struct St {
+    int32_t count;     // dense entries in use
+    int32_t nmem;      // members
+    int64_t K, V;      // k_in and volume of the community
+    double LK, LV;     // L(K), L(V) when positive
+    double alpha;
+    double pr;         // rank and id of the entry added last in this call
+    int32_t pu;
+    uint32_t Gl, Rl;   // lane partial counts of pops and rank computations
+    uint64_t Gu;       // wave-uniform part of G (removal-pass visits)
+    uint64_t M;        // moves in this (set, scale)
+    bool ovf;          // the table ran out of entries
+    uint32_t err;
+    int64_t move_limit; // guard against a runaway loop in one (set, scale)
+};
+
+struct Ctx {
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const uint8_t *w;
+    const int32_t *kdeg;
+    const double *logtab;
+    int32_t logtab_last;   // largest valid index of logtab
+};
+
+// queue rank R(d, k) = L(2d) - alpha L(k); 2d <= 2k <= 2 max degree, so both
+// logs come from the table (the clamp only keeps a broken table in bounds)
+__device__ __forceinline__ double rank_of(const Ctx &c, int32_t d, int32_t k, double alpha) {
+    const int32_t i2 = min(2 * d, c.logtab_last);
+    const int32_t ik = min(k, c.logtab_last);
+    return c.logtab[i2] - alpha * c.logtab[ik];
+}
+
+template <bool GLOBAL>
+__device__ __forceinline__ int32_t tab_find(const Tab &t, int32_t u, uint32_t &err) {
+    uint32_t p = hash_of(u, t.hbits);
+    for (uint32_t it = 0; it <= t.hmask; ++it) {
+        int32_t i = hs_load<GLOBAL>(&t.hs[p]);
+        if (i < 0)
+            return -1;
+        if (t.node[i] == u)
+            return i;
+        p = (p + 1) & t.hmask;
+    }
+    err |= ERR_PROBE;
+    return -1;
+}
+
+// Dense index of u for every active lane, inserting absent ids.  All active
+// ids of one call are distinct.  Returns -1 for inactive lanes, and for all
+// lanes when the table would overflow (st.ovf is then set).
+template <bool GLOBAL>
+__device__ int32_t tab_ensure(const Tab &t, St &st, const Ctx &c, bool act, int32_t u, int lane) {
+    int32_t idx = act ? tab_find<GLOBAL>(t, u, st.err) : -1;
+    bool need = act && idx < 0;
+    uint64_t m = __ballot(need);
+    if (m == 0)
+        return idx;
+    int nn = __popcll(m);
+    if (st.count + nn > t.cap) {
+        st.ovf = true;
+        return -1;
+    }
+    if (need) {
+        idx = st.count + __popcll(m & lanes_below(lane));
+        t.node[idx] = u;
+        t.kv[idx] = c.kdeg[u];
+        t.dv[idx] = 0u;
+        uint32_t p = hash_of(u, t.hbits);
+        uint32_t it = 0;
+        for (; it <= t.hmask; ++it) {
+            if (atomicCAS(&t.hs[p], -1, idx) == -1)
+                break;
+            p = (p + 1) & t.hmask;
+        }
+        if (it > t.hmask)
+            st.err |= ERR_PROBE;
+    }
+    st.count += nn;
+    wsync<GLOBAL>();
+    return idx;
+}
+
+enum { ROW_INIT = 0, ROW_ADD = 1, ROW_REMOVE = 2 };
+
+// Apply the edges of node n to the table: d_in += w for INIT and ADD,
+// d_in -= w for REMOVE.  For ADD, every non-member neighbour is (re)queued
+// with its new rank (the queue update of Algorithm 1).
+template <bool GLOBAL, int MODE>
+__device__ void row_update(const Tab &t, St &st, const Ctx &c, int32_t n, int lane) {
+    const int32_t beg = c.row_ptr[n];
+    const int32_t end = c.row_ptr[n + 1];
+    for (int32_t base = beg; base < end; base += 64) {
+        const int32_t j = base + lane;
+        const bool act = j < end;
+        const int32_t u = act ? c.col[j] : 0;
+        const int32_t wt = act ? (c.w ? (int32_t)c.w[j] : 1) : 0;
+        int32_t idx;
+        if constexpr (MODE == ROW_REMOVE) {
+            idx = act ? tab_find<GLOBAL>(t, u, st.err) : -1;
+            if (act && idx < 0)
+                st.err |= ERR_MISSING;
+        } else {
+            idx = tab_ensure<GLOBAL>(t, st, c, act, u, lane);
+            if (st.ovf)
+                return;
+        }
+        if (act && idx >= 0) {
+            const uint32_t v = t.dv[idx];
+            int32_t d = (int32_t)(v & kDMask);
+            if constexpr (MODE == ROW_REMOVE) {
+                d -= wt;
+                t.dv[idx] = (v & ~kDMask) | (uint32_t)d;
+            } else if constexpr (MODE == ROW_INIT) {
+                d += wt;
+                t.dv[idx] = (v & ~kDMask) | (uint32_t)d;
+            } else {
+                d += wt;
+                if (v & kMember) {
+                    t.dv[idx] = (v & ~kDMask) | (uint32_t)d;
+                } else {
+                    // still queued unless popped and rejected above the node just added
+                    const bool queued = (v & kLive) && !before(t.rk[idx], u, st.pr, st.pu);
+                    if (!queued)
+                        st.Gl += 1;
+                    const int32_t k = t.kv[idx];
+                    t.rk[idx] = rank_of(c, d, k, st.alpha);
+                    st.Rl += 1;
+                    t.dv[idx] = (uint32_t)d | kLive | kFresh;
+                }
+            }
+        }
+    }
+    wsync<GLOBAL>();
+}
+
+// Full decision "f(Kp, Vp) > f(K, V)" in the log domain (K, V > 0 here).
+__device__ __forceinline__ bool decide(const St &st, int64_t Kp, int64_t Vp) {
+    if (Kp == 0)
+        return false;
+    if (st.K == 0)
+        return true;
+    const double a = ilog((uint64_t)Kp) - st.LK;
+    const double b = ilog((uint64_t)Vp) - st.LV;
+    const double cc = st.alpha * b;
+    const double t = a - cc;
+    return t > kMargin;
+}
+
+// Would adding a non-member with (d, k) raise f?  The pre-test uses
+// ln(1+x) <= x and ln(1+y) >= y/(1+y):  the exact gain is at most
+//   2d/K - alpha k/(V+k),
+// evaluated multiplied out by K (V+k) (every product of integers below 2^53
+// is exact); when that bound is below -1e-9 the exact gain, and therefore
+// the computed one (error < 1e-11 for alpha <= 1000), is far below the
+// threshold, so the full test would reject as well.
+__device__ __forceinline__ bool improves_add(const St &st, int32_t d, int32_t k) {
+    if (st.K == 0)
+        return true;
+    const int64_t Kp = st.K + 2 * (int64_t)d;
+    const int64_t Vp = st.V + k;
+    const double X = (double)(2 * (int64_t)d) * (double)Vp - st.alpha * ((double)k * (double)st.K);
+    if (X < -kFilter * ((double)st.K * (double)Vp))
+        return false;
+    return decide(st, Kp, Vp);
+}
+
+// Would removing a member with internal weight d and degree k raise f?
+// Bound: ln(1-x) <= -x and -ln(1-y) <= y/(1-y) give a gain of at most
+//   -2d/K + alpha k/(V-k).
+__device__ __forceinline__ bool improves_remove(const St &st, int32_t d, int32_t k) {
+    const int64_t Kp = st.K - 2 * (int64_t)d;
+    if (Kp <= 0)
+        return false;
+    const int64_t Vp = st.V - k;
+    const double X = -(double)(2 * (int64_t)d) * (double)Vp + st.alpha * ((double)k * (double)st.K);
+    if (X < -kFilter * ((double)st.K * (double)Vp))
+        return false;
+    return decide(st, Kp, Vp);
+}
+
+__device__ __forceinline__ void set_logs(St &st) {
+    st.LK = st.K > 0 ? ilog((uint64_t)st.K) : 0.0;
+    st.LV = st.V > 0 ? ilog((uint64_t)st.V) : 0.0;
+}
+
+__device__ __forceinline__ void wave_argmax(double &r, int32_t &u, int32_t &i) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double r2 = __shfl_xor(r, off);
+        const int32_t u2 = __shfl_xor(u, off);
+        const int32_t i2 = __shfl_xor(i, off);
+        if (before(r2, u2, r, u)) {
+            r = r2;
+            u = u2;
+            i = i2;
+        }
+    }
+}
+
+__device__ __forceinline__ void wave_argmin(int32_t &u, int32_t &i) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int32_t u2 = __shfl_xor(u, off);
+        const int32_t i2 = __shfl_xor(i, off);
+        if (u2 < u) {
+            u = u2;
+            i = i2;
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v |= __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off);
+    return v;
+}
+
+// One call of the growth function (Algorithm 1) at st.alpha.
+// Returns the number of moves; stops early on table overflow.
+template <bool GLOBAL>
+__device__ int64_t grow(const Tab &t, St &st, const Ctx &c, uint32_t k_prune, int lane) {
+    int64_t moves = 0;
+    bool creation = true;
+    for (;;) {
+        double br = -__builtin_huge_val();
+        int32_t bu = INT32_MAX;
+        int32_t bi = -1;
+        for (int32_t i = lane; i < st.count; i += 64) {
+            uint32_t v = t.dv[i];
+            double r;
+            if (creation) {
+                // the queue is built from every non-member with a link into c
+                if ((v & kMember) || (v & kDMask) == 0) {
+                    if (v & (kLive | kFresh))
+                        t.dv[i] = v & ~(kLive | kFresh);
+                    continue;
+                }
+                const int32_t d = (int32_t)(v & kDMask);
+                r = rank_of(c, d, t.kv[i], st.alpha);
+                t.rk[i] = r;
+                st.Rl += 1;
+                st.Gl += 1;
+                v = (v | kLive) & ~kFresh;
+                t.dv[i] = v;
+            } else {
+                if (!(v & kLive))
+                    continue;
+                r = t.rk[i];
+                if (v & kFresh) {
+                    v &= ~kFresh;
+                    t.dv[i] = v;
+                } else if (before(r, t.node[i], st.pr, st.pu)) {
+                    t.dv[i] = v & ~kLive;      // popped and rejected last step
+                    continue;
+                }
+            }
+            const int32_t u = t.node[i];
+            if (before(r, u, br, bu) && improves_add(st, (int32_t)(v & kDMask), t.kv[i])) {
+                br = r;
+                bu = u;
+                bi = i;
+            }
+        }
+        creation = false;
+        wave_argmax(br, bu, bi);
+        wsync<GLOBAL>();
+        if (bi < 0)
+            break;
+        // add the best improving node
+        const uint32_t v = t.dv[bi];
+        const int32_t d = (int32_t)(v & kDMask);
+        const int32_t k = t.kv[bi];
+        wsync<GLOBAL>();
+        if (lane == 0)
+            t.dv[bi] = (v | kMember) & ~(kLive | kFresh);
+        st.K += 2 * (int64_t)d;
+        st.V += k;
+        st.nmem += 1;
+        st.M += 1;
+        moves += 1;
+        st.pr = br;
+        st.pu = bu;
+        set_logs(st);
+        wsync<GLOBAL>();
+        row_update<GLOBAL, ROW_ADD>(t, st, c, bu, lane);
+        if (st.ovf)
+            return moves;
+        if ((int64_t)st.M > st.move_limit) {
+            st.err |= ERR_LIMIT;
+            return moves;
+        }
+    }
+    if (moves == 0)
+        return 0;
+    // removal passes over the members in ascending id
+    for (uint32_t pass = 0; k_prune == 0 || pass < k_prune; ++pass) {
+        st.Gu += (uint64_t)st.nmem;
+        int32_t cursor = -1;
+        bool removed = false;
+        for (;;) {
+            int32_t cu = INT32_MAX;
+            int32_t ci = -1;
+            for (int32_t i = lane; i < st.count; i += 64) {
+                const uint32_t v = t.dv[i];
+                if (!(v & kMember))
+                    continue;
+                const int32_t u = t.node[i];
+                if (u <= cursor || u >= cu)
+                    continue;
+                if (improves_remove(st, (int32_t)(v & kDMask), t.kv[i])) {
+                    cu = u;
+                    ci = i;
+                }
+            }
+            wave_argmin(cu, ci);
+            wsync<GLOBAL>();
+            if (ci < 0)
+                break;
+            const uint32_t v = t.dv[ci];
+            const int32_t d = (int32_t)(v & kDMask);
+            const int32_t k = t.kv[ci];
+            wsync<GLOBAL>();
+            if (lane == 0)
+                t.dv[ci] = v & ~kMember;
+            st.K -= 2 * (int64_t)d;
+            st.V -= k;
+            st.nmem -= 1;
+            st.M += 1;
+            moves += 1;
+            set_logs(st);
+            wsync<GLOBAL>();
+            row_update<GLOBAL, ROW_REMOVE>(t, st, c, cu, lane);
+            removed = true;
+            cursor = cu;
+            if ((int64_t)st.M > st.move_limit) {
+                st.err |= ERR_LIMIT;
+                return moves;
+            }
+        }
+        if (!removed)
+            break;
+    }
+    return moves;
+}
+
+// Ascending sort of a[0..m) by one wave: bitonic network in its all-ascending
+// form (each merge starts with a "flip" stage), with virtual +inf padding to
+// the next power of two so comparators that touch the padding are no-ops.
+template <bool GLOBAL>
+__device__ void wave_sort(int32_t *a, int32_t m, int lane) {
+    int32_t P = 1;
+    while (P < m)
+        P <<= 1;
+    const int32_t half_n = P >> 1;
+    for (int32_t k = 2; k <= P; k <<= 1) {
+        const int32_t hk = k >> 1;
+        for (int32_t t = lane; t < half_n; t += 64) {
+            const int32_t blk = t / hk;
+            const int32_t off = t - blk * hk;
+            const int32_t i = blk * k + off;
+            const int32_t l = blk * k + k - 1 - off;
+            if (l < m) {
+                const int32_t x = a[i], y = a[l];
+                if (x > y) {
+                    a[i] = y;
+                    a[l] = x;
+                }
+            }
+        }
+        wsync<GLOBAL>();
+        for (int32_t j = k >> 2; j >= 1; j >>= 1) {
+            for (int32_t t = lane; t < half_n; t += 64) {
+                const int32_t i = (t / j) * 2 * j + (t % j);
+                const int32_t l = i + j;
+                if (l < m) {
+                    const int32_t x = a[i], y = a[l];
+                    if (x > y) {
+                        a[i] = y;
+                        a[l] = x;
+                    }
+                }
+            }
+            wsync<GLOBAL>();
+        }
+    }
+}
+
+template <bool GLOBAL>
+__device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
+    Ctx c;
+    c.row_ptr = A.g.row_ptr;
+    c.col = A.g.col;
+    c.w = A.g.w;
+    c.kdeg = A.g.kdeg;
+    c.logtab = A.g.logtab;
+    c.logtab_last = A.g.logtab_n - 1;
+    const uint32_t n_items = A.tier == 0 ? (uint32_t)A.n_sets : A.ctl->ovf_count[A.tier - 1];
+    for (;;) {
+        uint32_t item = 0;
+        if (lane == 0)
+            item = atomicAdd(&A.ctl->work_next[A.tier], 1u);
+        item = __shfl(item, 0);
+        if (item >= n_items)
+            break;
+        const int32_t set = A.tier == 0 ? (int32_t)item : A.work_in[item];
+
+        if constexpr (!GLOBAL) {
+            for (uint32_t i = lane; i <= t.hmask; i += 64)
+                t.hs[i] = -1;
+            wsync<GLOBAL>();
+        }
+        St st;
+        st.count = 0;
+        st.nmem = 0;
+        st.K = 0;
+        st.V = 0;
+        st.LK = st.LV = 0.0;
+        st.alpha = 0.0;
+        st.pr = 0.0;
+        st.pu = 0;
+        st.Gl = st.Rl = 0;
+        st.Gu = 0;
+        st.M = 0;
+        st.ovf = false;
+        st.err = 0;
+        st.move_limit = 8 * (int64_t)A.g.n + 65536;
+
+        // initial community: the seed set, or the members recorded at the
+        // previous scale when resuming
+        const int32_t *init = nullptr;
+        int32_t n_init = 0;
+        bool bad = false;
+        if (A.resume) {
+            const int64_t r = (int64_t)set * A.S + (A.s_begin - 1);
+            const int64_t off = A.rec.off[r];
+            n_init = A.rec.cnt[r];
+            if (off < 0 || off + n_init > A.pool_cap)
+                bad = true;   // the pool overflowed earlier: the host reruns
+            else
+                init = A.pool + off;
+        } else {
+            init = A.seed_nodes + A.seed_ptr[set];
+            n_init = A.seed_ptr[set + 1] - A.seed_ptr[set];
+        }
+        for (int32_t q = 0; q < n_init && !bad; ++q) {
+            const int32_t u = init[q];
+            const int32_t idx = tab_ensure<GLOBAL>(t, st, c, lane == 0, u, lane);
+            if (st.ovf)
+                break;
+            const int32_t i0 = __shfl(idx, 0);
+            const uint32_t v = t.dv[i0];
+            wsync<GLOBAL>();
+            if (lane == 0)
+                t.dv[i0] = v | kMember;
+            st.K += 2 * (int64_t)(v & kDMask);
+            st.V += c.kdeg[u];
+            st.nmem += 1;
+            wsync<GLOBAL>();
+            row_update<GLOBAL, ROW_INIT>(t, st, c, u, lane);
+            if (st.ovf)
+                break;
+        }
+
+        st.err = wave_or(st.err);
+        int64_t last_off = -1;
+        int32_t last_cnt = 0;
+        for (int32_t s = A.s_begin; s < A.s_end && !st.ovf && !bad && !st.err; ++s) {
+            st.alpha = A.scales[s];
+            set_logs(st);
+            st.Gl = st.Rl = 0;
+            st.Gu = 0;
+            st.M = 0;
+            uint64_t calls = 0;
+            int64_t moved = 0;
+            for (;;) {
+                calls += 1;
+                const int64_t mv = grow<GLOBAL>(t, st, c, A.k_prune, lane);
+                st.err = wave_or(st.err);   // probe failures are per lane
+                moved += mv;
+                if (st.ovf || st.err || mv == 0)
+                    break;
+                if ((int64_t)calls > st.move_limit) {
+                    st.err |= ERR_LIMIT;
+                    break;
+                }
+            }
+            if (st.ovf || st.err)
+                break;
+            const int64_t r = (int64_t)set * A.S + s;
+            const uint64_t G = wave_sum((uint64_t)st.Gl) + st.Gu;
+            const uint64_t R = wave_sum((uint64_t)st.Rl);
+            if (s == A.s_begin || moved > 0) {
+                // members, sorted, into the pool
+                int32_t m = 0;
+                for (int32_t base = 0; base < st.count; base += 64) {
+                    const int32_t i = base + lane;
+                    const bool ism = i < st.count && (t.dv[i] & kMember);
+                    const uint64_t bm = __ballot(ism);
+                    if (ism)
+                        t.scr[m + __popcll(bm & lanes_below(lane))] = t.node[i];
+                    m += __popcll(bm);
+                }
+                wsync<GLOBAL>();
+                wave_sort<GLOBAL>(t.scr, m, lane);
+                unsigned long long off = 0;
+                if (lane == 0)
+                    off = atomicAdd(A.pool_cursor, (unsigned long long)m);
+                off = __shfl(off, 0);
+                if ((int64_t)off + m <= A.pool_cap) {
+                    for (int32_t i = lane; i < m; i += 64)
+                        A.pool[off + i] = t.scr[i];
+                }
+                last_off = (int64_t)off;
+                last_cnt = m;
+            }
+            if (lane == 0) {
+                A.rec.off[r] = last_off;
+                A.rec.cnt[r] = last_cnt;
+                A.rec.K[r] = st.K;
+                A.rec.V[r] = st.V;
+                A.rec.f[r] = st.K == 0 ? 0.0 : (double)st.K / pow((double)st.V, st.alpha);
+                A.rec.ctr[4 * r + 0] = G;
+                A.rec.ctr[4 * r + 1] = R;
+                A.rec.ctr[4 * r + 2] = st.M;
+                A.rec.ctr[4 * r + 3] = calls;
+            }
+        }
+        if (st.ovf && lane == 0) {
+            if (A.work_out) {
+                const uint32_t pos = atomicAdd(&A.ctl->ovf_count[A.tier], 1u);
+                A.work_out[pos] = set;
+            } else {
+                atomicOr(A.err, ERR_CAPACITY);
+            }
+        }
+        if (st.err) {
+            const uint32_t e = st.err;
+            if (lane == 0)
+                atomicOr(A.err, e);
+        }
+        if constexpr (GLOBAL) {
+            // leave the slab's hash empty for the next community
+            wsync<GLOBAL>();
+            for (int32_t i = lane; i < st.count; i += 64) {
+                uint32_t p = hash_of(t.node[i], t.hbits);
+                for (uint32_t it = 0; it <= t.hmask; ++it) {
+                    if (hs_load<GLOBAL>(&t.hs[p]) == i) {
+                        hs_store<GLOBAL>(&t.hs[p], -1);
+                        break;
+                    }
+                    p = (p + 1) & t.hmask;
+                }
+            }
+            wsync<GLOBAL>();
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) sweep_lds_kernel(SweepArgs A) {
+    extern __shared__ __align__(16) char smem[];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t tb = table_bytes(A.cap, A.hbits);
+    Tab t = carve(smem + wave * tb, A.cap, A.hbits);
+    run_wave<false>(A, t, lane);
+}
+
+__global__ void __launch_bounds__(256) sweep_global_kernel(SweepArgs A) {
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int slot = blockIdx.x * (blockDim.x >> 6) + wave;
+    if (slot >= A.n_slots)
+        return;
+    Tab t = carve(A.gtab + (int64_t)slot * A.gtab_stride, A.cap, A.hbits);
+    run_wave<true>(A, t, lane);
+}
+
+// ---------------------------------------------------------------------------
+// Graph preparation
+// ---------------------------------------------------------------------------
+__global__ void degrees_kernel(const int32_t *row_ptr, const uint8_t *w, int32_t *kdeg, int32_t n) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n)
+        return;
+    const int32_t b = row_ptr[u], e = row_ptr[u + 1];
+    if (!w) {
+        kdeg[u] = e - b;
+        return;
+    }
+    int32_t s = 0;
+    for (int32_t j = b; j < e; ++j)
+        s += w[j];
+    kdeg[u] = s;
+}
+
+__global__ void logtab_kernel(double *tab, int32_t m) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= m)
+        return;
+    tab[x] = x == 0 ? 0.0 : ilog((uint64_t)x);
+}
+
+__global__ void log_kernel(const uint64_t *x, double *out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const uint64_t v = x[i];
+    out[i] = v == 0 ? 0.0 : ilog(v);
+}
+
+__global__ void fill_i32_kernel(int32_t *p, int32_t v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Readout
+// ---------------------------------------------------------------------------
+
+// exclusive scan of the member counts of one scale (single workgroup)
+__global__ void __launch_bounds__(1024) scale_scan_kernel(const int32_t *cnt, int32_t S, int32_t s,
+                                                          int32_t n_sets, int32_t *comm_ptr) {
+    __shared__ int64_t part[1024];
+    const int tid = threadIdx.x;
+    const int64_t per = ((int64_t)n_sets + 1023) / 1024;
+    const int64_t lo = tid * per;
+    const int64_t hi = lo + per < n_sets ? lo + per : n_sets;
+    int64_t sum = 0;
+    for (int64_t j = lo; j < hi; ++j)
+        sum += cnt[j * S + s];
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int64_t v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int64_t run = part[tid] - sum;
+    for (int64_t j = lo; j < hi; ++j) {
+        comm_ptr[j] = (int32_t)run;
+        run += cnt[j * S + s];
+    }
+    if (tid == 1023)
+        comm_ptr[n_sets] = (int32_t)part[1023];
+}
+
+__global__ void __launch_bounds__(256) scale_gather_kernel(Records rec, const int32_t *pool,
+                                                           const double *scales, int32_t S,
+                                                           int32_t s, int32_t n_sets,
+                                                           const int32_t *comm_ptr, int32_t *members,
+                                                           int64_t *k_in, int64_t *vol, double *f) {
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (j >= n_sets)
+        return;
+    const int64_t r = j * S + s;
+    const int64_t off = rec.off[r];
+    const int32_t m = rec.cnt[r];
+    const int32_t dst = comm_ptr[j];
+    if (members)
+        for (int32_t i = lane; i < m; i += 64)
+            members[dst + i] = pool[off + i];
+    if (lane == 0) {
+        if (k_in)
+            k_in[j] = rec.K[r];
+        if (vol)
+            vol[j] = rec.V[r];
+        if (f)
+            f[j] = rec.f[r];
+    }
+}
+
+__global__ void overlap_count_kernel(const int32_t *members, int64_t total, int32_t *cnt) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[members[i]], 1);
+}
+
+// three-phase exclusive scan of n counts into ptr[0..n]
+__global__ void __launch_bounds__(1024) scan_blocks_kernel(const int32_t *cnt, int64_t n,
+                                                           int32_t *ptr, int32_t *block_sums) {
+    __shared__ int32_t part[1024];
+    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    const int32_t v = i < n ? cnt[i] : 0;
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int32_t x = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += x;
+        __syncthreads();
+    }
+    if (i < n)
+        ptr[i] = part[threadIdx.x] - v;
+    if (threadIdx.x == 1023)
+        block_sums[blockIdx.x] = part[1023];
+}
+
+__global__ void __launch_bounds__(1024) scan_sums_kernel(int32_t *block_sums, int32_t nb,
+                                                         int32_t *total_out) {
+    __shared__ int32_t part[1024];
+    const int tid = threadIdx.x;
+    const int per = (nb + 1023) / 1024;
+    const int lo = tid * per;
+    const int hi = lo + per < nb ? lo + per : nb;
+    int32_t sum = 0;
+    for (int j = lo; j < hi; ++j)
+        sum += block_sums[j];
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int32_t x = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += x;
+        __syncthreads();
+    }
+    int32_t run = part[tid] - sum;
+    for (int j = lo; j < hi; ++j) {
+        const int32_t b = block_sums[j];
+        block_sums[j] = run;
+        run += b;
+    }
+    if (tid == 1023)
+        *total_out = part[1023];
+}
+
+__global__ void scan_add_kernel(int32_t *ptr, int64_t n, const int32_t *block_sums) {
+    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    if (i < n)
+        ptr[i] += block_sums[blockIdx.x];
+}
+
+__global__ void __launch_bounds__(256) overlap_scatter_kernel(const int32_t *comm_ptr,
+                                                              const int32_t *members, int32_t n_sets,
+                                                              const int32_t *node_ptr, int32_t *fill,
+                                                              int32_t *node_sets) {
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (j >= n_sets)
+        return;
+    for (int32_t i = comm_ptr[j] + lane; i < comm_ptr[j + 1]; i += 64) {
+        const int32_t u = members[i];
+        const int32_t pos = atomicAdd(&fill[u], 1);
+        node_sets[node_ptr[u] + pos] = (int32_t)j;
+    }
+}
+
+// Sort every node's list: lanes sort short lists alone; each long list is
+// then sorted by the whole wave.
+__global__ void __launch_bounds__(256) overlap_sort_kernel(const int32_t *node_ptr, int32_t n,
+                                                           int32_t *node_sets) {
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t u = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * 64 + lane;
+    int32_t lo = 0, len = 0;
+    if (u < n) {
+        lo = node_ptr[u];
+        len = node_ptr[u + 1] - lo;
+    }
+    const bool longl = len > 32;
+    if (!longl && len > 1) {
+        int32_t *a = node_sets + lo;
+        for (int32_t i = 1; i < len; ++i) {
+            const int32_t x = a[i];
+            int32_t j = i - 1;
+            while (j >= 0 && a[j] > x) {
+                a[j + 1] = a[j];
+                --j;
+            }
+            a[j + 1] = x;
+        }
+    }
+    uint64_t todo = __ballot(longl);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    while (todo) {
+        const int src = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        const int32_t l0 = __shfl(lo, src);
+        const int32_t n0 = __shfl(len, src);
+        wave_sort<true>(node_sets + l0, n0, lane);
+    }
+}
+
+__global__ void counter_sum_kernel(const uint64_t *ctr, int64_t n_rec, unsigned long long *tot) {
+    unsigned long long s[4] = {0, 0, 0, 0};
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rec;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        for (int q = 0; q < 4; ++q)
+            s[q] += ctr[4 * r + q];
+    }
+    for (int q = 0; q < 4; ++q) {
+        unsigned long long v = s[q];
+        for (int off = 32; off >= 1; off >>= 1)
+            v += __shfl_xor(v, off);
+        if ((threadIdx.x & 63) == 0 && v)
+            atomicAdd(&tot[q], v);
+    }
+}
+
+inline int grid_for(int64_t n, int block) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1)
+        g = 1;
+    if (g > 65535 * 64)
+        g = 65535 * 64;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_degrees(const int32_t *row_ptr, const uint8_t *w, int32_t *kdeg, int32_t n,
+                          hipStream_t st) {
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(degrees_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, row_ptr, w, kdeg, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_logtab(double *tab, int32_t m, hipStream_t st) {
+    hipLaunchKernelGGL(logtab_kernel, dim3(grid_for(m, 256)), dim3(256), 0, st, tab, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_log(const uint64_t *x, double *out, int64_t n, hipStream_t st) {
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(log_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, x, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st) {
+    if (n == 0)
+        return hipSuccess;
+    int64_t g = (n + 255) / 256;
+    if (g > 16384)
+        g = 16384;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((int)g), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_bytes(void *p, int64_t bytes, hipStream_t st) {
+    // callers pass 4-byte multiples
+    return launch_fill_i32((int32_t *)p, 0, bytes / 4, st);
+}
+
+hipError_t launch_sweep(const SweepArgs &a, int32_t blocks, int32_t waves_per_block, hipStream_t st) {
+    if (blocks <= 0)
+        return hipSuccess;
+    if (a.tier == 0) {
+        const size_t smem = (size_t)waves_per_block * (size_t)table_bytes(a.cap, a.hbits);
+        hipLaunchKernelGGL(sweep_lds_kernel, dim3(blocks), dim3(64 * waves_per_block), smem, st, a);
+    } else {
+        hipLaunchKernelGGL(sweep_global_kernel, dim3(blocks), dim3(64 * waves_per_block), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_scan(const Records &rec, int32_t S, int32_t s, int32_t n_sets,
+                             int32_t *comm_ptr, hipStream_t st) {
+    hipLaunchKernelGGL(scale_scan_kernel, dim3(1), dim3(1024), 0, st, rec.cnt, S, s, n_sets, comm_ptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_gather(const Records &rec, const int32_t *pool, const double *scales,
+                               int32_t S, int32_t s, int32_t n_sets, const int32_t *comm_ptr,
+                               int32_t *members, int64_t *k_in, int64_t *vol, double *f,
+                               hipStream_t st) {
+    if (n_sets == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(scale_gather_kernel, dim3((n_sets + 3) / 4), dim3(256), 0, st, rec, pool, scales,
+                       S, s, n_sets, comm_ptr, members, k_in, vol, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_overlap(const int32_t *comm_ptr, const int32_t *members, int64_t total,
+                               int32_t n_sets, int32_t n, int32_t *node_ptr, int32_t *node_sets,
+                               int32_t *cnt, int32_t *block_sums, hipStream_t st) {
+    hipError_t e;
+    if ((e = launch_fill_i32(cnt, 0, (int64_t)n + 1, st)) != hipSuccess)
+        return e;
+    if (total > 0) {
+        hipLaunchKernelGGL(overlap_count_kernel, dim3(grid_for(total, 256) < 8192 ? grid_for(total, 256) : 8192),
+                           dim3(256), 0, st, members, total, cnt);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+    }
+    const int64_t nn = (int64_t)n + 1;
+    const int nb = (int)((nn + 1023) / 1024);
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3(nb), dim3(1024), 0, st, cnt, nn, node_ptr, block_sums);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, st, block_sums, nb, block_sums + nb);
+    hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(1024), 0, st, node_ptr, nn, block_sums);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    if ((e = launch_fill_i32(cnt, 0, (int64_t)n + 1, st)) != hipSuccess)
+        return e;
+    if (n_sets > 0) {
+        hipLaunchKernelGGL(overlap_scatter_kernel, dim3((n_sets + 3) / 4), dim3(256), 0, st, comm_ptr,
+                           members, n_sets, node_ptr, cnt, node_sets);
+    }
+    if (n > 0) {
+        const int64_t waves = ((int64_t)n + 63) / 64;
+        hipLaunchKernelGGL(overlap_sort_kernel, dim3((int)((waves + 3) / 4)), dim3(256), 0, st, node_ptr,
+                           n, node_sets);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_counter_sum(const uint64_t *ctr, int64_t n_rec, unsigned long long *tot,
+                              hipStream_t st) {
+    if (n_rec == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(counter_sum_kernel, dim3(grid_for(n_rec, 256) < 4096 ? grid_for(n_rec, 256) : 4096),
+                       dim3(256), 0, st, ctr, n_rec, tot);
+    return hipGetLastError();
+}
+
+}  // namespace lcd

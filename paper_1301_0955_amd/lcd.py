@@ -1,0 +1,325 @@
+"""Python binding of the C ABI in include/lcd.h (liblcd.so).
+
+Argument marshalling only: every step of the sweep and of the readout runs
+in the library's HIP kernels.  PyTorch supplies device memory and the
+current stream.  There is no fallback: if the built library is missing,
+importing or calling this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblcd.so")
+
+LCD_OK, LCD_EINVAL, LCD_ENOMEM, LCD_EDEVICE, LCD_EAGAIN, LCD_ECAPACITY, LCD_ESTATE = range(7)
+LCD_MEM_HOST, LCD_MEM_DEVICE = 0, 1
+LCD_PERSISTENT, LCD_PER_SCALE_LOOP = 0, 1
+
+_STATUS = {0: "LCD_OK", 1: "LCD_EINVAL", 2: "LCD_ENOMEM", 3: "LCD_EDEVICE", 4: "LCD_EAGAIN",
+           5: "LCD_ECAPACITY", 6: "LCD_ESTATE"}
+
+
+class LcdError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__("%s: %s (%s)" % (where, msg, _STATUS.get(status, status)))
+        self.status = status
+
+
+class lcd_params(ctypes.Structure):
+    _fields_ = [("k_prune", ctypes.c_uint32), ("mode", ctypes.c_int32),
+                ("lds_capacity", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("pool_hint", ctypes.c_int64)]
+
+
+class lcd_sweep_stats(ctypes.Structure):
+    _fields_ = [("ms_total", ctypes.c_double), ("ms_main", ctypes.c_double),
+                ("ms_spill", ctypes.c_double), ("n_spilled", ctypes.c_int64),
+                ("n_spilled_big", ctypes.c_int64), ("pool_used", ctypes.c_int64),
+                ("reruns", ctypes.c_int32), ("lds_capacity", ctypes.c_int32),
+                ("waves_per_block", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
+                ("launches", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+_lib = None
+P = ctypes.c_void_p
+
+
+def library() -> ctypes.CDLL:
+    """The loaded liblcd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("liblcd.so is not built (run paper_1301_0955_amd/build.py)")
+    L = ctypes.CDLL(LIB_PATH)
+    st = ctypes.c_int
+    sig = {
+        "lcd_params_default": (None, [ctypes.POINTER(lcd_params)]),
+        "lcd_graph_upload": (st, [ctypes.c_int32, ctypes.c_int64, P, P, P, ctypes.c_int32, P,
+                                  ctypes.POINTER(P)]),
+        "lcd_graph_info": (st, [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+        "lcd_graph_free": (st, [P]),
+        "lcd_sweep": (st, [P, P, ctypes.c_int32, P, P, ctypes.c_int32, ctypes.c_int32,
+                           ctypes.POINTER(lcd_params), P, ctypes.POINTER(P)]),
+        "lcd_result_shape": (st, [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+        "lcd_result_sizes": (st, [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+        "lcd_result_membership": (st, [P, ctypes.c_int32, P, P, P, P, P, ctypes.c_int32, P]),
+        "lcd_result_overlap": (st, [P, ctypes.c_int32, P, P, ctypes.c_int32, P]),
+        "lcd_result_counters": (st, [P, P, P, ctypes.c_int32, P]),
+        "lcd_result_stats": (st, [P, ctypes.POINTER(lcd_sweep_stats)]),
+        "lcd_result_free": (st, [P]),
+        "lcd_log_device": (st, [P, P, ctypes.c_int64, P]),
+        "lcd_device_info": (st, [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(ctypes.c_int64), ctypes.c_char_p, ctypes.c_int32]),
+        "lcd_last_error": (ctypes.c_char_p, []),
+        "lcd_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str):
+    if status != LCD_OK:
+        msg = library().lcd_last_error().decode(errors="replace")
+        raise LcdError(status, where, msg)
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(a, dtype) -> torch.Tensor:
+    if isinstance(a, torch.Tensor):
+        return a.to(device="cuda", dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).to("cuda")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# Thin wrappers with the C names
+# ---------------------------------------------------------------------------
+
+def lcd_version() -> str:
+    return library().lcd_version().decode()
+
+
+def lcd_device_info() -> dict:
+    cu = ctypes.c_int32()
+    lc = ctypes.c_int64()
+    lb = ctypes.c_int64()
+    arch = ctypes.create_string_buffer(64)
+    _check(library().lcd_device_info(ctypes.byref(cu), ctypes.byref(lc), ctypes.byref(lb), arch, 64),
+           "lcd_device_info")
+    return dict(compute_units=cu.value, lds_per_cu=lc.value, lds_per_block=lb.value,
+                arch=arch.value.decode())
+
+
+def lcd_log_device(x: torch.Tensor) -> torch.Tensor:
+    """L(x) on the device for integer x in [1, 2^53) (int64 tensor)."""
+    x = _dev(x, torch.int64)
+    out = torch.empty(x.shape, dtype=torch.float64, device="cuda")
+    _check(library().lcd_log_device(_ptr(x), _ptr(out), x.numel(), _stream()), "lcd_log_device")
+    return out
+
+
+class Graph:
+    """A graph resident on the GPU (lcd_graph_upload)."""
+
+    def __init__(self, n: int, row_ptr, col, w=None):
+        self.n = int(n)
+        rp = _dev(row_ptr, torch.int32)
+        cl = _dev(col, torch.int32)
+        ww = None if w is None else _dev(w, torch.uint8)
+        h = P()
+        _check(library().lcd_graph_upload(self.n, int(cl.numel()), _ptr(rp), _ptr(cl), _ptr(ww),
+                                          LCD_MEM_DEVICE, _stream(), ctypes.byref(h)),
+               "lcd_graph_upload")
+        self._h = h
+
+    @classmethod
+    def from_host(cls, n, row_ptr, col, w=None):
+        """Upload from host numpy arrays (the library validates and copies)."""
+        self = cls.__new__(cls)
+        self.n = int(n)
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        ww = None if w is None else np.ascontiguousarray(w, dtype=np.uint8)
+        h = P()
+        _check(library().lcd_graph_upload(
+            self.n, int(cl.size), rp.ctypes.data_as(P), cl.ctypes.data_as(P),
+            None if ww is None else ww.ctypes.data_as(P), LCD_MEM_HOST, _stream(), ctypes.byref(h)),
+            "lcd_graph_upload")
+        self._h = h
+        return self
+
+    @classmethod
+    def from_workload(cls, g):
+        return cls(g.n, g.row_ptr, g.col, g.w)
+
+    def info(self) -> dict:
+        n = ctypes.c_int32()
+        nnz = ctypes.c_int64()
+        mk = ctypes.c_int64()
+        vol = ctypes.c_int64()
+        _check(library().lcd_graph_info(self._h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(mk),
+                                        ctypes.byref(vol)), "lcd_graph_info")
+        return dict(n=n.value, nnz=nnz.value, max_degree=mk.value, volume=vol.value)
+
+    def free(self):
+        if getattr(self, "_h", None):
+            library().lcd_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Result:
+    """The per-(seed set, scale) output of one sweep (lcd_result)."""
+
+    def __init__(self, h, n: int):
+        self._h = h
+        self.n = n
+        ns = ctypes.c_int32()
+        S = ctypes.c_int32()
+        _check(library().lcd_result_shape(h, ctypes.byref(ns), ctypes.byref(S)), "lcd_result_shape")
+        self.n_sets = ns.value
+        self.n_scales = S.value
+
+    def sizes(self, s: int) -> int:
+        t = ctypes.c_int64()
+        _check(library().lcd_result_sizes(self._h, s, ctypes.byref(t)), "lcd_result_sizes")
+        return t.value
+
+    def membership(self, s: int):
+        """(comm_ptr, members, k_in, vol, f) at scale s, device tensors."""
+        tot = self.sizes(s)
+        cp = torch.empty(self.n_sets + 1, dtype=torch.int32, device="cuda")
+        m = torch.empty(max(tot, 1), dtype=torch.int32, device="cuda")
+        k = torch.empty(max(self.n_sets, 1), dtype=torch.int64, device="cuda")
+        v = torch.empty(max(self.n_sets, 1), dtype=torch.int64, device="cuda")
+        f = torch.empty(max(self.n_sets, 1), dtype=torch.float64, device="cuda")
+        _check(library().lcd_result_membership(self._h, s, _ptr(cp), _ptr(m), _ptr(k), _ptr(v), _ptr(f),
+                                               LCD_MEM_DEVICE, _stream()), "lcd_result_membership")
+        return cp, m[:tot], k[:self.n_sets], v[:self.n_sets], f[:self.n_sets]
+
+    def overlap(self, s: int):
+        """(node_ptr, node_sets) at scale s, device tensors."""
+        tot = self.sizes(s)
+        npt = torch.empty(self.n + 1, dtype=torch.int32, device="cuda")
+        nst = torch.empty(max(tot, 1), dtype=torch.int32, device="cuda")
+        _check(library().lcd_result_overlap(self._h, s, _ptr(npt), _ptr(nst), LCD_MEM_DEVICE, _stream()),
+               "lcd_result_overlap")
+        return npt, nst[:tot]
+
+    def counters(self, per_record: bool = False):
+        tot = (ctypes.c_uint64 * 4)()
+        pr = None
+        if per_record:
+            pr = torch.empty(max(self.n_sets * self.n_scales * 4, 1), dtype=torch.int64, device="cuda")
+        _check(library().lcd_result_counters(self._h, ctypes.cast(tot, P), _ptr(pr), LCD_MEM_DEVICE,
+                                             _stream()), "lcd_result_counters")
+        totals = [int(x) for x in tot]
+        if per_record:
+            return totals, pr[:self.n_sets * self.n_scales * 4].view(-1, 4)
+        return totals
+
+    def stats(self) -> dict:
+        s = lcd_sweep_stats()
+        _check(library().lcd_result_stats(self._h, ctypes.byref(s)), "lcd_result_stats")
+        return s.as_dict()
+
+    def free(self):
+        if getattr(self, "_h", None):
+            library().lcd_result_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def make_params(k_prune: int = 0, mode: int = LCD_PERSISTENT, lds_capacity: int = 0,
+                waves_per_block: int = 0, blocks_per_cu: int = 0, use_graph: int = 0,
+                pool_hint: int = 0) -> lcd_params:
+    p = lcd_params()
+    library().lcd_params_default(ctypes.byref(p))
+    p.k_prune = k_prune
+    p.mode = mode
+    p.lds_capacity = lds_capacity
+    p.waves_per_block = waves_per_block
+    p.blocks_per_cu = blocks_per_cu
+    p.use_graph = use_graph
+    p.pool_hint = pool_hint
+    return p
+
+
+def lcd_sweep(graph: Graph, scales, seed_ptr, seed_nodes, params: Optional[lcd_params] = None,
+              **kw) -> Result:
+    """Grow every seed set through every scale (blocking).  Inputs may be
+    numpy arrays or tensors; they are placed on the device first."""
+    sc = _dev(scales, torch.float64)
+    sp = _dev(seed_ptr, torch.int32)
+    sn = _dev(seed_nodes, torch.int32)
+    if sn.numel() == 0:
+        sn = torch.zeros(1, dtype=torch.int32, device="cuda")
+    prm = params if params is not None else make_params(**kw)
+    h = P()
+    _check(library().lcd_sweep(graph._h, _ptr(sc), int(sc.numel()), _ptr(sp), _ptr(sn),
+                               int(sp.numel()) - 1, LCD_MEM_DEVICE, ctypes.byref(prm), _stream(),
+                               ctypes.byref(h)), "lcd_sweep")
+    return Result(h, graph.n)
+
+
+def sweep_to_numpy(res: Result) -> dict:
+    """Every record of a result as host arrays, laid out like the oracle's
+    (record r = set * S + s; members of r at members[off[r]:off[r]+cnt[r]])."""
+    S = res.n_scales
+    ns = res.n_sets
+    offs = np.zeros(ns * S, dtype=np.int64)
+    cnt = np.zeros(ns * S, dtype=np.int32)
+    K = np.zeros(ns * S, dtype=np.int64)
+    V = np.zeros(ns * S, dtype=np.int64)
+    f = np.zeros(ns * S, dtype=np.float64)
+    chunks = []
+    base = 0
+    for s in range(S):
+        cp, m, k, v, ff = res.membership(s)
+        cp = cp.cpu().numpy().astype(np.int64)
+        m = m.cpu().numpy()
+        idx = np.arange(ns) * S + s
+        offs[idx] = base + cp[:-1]
+        cnt[idx] = np.diff(cp)
+        K[idx] = k.cpu().numpy()
+        V[idx] = v.cpu().numpy()
+        f[idx] = ff.cpu().numpy()
+        chunks.append(m)
+        base += m.size
+    members = np.concatenate(chunks) if chunks else np.zeros(0, np.int32)
+    _, ctr = res.counters(per_record=True)
+    return dict(members=members, off=offs, cnt=cnt, K=K, V=V, f=f,
+                ctr=ctr.cpu().numpy().astype(np.uint64), n_sets=ns, n_scales=S)
