@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Benchmark of the multi-scale local community sweep on one MI355X.
+
+One step = one lcd_sweep() call: every seed set of the workload grown
+through every scale (queue-emulated additions, removal passes, fixpoint per
+scale, chained scales), with sorted member lists, K, V, f and the work
+counters written for every (seed set, scale).  Inputs (graph, seeds,
+scales) are resident on the device before the timed region.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("candidate-node gains/s + full multi-scale sweep time; "
+          "p50/p99 seed-query latency")
+HBM_PEAK_GBS = 8000.0
+RECORD_BYTES = 8 + 4 + 8 + 8 + 8 + 32   # off, cnt, K, V, f, four counters
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def workload(name: str):
+    from paper_1301_0955_amd import workloads as W
+    if name == "small":
+        g, sp, sn, sc = W.workload_small()
+        desc = "planted-partition-1k: 1,000 nodes (4 groups x 5 sub-communities), every node a seed, 10 scales on [0.5,1]"
+    elif name == "medium":
+        g, sp, sn, sc = W.workload_medium()
+        desc = ("lfr2-100k: 100,000-node 2-level LFR-style graph (degree exp 2.5, mean 20, max 100; "
+                "community sizes exp 1.5 on [20,200]; mixing 0.3; unweighted), rule-1 seeds, 32 scales on [0.5,1]")
+    elif name == "large":
+        g, sp, sn, sc = W.workload_large()
+        desc = ("lfr3-1M: 1,000,000-node 3-level LFR-style graph (mean degree 15, max 200, mixing 0.25, "
+                "weights 1..16), rule-1 seeds, 64 scales on [0.5,1]")
+    else:
+        raise SystemExit("unknown workload %s" % name)
+    return g, sp, sn, sc, desc
+
+
+def algorithmic_bytes(t: dict, weighted: bool, seed_nodes: int, n_records: int) -> int:
+    """HBM bytes the method itself must move for the work one tier finished:
+    per gathered CSR row its two offsets and its entries (id, plus weight),
+    one degree read per table entry created, the seed ids, and the output
+    (member ids and one record per (set, scale))."""
+    wb = 1 if weighted else 0
+    return (8 * t["rows_gathered"] + (4 + wb) * t["row_entries"] + 4 * t["entries_created"]
+            + 4 * seed_nodes + 4 * t["members_written"] + RECORD_BYTES * n_records)
+
+
+def cpu_baseline(g, sp, sn, sc, stride, got_res):
+    """The oracle on every stride-th seed set, single thread, on this host."""
+    import oracle
+    from paper_1301_0955_amd import workloads as W
+    sp2, sn2, ids = W.subsample_sets(sp, sn, stride)
+    o = oracle.Oracle.from_graph(g)
+    t0 = time.perf_counter()
+    ref = o.run_sets(sp2, sn2, sc)
+    dt = time.perf_counter() - t0
+    G = int(ref["ctr"][:, 0].sum())
+    parity = None
+    if got_res is not None:
+        S = sc.size
+        ok = True
+        for j, q in enumerate(ids.tolist()):
+            for s in range(S):
+                r, rq = j * S + s, q * S + s
+                a = got_res["members"][got_res["off"][rq]:got_res["off"][rq] + got_res["cnt"][rq]]
+                b = ref["members"][ref["off"][r]:ref["off"][r] + ref["cnt"][r]]
+                if (not np.array_equal(a, b) or got_res["K"][rq] != ref["K"][r]
+                        or not np.array_equal(got_res["ctr"][rq], ref["ctr"][r])):
+                    ok = False
+                    break
+            if not ok:
+                break
+        parity = "bit-exact" if ok else "MISMATCH"
+    return dict(value=G / dt, unit="gains/s", cores=1, kind="oracle",
+                sample="every %dth seed set (%d of %d), all %d scales; %.1f s, %d gains"
+                       % (stride, ids.size, sp.size - 1, sc.size, dt, G),
+                seconds=dt, parity_on_sample=parity)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="medium", choices=["small", "medium", "large"])
+    ap.add_argument("--lds-capacity", type=int, default=0)
+    ap.add_argument("--waves-per-block", type=int, default=0)
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--cpu-stride", type=int, default=0,
+                    help="oracle sample stride (0 = sized for ~15 s)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-loop-compare", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(asked for --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    from paper_1301_0955_amd import lcd
+
+    t0 = time.perf_counter()
+    g, sp, sn, sc, desc = workload(args.workload)
+    log("workload %s ready in %.1f s: n=%d nnz=%d sets=%d scales=%d"
+        % (args.workload, time.perf_counter() - t0, g.n, g.nnz, sp.size - 1, sc.size))
+    G = lcd.Graph.from_workload(g)
+    d_sc = torch.as_tensor(sc, dtype=torch.float64, device="cuda")
+    d_sp = torch.as_tensor(sp, dtype=torch.int32, device="cuda")
+    d_sn = torch.as_tensor(sn, dtype=torch.int32, device="cuda")
+    prm = dict(lds_capacity=args.lds_capacity, waves_per_block=args.waves_per_block,
+               blocks_per_cu=args.blocks_per_cu)
+    torch.cuda.synchronize()
+
+    for i in range(args.warmup):
+        r = lcd.lcd_sweep(G, d_sc, d_sp, d_sn, **prm)
+        st = r.stats()
+        r.free()
+        log("warmup %d: device %.2f ms (main %.2f, spill %.2f), spilled %d, reruns %d"
+            % (i, st["ms_total"], st["ms_main"], st["ms_spill"], st["n_spilled"], st["reruns"]))
+
+    results = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        results.append(lcd.lcd_sweep(G, d_sc, d_sp, d_sn, **prm))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1e3 * wall / max(args.steps, 1)
+    stats = [r.stats() for r in results]
+    totals = results[0].counters()
+    log("timed %d steps: %.2f ms/step wall" % (args.steps, ms_step))
+    got = lcd.sweep_to_numpy(results[0])
+    for r in results:
+        r.free()
+
+    gains = totals[0]
+    ms_main = float(np.mean([s["ms_main"] for s in stats]))
+    ms_spill = float(np.mean([s["ms_spill"] for s in stats]))
+    ms_dev = float(np.mean([s["ms_total"] for s in stats]))
+    st0 = stats[0]
+    S = sc.size
+    weighted = g.w is not None
+    t0s, t1s, t2s = st0["tier"]
+    b_main = algorithmic_bytes(t0s, weighted, int(sn.size) if t0s["sets_finished"] else 0,
+                               t0s["sets_finished"] * S)
+    b_spill = (algorithmic_bytes(t1s, weighted, 0, t1s["sets_finished"] * S)
+               + algorithmic_bytes(t2s, weighted, 0, t2s["sets_finished"] * S))
+    if ms_main >= ms_spill:
+        kname, kbytes, kms = "sweep_lds_kernel", b_main, ms_main
+    else:
+        kname, kbytes, kms = "sweep_global_kernel", b_spill, ms_spill
+    achieved = kbytes / (kms * 1e-3) / 1e9
+    roofline = dict(bound="hbm", kernel=kname, achieved=round(achieved, 2), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 6), traffic=None,
+                    algorithmic_bytes=int(kbytes), kernel_ms=round(kms, 4))
+
+    loop = None
+    if not args.no_loop_compare:
+        r = lcd.lcd_sweep(G, d_sc, d_sp, d_sn, mode=lcd.LCD_PER_SCALE_LOOP, **prm)
+        lst = r.stats()
+        same = lcd.sweep_to_numpy(r)
+        r.free()
+        identical = (np.array_equal(same["K"], got["K"]) and np.array_equal(same["ctr"], got["ctr"])
+                     and np.array_equal(same["cnt"], got["cnt"]))
+        loop = dict(device_ms=round(lst["ms_total"], 3), launches=lst["launches"],
+                    persistent_speedup=round(lst["ms_total"] / ms_dev, 3),
+                    identical_results=bool(identical))
+        log("per-scale loop: %.2f ms device (%d launches)" % (lst["ms_total"], lst["launches"]))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        stride = args.cpu_stride or {"small": 1, "medium": 16, "large": 1024}[args.workload]
+        log("cpu baseline: oracle on every %dth seed set" % stride)
+        cpu = cpu_baseline(g, sp, sn, sc, stride, got)
+        log("cpu baseline: %s" % cpu["sample"])
+
+    out = {
+        "metric": METRIC,
+        "value": gains / (ms_step * 1e-3),
+        "unit": "gains/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": g.n, "nnz": g.nnz, "seed_sets": int(sp.size - 1),
+                   "scales": int(S), "graph_sha256": g.sha256()[:16],
+                   "lds_capacity": st0["lds_capacity"], "waves_per_block": st0["waves_per_block"],
+                   "grid_blocks": st0["grid_blocks"]},
+        "sweep_ms_device": round(ms_dev, 4),
+        "gains_per_step": int(gains),
+        "counters": {"G": totals[0], "R": totals[1], "M": totals[2], "C": totals[3]},
+        "gains_per_s_device": gains / (ms_dev * 1e-3),
+        "spilled_sets": st0["n_spilled"],
+        "roofline": roofline,
+        "per_scale_loop": loop,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -80,6 +80,16 @@ typedef struct {
     int64_t pool_hint;       /* initial member-pool size in entries; 0 = estimate */
 } lcd_params;
 
+/* Work of one table tier (0 = LDS, 1 and 2 = global-memory tiers),
+ * counted over the seed sets that tier finished. */
+typedef struct {
+    int64_t rows_gathered;    /* CSR rows read: one per move and per initial member */
+    int64_t row_entries;      /* total length of those rows */
+    int64_t entries_created;  /* table entries created (one degree read each) */
+    int64_t members_written;  /* member ids written to the output pool */
+    int64_t sets_finished;    /* seed sets completed in this tier */
+} lcd_tier_stats;
+
 /* Timing and bookkeeping of one sweep (filled by lcd_result_stats). */
 typedef struct {
     double ms_total;          /* device time of the whole sweep (hipEvents on the caller's stream) */
@@ -94,6 +104,7 @@ typedef struct {
     int32_t grid_blocks;      /* workgroups of the LDS-resident launch */
     int32_t launches;         /* kernel launches of the sweep (excluding readout) */
     int32_t pad;
+    lcd_tier_stats tier[3];
 } lcd_sweep_stats;
 
 /* Fill *p with the defaults (k_prune 0, persistent mode, autotuned sizes). */

@@ -169,6 +169,9 @@ struct lcd_result {
 
 namespace {
 
+// pool cursor, error word, then 5 statistics per tier
+constexpr int kCursorWords = 2 + 5 * 3 + 1;
+
 struct TierPlan {
     int32_t cap0, hbits0, wpb0, blocks0;
     bool use1, use2;
@@ -257,6 +260,7 @@ lcd_status run_group(lcd_result *r, const TierPlan &tp, int32_t s_begin, int32_t
     a.ctl = r->ctl + gi;
     a.pool_cursor = r->cursor;
     a.err = r->err;
+    a.stat = r->cursor + 2;
 
     if (ev)
         HIPCHK(hipEventRecord(ev[0], st));
@@ -272,8 +276,8 @@ lcd_status run_group(lcd_result *r, const TierPlan &tp, int32_t s_begin, int32_t
     r->stats.launches += 1;
     if (ev)
         HIPCHK(hipEventRecord(ev[1], st));
-    // spill tiers read their item count from the previous tier's counter
-    int prev = 0;
+    // spill tiers read their item count from the tier that pushed to them
+    int from = 0;
     for (int k = 0; k < 2; ++k) {
         const bool use = k == 0 ? tp.use1 : tp.use2;
         if (!use)
@@ -281,25 +285,17 @@ lcd_status run_group(lcd_result *r, const TierPlan &tp, int32_t s_begin, int32_t
         Slab &sl = g->slab[k];
         SweepArgs b = a;
         b.tier = k + 1;
-        // ovf_count index = tier that pushed the items
+        b.in_from = from;
         b.work_in = r->work[k];
-        if (k == 1 && !tp.use1) {
-            b.work_in = r->work[1];
-        }
         b.work_out = (k == 0 && tp.use2) ? r->work[1] : nullptr;
         b.cap = sl.cap;
         b.hbits = sl.hbits;
         b.gtab = sl.buf;
         b.gtab_stride = sl.stride;
         b.n_slots = sl.slots;
-        // when tier 1 is skipped, tier 2 reads tier 0's pushes: shift the tier
-        // index so ovf_count[tier-1] is the right counter
-        if (k == 1 && !tp.use1)
-            b.tier = 1;
-        (void)prev;
         HIPCHK(launch_sweep(b, (sl.slots + 3) / 4, 4, st));
         r->stats.launches += 1;
-        sl.dirty = false;
+        from = k + 1;
     }
     if (ev)
         HIPCHK(hipEventRecord(ev[2], st));
@@ -322,7 +318,7 @@ lcd_status run_sweep(lcd_result *r, hipStream_t st) {
         r->stats.launches = 0;
         // zero the work queues, the pool cursor and the error word
         HIPCHK(launch_zero_bytes(r->ctl, (int64_t)sizeof(Counters) * r->n_ctl, st));
-        HIPCHK(launch_zero_bytes(r->cursor, 16, st));
+        HIPCHK(launch_zero_bytes(r->cursor, 8 * kCursorWords, st));
         HIPCHK(hipEventRecord(ev[3], st));
         float ms_main = 0.f, ms_spill = 0.f;
         if (r->n_sets > 0) {
@@ -338,8 +334,8 @@ lcd_status run_sweep(lcd_result *r, hipStream_t st) {
             HIPCHK(hipEventRecord(ev[2], st));
         }
         HIPCHK(hipEventSynchronize(ev[2]));
-        unsigned long long cur[2] = {0, 0};
-        HIPCHK(hipMemcpy(cur, r->cursor, 16, hipMemcpyDeviceToHost));
+        unsigned long long cur[kCursorWords] = {};
+        HIPCHK(hipMemcpy(cur, r->cursor, 8 * kCursorWords, hipMemcpyDeviceToHost));
         std::vector<Counters> ctl(r->n_ctl);
         HIPCHK(hipMemcpy(ctl.data(), r->ctl, sizeof(Counters) * r->n_ctl, hipMemcpyDeviceToHost));
         float ms_total = 0.f;
@@ -361,11 +357,18 @@ lcd_status run_sweep(lcd_result *r, hipStream_t st) {
         int64_t sp = 0, spb = 0;
         for (auto &c : ctl) {
             sp += c.ovf_count[0];
-            spb += tp.use1 && tp.use2 ? c.ovf_count[1] : 0;
+            spb += tp.use1 && tp.use2 ? c.ovf_count[1] : (tp.use2 ? c.ovf_count[0] : 0);
         }
         r->stats.n_spilled = sp;
         r->stats.n_spilled_big = spb;
         r->stats.pool_used = (int64_t)cur[0];
+        for (int t = 0; t < 3; ++t) {
+            r->stats.tier[t].rows_gathered = (int64_t)cur[2 + 5 * t];
+            r->stats.tier[t].row_entries = (int64_t)cur[3 + 5 * t];
+            r->stats.tier[t].entries_created = (int64_t)cur[4 + 5 * t];
+            r->stats.tier[t].members_written = (int64_t)cur[5 + 5 * t];
+            r->stats.tier[t].sets_finished = (int64_t)cur[6 + 5 * t];
+        }
         if ((int64_t)cur[0] <= r->pool_cap)
             break;
         // the pool was too small: grow it and run again
@@ -640,7 +643,7 @@ lcd_status lcd_sweep(const lcd_graph *g, const double *scales, int32_t n_scales,
         (s = dev_alloc(&r->rec.f, R)) != LCD_OK || (s = dev_alloc(&r->rec.ctr, 4 * R)) != LCD_OK ||
         (s = dev_alloc(&r->pool, (size_t)est)) != LCD_OK ||
         (s = dev_alloc(&r->ctl, (size_t)r->n_ctl)) != LCD_OK ||
-        (s = dev_alloc(&r->cursor, 2)) != LCD_OK ||
+        (s = dev_alloc(&r->cursor, kCursorWords)) != LCD_OK ||
         (s = dev_alloc(&r->work[0], (size_t)std::max(n_sets, 1))) != LCD_OK ||
         (s = dev_alloc(&r->work[1], (size_t)std::max(n_sets, 1))) != LCD_OK) {
         result_release(r);

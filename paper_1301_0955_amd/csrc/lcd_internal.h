@@ -59,8 +59,11 @@ struct SweepArgs {
     Counters *ctl;
     unsigned long long *pool_cursor;   // entries claimed in the pool (may pass pool_cap)
     uint32_t *err;                     // ERR_* bits
-    int32_t tier;             // 0 = LDS; 1.. = global-memory tiers
-    const int32_t *work_in;   // tier > 0: set ids pushed by the previous tier
+    unsigned long long *stat;          // per tier: rows gathered, their length, entries
+                                       // created, pool entries written, sets finished
+    int32_t tier;             // 0 = LDS; 1, 2 = global-memory tiers
+    int32_t in_from;          // tier > 0: the tier whose pushes this one consumes
+    const int32_t *work_in;   // tier > 0: set ids pushed by that tier
     int32_t *work_out;        // sets pushed to the next tier (nullptr for the last)
     int32_t cap;              // table entries per community
     int32_t hbits;            // hash slots = 2^hbits >= 2 * cap

@@ -155,6 +155,10 @@ struct St {
     bool ovf;          // the table ran out of entries
     uint32_t err;
     int64_t move_limit; // guard against a runaway loop in one (set, scale)
+    uint64_t rows;      // CSR rows gathered (moves and initial members)
+    uint64_t row_len;   // ... and their total length
+    uint64_t inserted;  // table entries created (one degree read each)
+    uint64_t written;   // member ids written to the pool
 };
 
 struct Ctx {
@@ -204,6 +208,7 @@ __device__ int32_t tab_ensure(const Tab &t, St &st, const Ctx &c, bool act, int3
         st.ovf = true;
         return -1;
     }
+    st.inserted += (uint64_t)nn;
     if (need) {
         idx = st.count + __popcll(m & lanes_below(lane));
         t.node[idx] = u;
@@ -233,6 +238,8 @@ template <bool GLOBAL, int MODE>
 __device__ void row_update(const Tab &t, St &st, const Ctx &c, int32_t n, int lane) {
     const int32_t beg = c.row_ptr[n];
     const int32_t end = c.row_ptr[n + 1];
+    st.rows += 1;
+    st.row_len += (uint64_t)(end - beg);
     for (int32_t base = beg; base < end; base += 64) {
         const int32_t j = base + lane;
         const bool act = j < end;
@@ -546,7 +553,7 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
     c.kdeg = A.g.kdeg;
     c.logtab = A.g.logtab;
     c.logtab_last = A.g.logtab_n - 1;
-    const uint32_t n_items = A.tier == 0 ? (uint32_t)A.n_sets : A.ctl->ovf_count[A.tier - 1];
+    const uint32_t n_items = A.tier == 0 ? (uint32_t)A.n_sets : A.ctl->ovf_count[A.in_from];
     for (;;) {
         uint32_t item = 0;
         if (lane == 0)
@@ -576,6 +583,7 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
         st.ovf = false;
         st.err = 0;
         st.move_limit = 8 * (int64_t)A.g.n + 65536;
+        st.rows = st.row_len = st.inserted = st.written = 0;
 
         // initial community: the seed set, or the members recorded at the
         // previous scale when resuming
@@ -664,6 +672,7 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
                 }
                 last_off = (int64_t)off;
                 last_cnt = m;
+                st.written += (uint64_t)m;
             }
             if (lane == 0) {
                 A.rec.off[r] = last_off;
@@ -689,6 +698,14 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
             const uint32_t e = st.err;
             if (lane == 0)
                 atomicOr(A.err, e);
+        }
+        if (!st.ovf && lane == 0) {
+            unsigned long long *sx = A.stat + 5 * A.tier;
+            atomicAdd(&sx[0], (unsigned long long)st.rows);
+            atomicAdd(&sx[1], (unsigned long long)st.row_len);
+            atomicAdd(&sx[2], (unsigned long long)st.inserted);
+            atomicAdd(&sx[3], (unsigned long long)st.written);
+            atomicAdd(&sx[4], 1ull);
         }
         if constexpr (GLOBAL) {
             // leave the slab's hash empty for the next community

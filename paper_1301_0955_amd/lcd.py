@@ -38,16 +38,28 @@ class lcd_params(ctypes.Structure):
                 ("pool_hint", ctypes.c_int64)]
 
 
+class lcd_tier_stats(ctypes.Structure):
+    _fields_ = [("rows_gathered", ctypes.c_int64), ("row_entries", ctypes.c_int64),
+                ("entries_created", ctypes.c_int64), ("members_written", ctypes.c_int64),
+                ("sets_finished", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class lcd_sweep_stats(ctypes.Structure):
     _fields_ = [("ms_total", ctypes.c_double), ("ms_main", ctypes.c_double),
                 ("ms_spill", ctypes.c_double), ("n_spilled", ctypes.c_int64),
                 ("n_spilled_big", ctypes.c_int64), ("pool_used", ctypes.c_int64),
                 ("reruns", ctypes.c_int32), ("lds_capacity", ctypes.c_int32),
                 ("waves_per_block", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
-                ("launches", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("launches", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("tier", lcd_tier_stats * 3)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("pad", "tier")}
+        d["tier"] = [t.as_dict() for t in self.tier]
+        return d
 
 
 _lib = None
