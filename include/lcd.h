@@ -78,6 +78,10 @@ typedef struct {
     int32_t blocks_per_cu;   /* resident workgroups per compute unit; 0 = default */
     int32_t use_graph;       /* 1: capture the launch sequence in a hipGraph and replay it */
     int64_t pool_hint;       /* initial member-pool size in entries; 0 = estimate */
+    int32_t watchdog_ms;     /* wall-clock budget of one seed set; past it the sweep
+                                stops with LCD_EDEVICE.  0 = default (20000);
+                                negative = no budget at all (tests the error path) */
+    int32_t pad;
 } lcd_params;
 
 /* Work of one table tier (0 = LDS, 1 and 2 = global-memory tiers),

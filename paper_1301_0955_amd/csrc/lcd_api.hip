@@ -91,6 +91,7 @@ int next_pow2_bits(int64_t x) {
 }
 
 struct DevInfo {
+    int64_t wall_khz = 100000;   // wall_clock64() rate
     int device = -1;
     int cus = 0;
     int64_t lds_cu = 0;
@@ -107,6 +108,9 @@ lcd_status device_info(DevInfo &d) {
     d.lds_cu = v;
     HIPCHK(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, d.device));
     d.lds_block = v;
+    HIPCHK(hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, d.device));
+    if (v > 0)
+        d.wall_khz = v;
     hipDeviceProp_t prop;
     HIPCHK(hipGetDeviceProperties(&prop, d.device));
     std::snprintf(d.arch, sizeof(d.arch), "%s", prop.gcnArchName);
@@ -260,6 +264,7 @@ lcd_status run_group(lcd_result *r, const TierPlan &tp, int32_t s_begin, int32_t
     a.ctl = r->ctl + gi;
     a.pool_cursor = r->cursor;
     a.err = r->err;
+    a.budget_ticks = r->prm.watchdog_ms < 0 ? 0 : g->dev.wall_khz * (int64_t)r->prm.watchdog_ms;
     a.stat = r->cursor + 2;
 
     if (ev)
@@ -348,7 +353,8 @@ lcd_status run_sweep(lcd_result *r, hipStream_t st) {
         if (err) {
             g->slab[0].dirty = g->slab[1].dirty = true;
             status = fail(err & ERR_CAPACITY ? LCD_ECAPACITY : LCD_EDEVICE,
-                          "sweep kernel reported error bits 0x%x", err);
+                          "sweep kernel reported error bits 0x%x%s", err,
+                          err & ERR_TIMEOUT ? " (watchdog: a seed set ran past its time budget)" : "");
             break;
         }
         r->stats.ms_total = ms_total;
@@ -417,6 +423,7 @@ void lcd_params_default(lcd_params *p) {
         return;
     std::memset(p, 0, sizeof(*p));
     p->mode = LCD_PERSISTENT;
+    p->watchdog_ms = 20000;
 }
 
 const char *lcd_last_error(void) { return t_err.c_str(); }
@@ -589,6 +596,8 @@ lcd_status lcd_sweep(const lcd_graph *g, const double *scales, int32_t n_scales,
         prm = *params;
     if (prm.mode != LCD_PERSISTENT && prm.mode != LCD_PER_SCALE_LOOP)
         return fail(LCD_EINVAL, "unknown mode %d", prm.mode);
+    if (prm.watchdog_ms == 0)
+        prm.watchdog_ms = 20000;
     hipStream_t st = (hipStream_t)stream;
     std::vector<double> sc;
     CHK(fetch(sc, scales, (size_t)n_scales, mem_kind, st));

@@ -33,7 +33,8 @@ enum : uint32_t {
     ERR_PROBE = 1u,           // hash probe exceeded the table size
     ERR_MISSING = 2u,         // a neighbour of a member was absent from the table
     ERR_LIMIT = 4u,           // move or growth-call limit of one (set, scale) hit
-    ERR_CAPACITY = 8u         // the largest tier ran out of entries
+    ERR_CAPACITY = 8u,        // the largest tier ran out of entries
+    ERR_TIMEOUT = 16u         // a seed set ran past the watchdog budget (sweep aborted)
 };
 
 // Work-queue state of one launch group (all tiers of one scale range),
@@ -70,6 +71,7 @@ struct SweepArgs {
     char *gtab;               // global tiers: table workspace
     int64_t gtab_stride;      // bytes per table
     int32_t n_slots;          // global tiers: number of tables
+    int64_t budget_ticks;     // watchdog: wall-clock ticks one seed set may take
 };
 
 // Bytes per table entry (dense arrays + scratch) and per hash slot.

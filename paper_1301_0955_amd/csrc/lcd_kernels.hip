@@ -155,11 +155,23 @@ struct St {
     bool ovf;          // the table ran out of entries
     uint32_t err;
     int64_t move_limit; // guard against a runaway loop in one (set, scale)
+    uint64_t t0;        // wall clock when the set started
+    uint64_t budget;    // wall-clock ticks the set may take
     uint64_t rows;      // CSR rows gathered (moves and initial members)
     uint64_t row_len;   // ... and their total length
     uint64_t inserted;  // table entries created (one degree read each)
     uint64_t written;   // member ids written to the pool
 };
+
+// Watchdog: a seed set that runs past its budget stops with ERR_TIMEOUT, so
+// a logic error ends the sweep with an error instead of running on.
+__device__ __forceinline__ bool over_budget(St &st) {
+    if (wall_clock64() - st.t0 > st.budget) {
+        st.err |= ERR_TIMEOUT;
+        return true;
+    }
+    return false;
+}
 
 struct Ctx {
     const int32_t *row_ptr;
@@ -448,6 +460,8 @@ __device__ int64_t grow(const Tab &t, St &st, const Ctx &c, uint32_t k_prune, in
             st.err |= ERR_LIMIT;
             return moves;
         }
+        if (over_budget(st))
+            return moves;
     }
     if (moves == 0)
         return 0;
@@ -495,6 +509,8 @@ __device__ int64_t grow(const Tab &t, St &st, const Ctx &c, uint32_t k_prune, in
                 st.err |= ERR_LIMIT;
                 return moves;
             }
+            if (over_budget(st))
+                return moves;
         }
         if (!removed)
             break;
@@ -561,6 +577,9 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
         item = __shfl(item, 0);
         if (item >= n_items)
             break;
+        // another wave hit the watchdog: stop taking work
+        if (__hip_atomic_load(A.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_TIMEOUT)
+            break;
         const int32_t set = A.tier == 0 ? (int32_t)item : A.work_in[item];
 
         if constexpr (!GLOBAL) {
@@ -583,6 +602,8 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
         st.ovf = false;
         st.err = 0;
         st.move_limit = 8 * (int64_t)A.g.n + 65536;
+        st.t0 = wall_clock64();
+        st.budget = (uint64_t)A.budget_ticks;
         st.rows = st.row_len = st.inserted = st.written = 0;
 
         // initial community: the seed set, or the members recorded at the
@@ -643,6 +664,8 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
                     st.err |= ERR_LIMIT;
                     break;
                 }
+                if (over_budget(st))
+                    break;
             }
             if (st.ovf || st.err)
                 break;

@@ -35,7 +35,8 @@ class lcd_params(ctypes.Structure):
     _fields_ = [("k_prune", ctypes.c_uint32), ("mode", ctypes.c_int32),
                 ("lds_capacity", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("pool_hint", ctypes.c_int64)]
+                ("pool_hint", ctypes.c_int64), ("watchdog_ms", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class lcd_tier_stats(ctypes.Structure):
@@ -277,7 +278,7 @@ class Result:
 
 def make_params(k_prune: int = 0, mode: int = LCD_PERSISTENT, lds_capacity: int = 0,
                 waves_per_block: int = 0, blocks_per_cu: int = 0, use_graph: int = 0,
-                pool_hint: int = 0) -> lcd_params:
+                pool_hint: int = 0, watchdog_ms: int = 0) -> lcd_params:
     p = lcd_params()
     library().lcd_params_default(ctypes.byref(p))
     p.k_prune = k_prune
@@ -287,6 +288,8 @@ def make_params(k_prune: int = 0, mode: int = LCD_PERSISTENT, lds_capacity: int 
     p.blocks_per_cu = blocks_per_cu
     p.use_graph = use_graph
     p.pool_hint = pool_hint
+    if watchdog_ms:
+        p.watchdog_ms = watchdog_ms
     return p
 
 

@@ -169,3 +169,17 @@ def test_overlap_readout(L):
         ptr[1:] = np.cumsum([len(x) for x in want])
         assert np.array_equal(npt, ptr)
         assert np.array_equal(nst, np.concatenate([np.array(x, np.int32) for x in want]))
+
+
+def test_watchdog_turns_runaway_into_error(L):
+    """With a zero time budget every seed set stops at its first watchdog
+    check: the sweep must come back as an error (and every kernel exit)."""
+    g, sp, sn, scales = W.workload_small()
+    G = L.Graph.from_workload(g)
+    with pytest.raises(L.LcdError) as e:
+        L.lcd_sweep(G, scales, sp, sn, watchdog_ms=-1)
+    assert e.value.status == L.LCD_EDEVICE
+    assert "watchdog" in str(e.value)
+    # the library stays usable afterwards
+    res = L.lcd_sweep(G, scales, sp[:11], sn[:10])
+    assert res.n_sets == 10
