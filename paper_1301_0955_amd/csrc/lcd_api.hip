@@ -176,6 +176,10 @@ namespace {
 // pool cursor, error word, then 5 statistics per tier
 constexpr int kCursorWords = 2 + 5 * 3 + 1;
 
+// global-memory tables of the first spill tier: enough that the sets which
+// outgrow their LDS table in a typical sweep run in one round
+constexpr int32_t kSpillSlots = 4096;
+
 struct TierPlan {
     int32_t cap0, hbits0, wpb0, blocks0;
     bool use1, use2;
@@ -228,7 +232,7 @@ lcd_status plan_tiers(lcd_graph *g, const lcd_params &p, TierPlan &tp, hipStream
     tp.use1 = cap1 > cap && g->n > cap;
     tp.use2 = cap2 > std::max(cap, cap1) && g->n > cap1;
     if (tp.use1)
-        CHK(ensure_slab(g, 0, cap1, 1024, st));
+        CHK(ensure_slab(g, 0, cap1, kSpillSlots, st));
     if (tp.use2) {
         const int64_t tb2 = table_bytes(cap2, next_pow2_bits(2 * (int64_t)cap2));
         int64_t slots = ((int64_t)4 << 30) / tb2;
