@@ -188,6 +188,19 @@ lcd_status lcd_result_overlap(const lcd_result *r, int32_t scale_idx, int32_t *n
 lcd_status lcd_result_counters(const lcd_result *r, uint64_t *totals, uint64_t *per_record,
                                int32_t mem_kind, void *stream);
 
+/*
+ * Every scale of selected seed sets, in host memory.  For the q-th id and
+ * scale s (record o = q * n_scales + s): members[rec_off[o] .. +rec_cnt[o])
+ * ascending, k_in[o], vol[o], f[o], ctr[4*o .. 4*o+4) (G, R, M, C).
+ * members may be NULL to learn *members_needed first; k_in, vol, f, ctr may
+ * be NULL.  LCD_ECAPACITY (with *members_needed set) when members_cap is too
+ * small.  Blocking.
+ */
+lcd_status lcd_result_sets(const lcd_result *r, const int32_t *set_ids, int32_t n_ids,
+                           int64_t *rec_off, int32_t *rec_cnt, int32_t *members, int64_t members_cap,
+                           int64_t *members_needed, int64_t *k_in, int64_t *vol, double *f,
+                           uint64_t *ctr);
+
 lcd_status lcd_result_stats(const lcd_result *r, lcd_sweep_stats *out);
 lcd_status lcd_result_free(lcd_result *r);
 

@@ -878,6 +878,49 @@ lcd_status lcd_result_counters(const lcd_result *r, uint64_t *totals, uint64_t *
     return LCD_OK;
 }
 
+lcd_status lcd_result_sets(const lcd_result *r, const int32_t *set_ids, int32_t n_ids,
+                           int64_t *rec_off, int32_t *rec_cnt, int32_t *members, int64_t members_cap,
+                           int64_t *members_needed, int64_t *k_in, int64_t *vol, double *f,
+                           uint64_t *ctr) {
+    if (!r || (n_ids > 0 && (!set_ids || !rec_off || !rec_cnt || !members_needed)))
+        return fail(LCD_EINVAL, "null argument");
+    const int32_t S = r->S;
+    std::vector<int64_t> off((size_t)S);
+    std::vector<int32_t> cnt((size_t)S);
+    int64_t pos = 0;
+    for (int32_t q = 0; q < n_ids; ++q) {
+        const int32_t j = set_ids[q];
+        if (j < 0 || j >= r->n_sets)
+            return fail(LCD_EINVAL, "set id %d out of range", j);
+        const size_t r0 = (size_t)j * S;
+        HIPCHK(hipMemcpy(off.data(), r->rec.off + r0, sizeof(int64_t) * S, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(cnt.data(), r->rec.cnt + r0, sizeof(int32_t) * S, hipMemcpyDeviceToHost));
+        const size_t o = (size_t)q * S;
+        if (k_in)
+            HIPCHK(hipMemcpy(k_in + o, r->rec.K + r0, sizeof(int64_t) * S, hipMemcpyDeviceToHost));
+        if (vol)
+            HIPCHK(hipMemcpy(vol + o, r->rec.V + r0, sizeof(int64_t) * S, hipMemcpyDeviceToHost));
+        if (f)
+            HIPCHK(hipMemcpy(f + o, r->rec.f + r0, sizeof(double) * S, hipMemcpyDeviceToHost));
+        if (ctr)
+            HIPCHK(hipMemcpy(ctr + 4 * o, r->rec.ctr + 4 * r0, sizeof(uint64_t) * 4 * S,
+                             hipMemcpyDeviceToHost));
+        for (int32_t s = 0; s < S; ++s) {
+            rec_off[o + s] = pos;
+            rec_cnt[o + s] = cnt[s];
+            if (members && pos + cnt[s] <= members_cap && cnt[s] > 0)
+                HIPCHK(hipMemcpy(members + pos, r->pool + off[s], sizeof(int32_t) * (size_t)cnt[s],
+                                 hipMemcpyDeviceToHost));
+            pos += cnt[s];
+        }
+    }
+    *members_needed = pos;
+    if (members && pos > members_cap)
+        return fail(LCD_ECAPACITY, "members buffer holds %lld entries, %lld needed",
+                    (long long)members_cap, (long long)pos);
+    return LCD_OK;
+}
+
 lcd_status lcd_result_stats(const lcd_result *r, lcd_sweep_stats *out) {
     if (!r || !out)
         return fail(LCD_EINVAL, "null argument");

@@ -91,6 +91,8 @@ def library() -> ctypes.CDLL:
         "lcd_result_overlap": (st, [P, ctypes.c_int32, P, P, ctypes.c_int32, P]),
         "lcd_result_counters": (st, [P, P, P, ctypes.c_int32, P]),
         "lcd_result_stats": (st, [P, ctypes.POINTER(lcd_sweep_stats)]),
+        "lcd_result_sets": (st, [P, P, ctypes.c_int32, P, P, P, ctypes.c_int64,
+                                 ctypes.POINTER(ctypes.c_int64), P, P, P, P]),
         "lcd_result_free": (st, [P]),
         "lcd_log_device": (st, [P, P, ctypes.c_int64, P]),
         "lcd_device_info": (st, [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
@@ -258,6 +260,31 @@ class Result:
         if per_record:
             return totals, pr[:self.n_sets * self.n_scales * 4].view(-1, 4)
         return totals
+
+    def sets_to_numpy(self, set_ids) -> dict:
+        """Every scale of the given seed sets, laid out like the oracle's
+        run_sets() output for those sets (record q * S + s)."""
+        ids = np.ascontiguousarray(set_ids, dtype=np.int32)
+        S = self.n_scales
+        R = ids.size * S
+        off = np.zeros(max(R, 1), np.int64)
+        cnt = np.zeros(max(R, 1), np.int32)
+        K = np.zeros(max(R, 1), np.int64)
+        V = np.zeros(max(R, 1), np.int64)
+        f = np.zeros(max(R, 1), np.float64)
+        ctr = np.zeros(max(R, 1) * 4, np.uint64)
+        need = ctypes.c_int64()
+        lib = library()
+        _check(lib.lcd_result_sets(self._h, ids.ctypes.data_as(P), ids.size, off.ctypes.data_as(P),
+                                   cnt.ctypes.data_as(P), None, 0, ctypes.byref(need), None, None,
+                                   None, None), "lcd_result_sets")
+        mem = np.zeros(max(need.value, 1), np.int32)
+        _check(lib.lcd_result_sets(self._h, ids.ctypes.data_as(P), ids.size, off.ctypes.data_as(P),
+                                   cnt.ctypes.data_as(P), mem.ctypes.data_as(P), mem.size,
+                                   ctypes.byref(need), K.ctypes.data_as(P), V.ctypes.data_as(P),
+                                   f.ctypes.data_as(P), ctr.ctypes.data_as(P)), "lcd_result_sets")
+        return dict(members=mem[:need.value], off=off[:R], cnt=cnt[:R], K=K[:R], V=V[:R], f=f[:R],
+                    ctr=ctr[:R * 4].reshape(R, 4), n_sets=ids.size, n_scales=S)
 
     def stats(self) -> dict:
         s = lcd_sweep_stats()

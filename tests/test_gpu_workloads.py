@@ -1,0 +1,90 @@
+"""Parity at the full workload sizes, on seed sets the oracle can afford.
+
+The GPU grows every seed set of the workload in one sweep (the launch the
+benchmark times); the oracle grows a deterministic subsample (every k-th set)
+and every record of those sets must match bit for bit (members, K, V, G, R,
+M, C; f within 1e-12).  Seed sets are independent, so a subsample checks the
+full-size run exactly.  Also: a sweep split at scale j and resumed from its own
+results equals the unsplit sweep."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from _gpu_common import compare_results
+from paper_1301_0955_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1301_0955_amd import lcd
+    lcd.library()
+    return lcd
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _sampled(L, g, sp, sn, scales, stride, **kw):
+    G = L.Graph.from_workload(g)
+    res = L.lcd_sweep(G, scales, sp, sn, **kw)
+    sp2, sn2, ids = W.subsample_sets(sp, sn, stride)
+    got = res.sets_to_numpy(ids)
+    st = res.stats()
+    res.free()
+    ref = oracle.Oracle.from_graph(g).run_sets(sp2, sn2, scales)
+    compare_results(got, ref, label="sampled")
+    return st, ids.size
+
+
+def test_medium_workload_sampled(L):
+    g, sp, sn, scales = W.workload_medium()
+    _say("medium: %d sets x %d scales" % (sp.size - 1, scales.size))
+    st, k = _sampled(L, g, sp, sn, scales, 32)
+    _say("medium: %d sampled sets match; spilled %d" % (k, st["n_spilled"]))
+    assert st["n_spilled"] > 0          # the global-memory tier is exercised too
+
+
+@pytest.mark.parametrize("cap", [256, 2048])
+def test_medium_workload_other_capacities(L, cap):
+    g, sp, sn, scales = W.workload_medium()
+    st, k = _sampled(L, g, sp, sn, scales, 64, lds_capacity=cap)
+    _say("medium cap %d: %d sampled sets match" % (cap, k))
+
+
+def test_large_workload_sampled(L):
+    g, sp, sn, scales = W.workload_large()
+    _say("large: %d sets x %d scales" % (sp.size - 1, scales.size))
+    st, k = _sampled(L, g, sp, sn, scales, 2048)
+    _say("large: %d sampled sets match; %.0f ms device" % (k, st["ms_total"]))
+
+
+def test_resume_equals_full_sweep(L):
+    """sweep(scales[:j]) -> its communities at scale j-1 as initial sets ->
+    sweep(scales[j:]) equals one sweep over all scales (Sec. 2: the result
+    at one scale is the start of the next)."""
+    g, sp, sn, scales = W.workload_small()
+    G = L.Graph.from_workload(g)
+    full = L.sweep_to_numpy(L.lcd_sweep(G, scales, sp, sn))
+    j = 4
+    first = L.lcd_sweep(G, scales[:j], sp, sn)
+    cp, m, _, _, _ = first.membership(j - 1)
+    rest = L.sweep_to_numpy(L.lcd_sweep(G, scales[j:], cp.cpu().numpy(), m.cpu().numpy()))
+    S = scales.size
+    for jj in range(sp.size - 1):
+        for s in range(j, S):
+            r = jj * S + s
+            q = jj * (S - j) + (s - j)
+            a = full["members"][full["off"][r]:full["off"][r] + full["cnt"][r]]
+            b = rest["members"][rest["off"][q]:rest["off"][q] + rest["cnt"][q]]
+            assert np.array_equal(a, b), (jj, s)
+            assert full["K"][r] == rest["K"][q] and full["V"][r] == rest["V"][q]
+            assert np.array_equal(full["ctr"][r], rest["ctr"][q]), (jj, s)
