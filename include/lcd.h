@@ -69,6 +69,7 @@ enum {
 
 typedef struct lcd_graph lcd_graph;
 typedef struct lcd_result lcd_result;
+typedef struct lcd_server lcd_server;
 
 typedef struct {
     uint32_t k_prune;        /* removal passes per growth call; 0 = unbounded */
@@ -203,6 +204,89 @@ lcd_status lcd_result_sets(const lcd_result *r, const int32_t *set_ids, int32_t 
 
 lcd_status lcd_result_stats(const lcd_result *r, lcd_sweep_stats *out);
 lcd_status lcd_result_free(lcd_result *r);
+
+/* ------------------------------------------------------------------------
+ * Query server.  A resident graph answers local-community queries: a query
+ * (S, alpha) starts from the seed set S and applies the growth function of
+ * Algorithm 1 at the single scale alpha until nothing changes (the per-scale
+ * step of Sec. 2 without chaining), with k_prune as in lcd_params.  The
+ * result (members ascending, K, V, f, counters) is exactly that of
+ * lcd_sweep() with n_scales = 1 and the same seed set; it does not depend on
+ * which other queries run at the same time.
+ *
+ * Queries are batched as they arrive: a worker thread owned by the server
+ * admits waiting queries into any idle launch lane (each lane a HIP stream
+ * with its own buffers), limited by max_slots queries in flight and by the
+ * lane's member pool, so batches of several lanes run on the device at once.
+ * ------------------------------------------------------------------------ */
+
+/* Outcome of one query (filled by lcd_server_poll). */
+typedef struct {
+    int32_t n_members;
+    int32_t batch_size;       /* queries in the launch that answered it */
+    int64_t k_in, vol;
+    double f;                 /* K / pow(V, alpha) */
+    uint64_t ctr[4];          /* G, R, M, C */
+    int64_t t_submit_ns;      /* CLOCK_MONOTONIC stamps: submitted, launched, done */
+    int64_t t_start_ns;
+    int64_t t_done_ns;
+    int32_t lane;             /* launch lane (stream) that ran it */
+    int32_t pad;
+} lcd_query_info;
+
+typedef struct {
+    int64_t submitted, completed, failed;
+    int64_t batches;          /* launches of query batches */
+    int64_t requeued;         /* queries run again alone after a pool overflow */
+    int64_t pending;          /* waiting for a lane now */
+    int64_t in_flight;        /* admitted and not finished now */
+    int64_t mem_held;         /* device bytes the server holds */
+    int32_t lanes, max_slots;
+    int32_t max_batch;        /* largest batch launched */
+    int32_t max_lanes_busy;   /* most lanes with a batch on the device at once */
+    int32_t spill_tables[2];  /* global-memory tables per lane, per spill tier */
+} lcd_server_stats;
+
+/*
+ * Create a server on the current device (the graph's device).
+ *   mem_budget  device bytes the server may allocate (0 = 1 GiB); it must
+ *               not exceed the free device memory (LCD_ENOMEM) and must
+ *               cover four lanes that can each hold any single query
+ *   max_slots   queries admitted and unfinished at once (0 = 1024)
+ *   params      k_prune, lds_capacity, waves_per_block, watchdog_ms used;
+ *               NULL for defaults
+ * The graph must outlive the server.
+ */
+lcd_status lcd_server_create(const lcd_graph *g, int64_t mem_budget, int32_t max_slots,
+                             const lcd_params *params, lcd_server **out);
+
+/*
+ * Queue one query: n >= 1 distinct seed ids in [0, n_nodes) in host memory
+ * (copied), alpha finite in [0, 1000].  Returns at once with a ticket.
+ * Thread-safe.
+ */
+lcd_status lcd_server_submit(lcd_server *s, const int32_t *seeds, int32_t n, double alpha,
+                             uint64_t *ticket);
+
+/*
+ * Result of a ticket.  LCD_EAGAIN while it runs.  When done: *info is
+ * filled (if not NULL) and the members are copied to members[0 .. cap);
+ * with cap too small the call returns LCD_ECAPACITY (info->n_members set)
+ * and the ticket stays valid.  LCD_OK and a query's own error status
+ * retire the ticket.  Thread-safe.
+ */
+lcd_status lcd_server_poll(lcd_server *s, uint64_t ticket, int32_t *members, int32_t cap,
+                           lcd_query_info *info);
+
+/* Block until the ticket is done (LCD_OK) or timeout_ms passes (LCD_EAGAIN);
+ * timeout_ms < 0 waits without limit.  Does not retire the ticket. */
+lcd_status lcd_server_wait(lcd_server *s, uint64_t ticket, int32_t timeout_ms);
+
+lcd_status lcd_server_get_stats(lcd_server *s, lcd_server_stats *out);
+
+/* Finish the batches on the device, fail queries still waiting
+ * (LCD_ESTATE), free everything.  Outstanding tickets become invalid. */
+lcd_status lcd_server_destroy(lcd_server *s);
 
 /*
  * The library's integer logarithm L(x) evaluated on the device, for

@@ -12,13 +12,16 @@
 #include <vector>
 
 #include "lcd.h"
+#include "lcd_host.h"
 #include "lcd_internal.h"
 
 using namespace lcd;
 
 namespace {
-
 thread_local std::string t_err;
+}  // namespace
+
+namespace lcd {
 
 lcd_status fail(lcd_status s, const char *fmt, ...) {
     char buf[512];
@@ -29,75 +32,6 @@ lcd_status fail(lcd_status s, const char *fmt, ...) {
     t_err = buf;
     return s;
 }
-
-#define HIPCHK(expr)                                                                        \
-    do {                                                                                    \
-        hipError_t e_ = (expr);                                                             \
-        if (e_ != hipSuccess)                                                               \
-            return fail(LCD_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
-    } while (0)
-
-template <typename T>
-lcd_status dev_alloc(T **p, size_t count) {
-    *p = nullptr;
-    if (count == 0)
-        count = 1;
-    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
-    if (e != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return fail(LCD_ENOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T),
-                    hipGetErrorString(e));
-    }
-    return LCD_OK;
-}
-
-template <typename T>
-void dev_free(T *&p) {
-    if (p)
-        (void)hipFree((void *)p);
-    p = nullptr;
-}
-
-#define CHK(expr)                      \
-    do {                               \
-        lcd_status s_ = (expr);        \
-        if (s_ != LCD_OK)              \
-            return s_;                 \
-    } while (0)
-
-// Copy n elements from caller memory (host or device) to host vector.
-template <typename T>
-lcd_status fetch(std::vector<T> &dst, const T *src, size_t n, int32_t mem_kind, hipStream_t st) {
-    dst.resize(n);
-    if (n == 0)
-        return LCD_OK;
-    if (!src)
-        return fail(LCD_EINVAL, "null input array");
-    if (mem_kind == LCD_MEM_DEVICE) {
-        HIPCHK(hipMemcpyAsync(dst.data(), src, n * sizeof(T), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-    } else {
-        std::memcpy(dst.data(), src, n * sizeof(T));
-    }
-    return LCD_OK;
-}
-
-int next_pow2_bits(int64_t x) {
-    int b = 0;
-    while (((int64_t)1 << b) < x)
-        ++b;
-    return b;
-}
-
-struct DevInfo {
-    int64_t wall_khz = 100000;   // wall_clock64() rate
-    int device = -1;
-    int cus = 0;
-    int64_t lds_cu = 0;
-    int64_t lds_block = 0;
-    char arch[64] = {0};
-};
 
 lcd_status device_info(DevInfo &d) {
     HIPCHK(hipGetDevice(&d.device));
@@ -121,34 +55,100 @@ lcd_status device_info(DevInfo &d) {
     return LCD_OK;
 }
 
-// Global-memory table workspace of one spill tier.
-struct Slab {
-    char *buf = nullptr;
-    int64_t stride = 0;
-    int32_t cap = 0;
-    int32_t hbits = 0;
-    int32_t slots = 0;
-    bool dirty = false;
-};
+lcd_status ensure_slab(Slab &sl, int32_t cap, int32_t slots, hipStream_t st) {
+    const int32_t hbits = next_pow2_bits(2 * (int64_t)cap);
+    const int64_t stride = (table_bytes(cap, hbits) + 255) / 256 * 256;
+    if (sl.buf && sl.cap == cap && sl.slots == slots && !sl.dirty)
+        return LCD_OK;
+    if (!(sl.buf && sl.cap == cap && sl.slots == slots)) {
+        dev_free(sl.buf);
+        CHK(dev_alloc(&sl.buf, (size_t)(stride * slots)));
+    }
+    sl.stride = stride;
+    sl.cap = cap;
+    sl.hbits = hbits;
+    sl.slots = slots;
+    // all-ones bytes: every hash slot empty (-1); other arrays need no init
+    HIPCHK(launch_fill_i32((int32_t *)sl.buf, -1, stride * slots / 4, st));
+    sl.dirty = false;
+    return LCD_OK;
+}
 
-}  // namespace
+lcd_status plan_tiers(const DevInfo &dev, int32_t n, const lcd_params &p, TierPlan &tp) {
+    int32_t cap = p.lds_capacity > 0 ? p.lds_capacity : 1024;
+    if (cap % 64 != 0 || cap < 64 || cap > 8192)
+        return fail(LCD_EINVAL, "lds_capacity must be a multiple of 64 in [64, 8192]");
+    tp.cap0 = cap;
+    tp.hbits0 = next_pow2_bits(2 * (int64_t)cap);
+    const int64_t tb = table_bytes(cap, tp.hbits0);
+    int32_t wpb = p.waves_per_block > 0 ? p.waves_per_block
+                                        : (int32_t)std::max<int64_t>(1, std::min<int64_t>(4, dev.lds_block / tb));
+    if (wpb > 4)
+        return fail(LCD_EINVAL, "waves_per_block must be at most 4");
+    if (wpb * tb > dev.lds_block)
+        return fail(LCD_EINVAL, "LDS table of %lld bytes x %d waves exceeds %lld bytes per block",
+                    (long long)tb, wpb, (long long)dev.lds_block);
+    int32_t bpc = p.blocks_per_cu > 0 ? p.blocks_per_cu
+                                      : (int32_t)std::max<int64_t>(1, dev.lds_cu / (wpb * tb));
+    bpc = std::min(bpc, 32);
+    tp.wpb0 = wpb;
+    tp.blocks0 = dev.cus * bpc;
+    // spill tiers: a 16k-entry tier with many tables, then one that holds
+    // every node of the graph
+    const int64_t need = std::max<int64_t>(64, n);
+    tp.cap1 = (int32_t)std::min<int64_t>(16384, ((int64_t)1 << next_pow2_bits(need)));
+    tp.cap2 = (int32_t)((int64_t)1 << next_pow2_bits(need));
+    tp.use1 = tp.cap1 > cap && n > cap;
+    tp.use2 = tp.cap2 > std::max(cap, tp.cap1) && n > tp.cap1;
+    return LCD_OK;
+}
 
-struct lcd_graph {
-    int32_t n = 0;
-    int64_t nnz = 0;
-    int64_t maxk = 0;
-    int64_t volume = 0;
-    int device = -1;
-    int32_t *row_ptr = nullptr;
-    int32_t *col = nullptr;
-    uint8_t *w = nullptr;
-    int32_t *kdeg = nullptr;
-    double *logtab = nullptr;
-    int32_t logtab_n = 0;
-    DevInfo dev;
-    Slab slab[2];
-    int64_t pool_hint = 0;
-};
+lcd_status enqueue_tiers(const SweepArgs &a0, const TierPlan &tp, int32_t blocks0, Slab *slabs,
+                         int32_t *const work[2], hipStream_t st, hipEvent_t *ev,
+                         int32_t *launches) {
+    SweepArgs a = a0;
+    if (ev)
+        HIPCHK(hipEventRecord(ev[0], st));
+    a.tier = 0;
+    a.in_from = 0;
+    a.work_in = nullptr;
+    a.work_out = tp.use1 ? work[0] : (tp.use2 ? work[1] : nullptr);
+    a.cap = tp.cap0;
+    a.hbits = tp.hbits0;
+    a.gtab = nullptr;
+    a.gtab_stride = 0;
+    a.n_slots = 0;
+    HIPCHK(launch_sweep(a, blocks0, tp.wpb0, st));
+    *launches += 1;
+    if (ev)
+        HIPCHK(hipEventRecord(ev[1], st));
+    // spill tiers read their item count from the tier that pushed to them
+    int from = 0;
+    for (int k = 0; k < 2; ++k) {
+        const bool use = k == 0 ? tp.use1 : tp.use2;
+        if (!use)
+            continue;
+        const Slab &sl = slabs[k];
+        SweepArgs b = a;
+        b.tier = k + 1;
+        b.in_from = from;
+        b.work_in = work[k];
+        b.work_out = (k == 0 && tp.use2) ? work[1] : nullptr;
+        b.cap = sl.cap;
+        b.hbits = sl.hbits;
+        b.gtab = sl.buf;
+        b.gtab_stride = sl.stride;
+        b.n_slots = sl.slots;
+        HIPCHK(launch_sweep(b, (sl.slots + 3) / 4, 4, st));
+        *launches += 1;
+        from = k + 1;
+    }
+    if (ev)
+        HIPCHK(hipEventRecord(ev[2], st));
+    return LCD_OK;
+}
+
+}  // namespace lcd
 
 struct lcd_result {
     const lcd_graph *g = nullptr;
@@ -173,71 +173,18 @@ struct lcd_result {
 
 namespace {
 
-// pool cursor, error word, then 5 statistics per tier
-constexpr int kCursorWords = 2 + 5 * 3 + 1;
-
 // global-memory tables of the first spill tier: enough that the sets which
 // outgrow their LDS table in a typical sweep run in one round
 constexpr int32_t kSpillSlots = 4096;
 
-struct TierPlan {
-    int32_t cap0, hbits0, wpb0, blocks0;
-    bool use1, use2;
-};
-
-lcd_status ensure_slab(lcd_graph *g, int which, int32_t cap, int32_t slots, hipStream_t st) {
-    Slab &sl = g->slab[which];
-    const int32_t hbits = next_pow2_bits(2 * (int64_t)cap);
-    const int64_t stride = (table_bytes(cap, hbits) + 255) / 256 * 256;
-    if (sl.buf && sl.cap == cap && sl.slots == slots && !sl.dirty)
-        return LCD_OK;
-    if (!(sl.buf && sl.cap == cap && sl.slots == slots)) {
-        dev_free(sl.buf);
-        CHK(dev_alloc(&sl.buf, (size_t)(stride * slots)));
-    }
-    sl.stride = stride;
-    sl.cap = cap;
-    sl.hbits = hbits;
-    sl.slots = slots;
-    // all-ones bytes: every hash slot empty (-1); other arrays need no init
-    HIPCHK(launch_fill_i32((int32_t *)sl.buf, -1, stride * slots / 4, st));
-    sl.dirty = false;
-    return LCD_OK;
-}
-
-lcd_status plan_tiers(lcd_graph *g, const lcd_params &p, TierPlan &tp, hipStream_t st) {
-    int32_t cap = p.lds_capacity > 0 ? p.lds_capacity : 1024;
-    if (cap % 64 != 0 || cap < 64 || cap > 8192)
-        return fail(LCD_EINVAL, "lds_capacity must be a multiple of 64 in [64, 8192]");
-    tp.cap0 = cap;
-    tp.hbits0 = next_pow2_bits(2 * (int64_t)cap);
-    const int64_t tb = table_bytes(cap, tp.hbits0);
-    int32_t wpb = p.waves_per_block > 0 ? p.waves_per_block
-                                        : (int32_t)std::max<int64_t>(1, std::min<int64_t>(4, g->dev.lds_block / tb));
-    if (wpb > 4)
-        return fail(LCD_EINVAL, "waves_per_block must be at most 4");
-    if (wpb * tb > g->dev.lds_block)
-        return fail(LCD_EINVAL, "LDS table of %lld bytes x %d waves exceeds %lld bytes per block",
-                    (long long)tb, wpb, (long long)g->dev.lds_block);
-    int32_t bpc = p.blocks_per_cu > 0 ? p.blocks_per_cu
-                                      : (int32_t)std::max<int64_t>(1, g->dev.lds_cu / (wpb * tb));
-    bpc = std::min(bpc, 32);
-    tp.wpb0 = wpb;
-    tp.blocks0 = g->dev.cus * bpc;
-    // spill tiers: a 16k-entry tier with many tables, then one that holds
-    // every node of the graph
-    const int64_t need = std::max<int64_t>(64, g->n);
-    const int32_t cap1 = (int32_t)std::min<int64_t>(16384, ((int64_t)1 << next_pow2_bits(need)));
-    const int32_t cap2 = (int32_t)((int64_t)1 << next_pow2_bits(need));
-    tp.use1 = cap1 > cap && g->n > cap;
-    tp.use2 = cap2 > std::max(cap, cap1) && g->n > cap1;
+lcd_status prepare_slabs(lcd_graph *g, const TierPlan &tp, hipStream_t st) {
     if (tp.use1)
-        CHK(ensure_slab(g, 0, cap1, kSpillSlots, st));
+        CHK(ensure_slab(g->slab[0], tp.cap1, kSpillSlots, st));
     if (tp.use2) {
-        const int64_t tb2 = table_bytes(cap2, next_pow2_bits(2 * (int64_t)cap2));
+        const int64_t tb2 = table_bytes(tp.cap2, next_pow2_bits(2 * (int64_t)tp.cap2));
         int64_t slots = ((int64_t)4 << 30) / tb2;
         slots = std::max<int64_t>(4, std::min<int64_t>(256, slots));
-        CHK(ensure_slab(g, 1, cap2, (int32_t)slots, st));
+        CHK(ensure_slab(g->slab[1], tp.cap2, (int32_t)slots, st));
     }
     return LCD_OK;
 }
@@ -246,14 +193,9 @@ lcd_status run_group(lcd_result *r, const TierPlan &tp, int32_t s_begin, int32_t
                      hipStream_t st, hipEvent_t *ev) {
     lcd_graph *g = const_cast<lcd_graph *>(r->g);
     SweepArgs a{};
-    a.g.row_ptr = g->row_ptr;
-    a.g.col = g->col;
-    a.g.w = g->w;
-    a.g.kdeg = g->kdeg;
-    a.g.logtab = g->logtab;
-    a.g.n = g->n;
-    a.g.logtab_n = g->logtab_n;
+    a.g = graph_dev(g);
     a.scales = r->scales;
+    a.alpha_set = nullptr;
     a.S = r->S;
     a.s_begin = s_begin;
     a.s_end = s_end;
@@ -270,51 +212,14 @@ lcd_status run_group(lcd_result *r, const TierPlan &tp, int32_t s_begin, int32_t
     a.err = r->err;
     a.budget_ticks = r->prm.watchdog_ms < 0 ? 0 : g->dev.wall_khz * (int64_t)r->prm.watchdog_ms;
     a.stat = r->cursor + 2;
-
-    if (ev)
-        HIPCHK(hipEventRecord(ev[0], st));
-    a.tier = 0;
-    a.work_in = nullptr;
-    a.work_out = tp.use1 ? r->work[0] : (tp.use2 ? r->work[1] : nullptr);
-    a.cap = tp.cap0;
-    a.hbits = tp.hbits0;
-    a.gtab = nullptr;
-    a.gtab_stride = 0;
-    a.n_slots = 0;
-    HIPCHK(launch_sweep(a, tp.blocks0, tp.wpb0, st));
-    r->stats.launches += 1;
-    if (ev)
-        HIPCHK(hipEventRecord(ev[1], st));
-    // spill tiers read their item count from the tier that pushed to them
-    int from = 0;
-    for (int k = 0; k < 2; ++k) {
-        const bool use = k == 0 ? tp.use1 : tp.use2;
-        if (!use)
-            continue;
-        Slab &sl = g->slab[k];
-        SweepArgs b = a;
-        b.tier = k + 1;
-        b.in_from = from;
-        b.work_in = r->work[k];
-        b.work_out = (k == 0 && tp.use2) ? r->work[1] : nullptr;
-        b.cap = sl.cap;
-        b.hbits = sl.hbits;
-        b.gtab = sl.buf;
-        b.gtab_stride = sl.stride;
-        b.n_slots = sl.slots;
-        HIPCHK(launch_sweep(b, (sl.slots + 3) / 4, 4, st));
-        r->stats.launches += 1;
-        from = k + 1;
-    }
-    if (ev)
-        HIPCHK(hipEventRecord(ev[2], st));
-    return LCD_OK;
+    return enqueue_tiers(a, tp, tp.blocks0, g->slab, r->work, st, ev, &r->stats.launches);
 }
 
 lcd_status run_sweep(lcd_result *r, hipStream_t st) {
     lcd_graph *g = const_cast<lcd_graph *>(r->g);
     TierPlan tp;
-    CHK(plan_tiers(g, r->prm, tp, st));
+    CHK(plan_tiers(g->dev, g->n, r->prm, tp));
+    CHK(prepare_slabs(g, tp, st));
     r->stats = lcd_sweep_stats{};
     r->stats.lds_capacity = tp.cap0;
     r->stats.waves_per_block = tp.wpb0;

@@ -72,6 +72,7 @@ struct SweepArgs {
     int64_t gtab_stride;      // bytes per table
     int32_t n_slots;          // global tiers: number of tables
     int64_t budget_ticks;     // watchdog: wall-clock ticks one seed set may take
+    const double *alpha_set;  // query kernels: one scale per set (S = 1); nullptr for sweeps
 };
 
 // Bytes per table entry (dense arrays + scratch) and per hash slot.

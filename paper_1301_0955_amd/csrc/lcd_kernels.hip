@@ -560,7 +560,9 @@ __device__ void wave_sort(int32_t *a, int32_t m, int lane) {
     }
 }
 
-template <bool GLOBAL>
+// PERSET: each set carries its own scale (query batches, one record per
+// set); otherwise every set runs through scales[s_begin, s_end).
+template <bool GLOBAL, bool PERSET>
 __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
     Ctx c;
     c.row_ptr = A.g.row_ptr;
@@ -646,7 +648,10 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
         int64_t last_off = -1;
         int32_t last_cnt = 0;
         for (int32_t s = A.s_begin; s < A.s_end && !st.ovf && !bad && !st.err; ++s) {
-            st.alpha = A.scales[s];
+            if constexpr (PERSET)
+                st.alpha = A.alpha_set[set];
+            else
+                st.alpha = A.scales[s];
             set_logs(st);
             st.Gl = st.Rl = 0;
             st.Gu = 0;
@@ -754,7 +759,7 @@ __global__ void __launch_bounds__(256) sweep_lds_kernel(SweepArgs A) {
     const int lane = threadIdx.x & 63;
     const int64_t tb = table_bytes(A.cap, A.hbits);
     Tab t = carve(smem + wave * tb, A.cap, A.hbits);
-    run_wave<false>(A, t, lane);
+    run_wave<false, false>(A, t, lane);
 }
 
 __global__ void __launch_bounds__(256) sweep_global_kernel(SweepArgs A) {
@@ -764,7 +769,27 @@ __global__ void __launch_bounds__(256) sweep_global_kernel(SweepArgs A) {
     if (slot >= A.n_slots)
         return;
     Tab t = carve(A.gtab + (int64_t)slot * A.gtab_stride, A.cap, A.hbits);
-    run_wave<true>(A, t, lane);
+    run_wave<true, false>(A, t, lane);
+}
+
+// The same growth for query batches: set j grows once at alpha_set[j].
+__global__ void __launch_bounds__(256) query_lds_kernel(SweepArgs A) {
+    extern __shared__ __align__(16) char smem[];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t tb = table_bytes(A.cap, A.hbits);
+    Tab t = carve(smem + wave * tb, A.cap, A.hbits);
+    run_wave<false, true>(A, t, lane);
+}
+
+__global__ void __launch_bounds__(256) query_global_kernel(SweepArgs A) {
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int slot = blockIdx.x * (blockDim.x >> 6) + wave;
+    if (slot >= A.n_slots)
+        return;
+    Tab t = carve(A.gtab + (int64_t)slot * A.gtab_stride, A.cap, A.hbits);
+    run_wave<true, true>(A, t, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -1042,11 +1067,16 @@ hipError_t launch_zero_bytes(void *p, int64_t bytes, hipStream_t st) {
 hipError_t launch_sweep(const SweepArgs &a, int32_t blocks, int32_t waves_per_block, hipStream_t st) {
     if (blocks <= 0)
         return hipSuccess;
+    const bool q = a.alpha_set != nullptr;
+    if (q && (a.S != 1 || a.s_begin != 0 || a.s_end != 1 || a.resume))
+        return hipErrorInvalidValue;
     if (a.tier == 0) {
         const size_t smem = (size_t)waves_per_block * (size_t)table_bytes(a.cap, a.hbits);
-        hipLaunchKernelGGL(sweep_lds_kernel, dim3(blocks), dim3(64 * waves_per_block), smem, st, a);
+        hipLaunchKernelGGL(q ? query_lds_kernel : sweep_lds_kernel, dim3(blocks),
+                           dim3(64 * waves_per_block), smem, st, a);
     } else {
-        hipLaunchKernelGGL(sweep_global_kernel, dim3(blocks), dim3(64 * waves_per_block), 0, st, a);
+        hipLaunchKernelGGL(q ? query_global_kernel : sweep_global_kernel, dim3(blocks),
+                           dim3(64 * waves_per_block), 0, st, a);
     }
     return hipGetLastError();
 }

@@ -1,0 +1,663 @@
+// Local-community query server: a resident graph answers (seed set, scale)
+// queries (growth to a fixpoint at one scale, the per-scale step of the
+// method in Sec. 2 and Algorithm 1, without chaining).
+//
+// Continuous batching over a small number of launch lanes.  Each lane owns
+// a HIP stream, device buffers for one batch (seeds, scales, records, member
+// pool, spill-tier tables) and pinned host staging.  One worker thread
+//   * retires lanes whose batch finished (records and member lists back to
+//     the host, tickets completed),
+//   * admits pending queries into every idle lane at once, as many as the
+//     lane's memory, the batch limit and the free query slots allow, and
+//     launches the batch on that lane's stream,
+// so queries that arrive while others run start in another lane without
+// waiting for them, and batches of different lanes overlap on the device.
+// A query's result does not depend on its batch: every set is grown by its
+// own wavefront from its own seeds, and the kernels are the sweep kernels
+// with a per-set scale.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "lcd.h"
+#include "lcd_host.h"
+#include "lcd_internal.h"
+
+using namespace lcd;
+
+namespace {
+
+int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+struct Query {
+    uint64_t ticket = 0;
+    std::vector<int32_t> seeds;
+    double alpha = 0.0;
+    int64_t reserve = 0;        // member-pool entries reserved at admission
+    bool solo = false;          // rerun alone after its batch's pool overflowed
+    bool done = false;
+    lcd_status status = LCD_EAGAIN;
+    std::string msg;
+    std::vector<int32_t> members;
+    lcd_query_info info{};
+};
+
+template <typename T>
+lcd_status host_alloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0)
+        count = 1;
+    hipError_t e = hipHostMalloc((void **)p, count * sizeof(T), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(LCD_ENOMEM, "hipHostMalloc of %zu bytes failed", count * sizeof(T));
+    }
+    return LCD_OK;
+}
+
+template <typename T>
+void host_free(T *&p) {
+    if (p)
+        (void)hipHostFree((void *)p);
+    p = nullptr;
+}
+
+struct Lane {
+    int id = 0;
+    hipStream_t st = nullptr;
+    hipEvent_t done = nullptr;
+    int32_t max_q = 0;
+    int64_t max_seed = 0;
+    int64_t pool_cap = 0;
+    // device
+    double *alpha = nullptr;
+    int32_t *seed_ptr = nullptr;
+    int32_t *seed_nodes = nullptr;
+    Records rec{};
+    int32_t *pool = nullptr;
+    Counters *ctl = nullptr;
+    unsigned long long *cursor = nullptr;
+    int32_t *work[2] = {nullptr, nullptr};
+    Slab slab[2];
+    // pinned host staging
+    double *h_alpha = nullptr;
+    int32_t *h_seed_ptr = nullptr;
+    int32_t *h_seed_nodes = nullptr;
+    int64_t *h_off = nullptr;
+    int32_t *h_cnt = nullptr;
+    int64_t *h_K = nullptr;
+    int64_t *h_V = nullptr;
+    double *h_f = nullptr;
+    uint64_t *h_ctr = nullptr;
+    unsigned long long *h_cursor = nullptr;
+    int32_t *h_pool = nullptr;
+    // batch in flight
+    std::vector<Query *> batch;
+    bool busy = false;
+    int64_t t_start = 0;
+};
+
+void lane_release(Lane &L) {
+    dev_free(L.alpha);
+    dev_free(L.seed_ptr);
+    dev_free(L.seed_nodes);
+    dev_free(L.rec.off);
+    dev_free(L.rec.cnt);
+    dev_free(L.rec.K);
+    dev_free(L.rec.V);
+    dev_free(L.rec.f);
+    dev_free(L.rec.ctr);
+    dev_free(L.pool);
+    dev_free(L.ctl);
+    dev_free(L.cursor);
+    dev_free(L.work[0]);
+    dev_free(L.work[1]);
+    dev_free(L.slab[0].buf);
+    dev_free(L.slab[1].buf);
+    host_free(L.h_alpha);
+    host_free(L.h_seed_ptr);
+    host_free(L.h_seed_nodes);
+    host_free(L.h_off);
+    host_free(L.h_cnt);
+    host_free(L.h_K);
+    host_free(L.h_V);
+    host_free(L.h_f);
+    host_free(L.h_ctr);
+    host_free(L.h_cursor);
+    host_free(L.h_pool);
+    if (L.done)
+        (void)hipEventDestroy(L.done);
+    if (L.st)
+        (void)hipStreamDestroy(L.st);
+    L.done = nullptr;
+    L.st = nullptr;
+}
+
+// Device bytes of one lane's buffers (without the spill tables).
+int64_t lane_bytes(int32_t max_q, int64_t max_seed, int64_t pool_cap) {
+    return (int64_t)max_q * (8 + 4 + 8 + 4 + 8 + 8 + 8 + 32 + 8) + max_seed * 4 + pool_cap * 4 +
+           8 * kCursorWords + (int64_t)sizeof(Counters) + 256 * 16;
+}
+
+}  // namespace
+
+struct lcd_server {
+    const lcd_graph *g = nullptr;
+    lcd_params prm{};
+    TierPlan tp{};
+    int32_t max_slots = 0;
+    int64_t mem_budget = 0;
+    int64_t mem_held = 0;
+    std::vector<Lane> lanes;
+    std::mutex mu;
+    std::condition_variable cv_work;
+    std::condition_variable cv_done;
+    std::deque<Query *> pending;
+    std::unordered_map<uint64_t, Query *> tickets;
+    uint64_t next_ticket = 1;
+    int64_t in_flight = 0;
+    bool stop = false;
+    std::thread worker;
+    lcd_server_stats stats{};
+};
+
+namespace {
+
+// Launch the batch already placed in L.batch; called without the lock.
+lcd_status launch_lane(lcd_server *S, Lane &L) {
+    const lcd_graph *g = S->g;
+    const int32_t nq = (int32_t)L.batch.size();
+    int64_t pos = 0;
+    for (int32_t i = 0; i < nq; ++i) {
+        const Query *q = L.batch[i];
+        L.h_alpha[i] = q->alpha;
+        L.h_seed_ptr[i] = (int32_t)pos;
+        std::memcpy(L.h_seed_nodes + pos, q->seeds.data(), sizeof(int32_t) * q->seeds.size());
+        pos += (int64_t)q->seeds.size();
+    }
+    L.h_seed_ptr[nq] = (int32_t)pos;
+    hipStream_t st = L.st;
+    HIPCHK(hipMemcpyAsync(L.alpha, L.h_alpha, sizeof(double) * nq, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(L.seed_ptr, L.h_seed_ptr, sizeof(int32_t) * (nq + 1), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(L.seed_nodes, L.h_seed_nodes, sizeof(int32_t) * pos, hipMemcpyHostToDevice, st));
+    HIPCHK(launch_zero_bytes(L.ctl, (int64_t)sizeof(Counters), st));
+    HIPCHK(launch_zero_bytes(L.cursor, 8 * kCursorWords, st));
+    if (S->tp.use1)
+        CHK(ensure_slab(L.slab[0], L.slab[0].cap, L.slab[0].slots, st));
+    if (S->tp.use2)
+        CHK(ensure_slab(L.slab[1], L.slab[1].cap, L.slab[1].slots, st));
+    SweepArgs a{};
+    a.g = graph_dev(g);
+    a.scales = L.alpha;
+    a.alpha_set = L.alpha;
+    a.S = 1;
+    a.s_begin = 0;
+    a.s_end = 1;
+    a.seed_ptr = L.seed_ptr;
+    a.seed_nodes = L.seed_nodes;
+    a.n_sets = nq;
+    a.k_prune = S->prm.k_prune;
+    a.resume = 0;
+    a.rec = L.rec;
+    a.pool = L.pool;
+    a.pool_cap = L.pool_cap;
+    a.ctl = L.ctl;
+    a.pool_cursor = L.cursor;
+    a.err = (uint32_t *)(L.cursor + 1);
+    a.stat = L.cursor + 2;
+    a.budget_ticks = S->prm.watchdog_ms < 0 ? 0 : g->dev.wall_khz * (int64_t)S->prm.watchdog_ms;
+    const int32_t blocks0 = std::min<int32_t>(S->tp.blocks0, (nq + S->tp.wpb0 - 1) / S->tp.wpb0);
+    int32_t launches = 0;
+    CHK(enqueue_tiers(a, S->tp, blocks0, L.slab, L.work, st, nullptr, &launches));
+    HIPCHK(hipMemcpyAsync(L.h_off, L.rec.off, sizeof(int64_t) * nq, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(L.h_cnt, L.rec.cnt, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(L.h_K, L.rec.K, sizeof(int64_t) * nq, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(L.h_V, L.rec.V, sizeof(int64_t) * nq, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(L.h_f, L.rec.f, sizeof(double) * nq, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(L.h_ctr, L.rec.ctr, sizeof(uint64_t) * 4 * nq, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(L.h_cursor, L.cursor, 8 * kCursorWords, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(L.done, st));
+    return LCD_OK;
+}
+
+// The lane's batch has finished on the device: fetch member lists and fill
+// the queries.  Called without the lock; returns the queries to run again.
+lcd_status collect_lane(lcd_server *S, Lane &L, std::vector<Query *> &again) {
+    const int32_t nq = (int32_t)L.batch.size();
+    const uint32_t err = (uint32_t)(L.h_cursor[1] & 0xffffffffu);
+    if (err) {
+        L.slab[0].dirty = L.slab[1].dirty = true;
+        return fail(err & ERR_CAPACITY ? LCD_ECAPACITY : LCD_EDEVICE,
+                    "query kernel reported error bits 0x%x%s", err,
+                    err & ERR_TIMEOUT ? " (watchdog: a query ran past its time budget)" : "");
+    }
+    const int64_t used = std::min<int64_t>((int64_t)L.h_cursor[0], L.pool_cap);
+    if (used > 0) {
+        HIPCHK(hipMemcpyAsync(L.h_pool, L.pool, sizeof(int32_t) * used, hipMemcpyDeviceToHost, L.st));
+        HIPCHK(hipStreamSynchronize(L.st));
+    }
+    const int64_t t_done = now_ns();
+    for (int32_t i = 0; i < nq; ++i) {
+        Query *q = L.batch[i];
+        const int64_t off = L.h_off[i];
+        const int32_t cnt = L.h_cnt[i];
+        if (off < 0 || off + cnt > L.pool_cap) {
+            // the batch outgrew the lane's pool: this query runs again alone
+            q->solo = true;
+            q->reserve = L.pool_cap;
+            again.push_back(q);
+            continue;
+        }
+        q->members.assign(L.h_pool + off, L.h_pool + off + cnt);
+        q->info.n_members = cnt;
+        q->info.k_in = L.h_K[i];
+        q->info.vol = L.h_V[i];
+        q->info.f = L.h_f[i];
+        for (int c = 0; c < 4; ++c)
+            q->info.ctr[c] = L.h_ctr[4 * i + c];
+        q->info.t_start_ns = L.t_start;
+        q->info.t_done_ns = t_done;
+        q->info.batch_size = nq;
+        q->info.lane = L.id;
+        q->status = LCD_OK;
+    }
+    return LCD_OK;
+}
+
+void worker_main(lcd_server *S) {
+    (void)hipSetDevice(S->g->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        bool progress = false;
+        // 1. retire finished lanes
+        for (Lane &L : S->lanes) {
+            if (!L.busy)
+                continue;
+            lk.unlock();
+            const hipError_t q = hipEventQuery(L.done);
+            std::vector<Query *> again;
+            lcd_status s = LCD_OK;
+            std::string msg;
+            bool finished = false;
+            if (q == hipSuccess) {
+                s = collect_lane(S, L, again);
+                finished = true;
+            } else if (q != hipErrorNotReady) {
+                s = fail(LCD_EDEVICE, "query batch failed: %s", hipGetErrorString(q));
+                finished = true;
+            }
+            if (s != LCD_OK)
+                msg = lcd_last_error();
+            lk.lock();
+            if (!finished)
+                continue;
+            progress = true;
+            for (Query *qq : L.batch) {
+                bool rerun = false;
+                for (Query *a : again)
+                    rerun |= a == qq;
+                if (rerun)
+                    continue;
+                if (s != LCD_OK) {
+                    qq->status = s;
+                    qq->msg = msg;
+                    S->stats.failed += 1;
+                } else {
+                    S->stats.completed += 1;
+                }
+                qq->done = true;
+            }
+            for (auto it = again.rbegin(); it != again.rend(); ++it)
+                S->pending.push_front(*it);
+            S->stats.requeued += (int64_t)again.size();
+            S->in_flight -= (int64_t)L.batch.size();
+            L.batch.clear();
+            L.busy = false;
+            S->cv_done.notify_all();
+        }
+        if (S->stop) {
+            bool any = false;
+            for (Lane &L : S->lanes)
+                any |= L.busy;
+            if (!any)
+                break;
+        }
+        // 2. admit pending queries into idle lanes
+        for (Lane &L : S->lanes) {
+            if (S->stop || L.busy || S->pending.empty() || S->in_flight >= S->max_slots)
+                continue;
+            int64_t seeds = 0, reserved = 0;
+            while (!S->pending.empty() && (int32_t)L.batch.size() < L.max_q &&
+                   S->in_flight + (int64_t)L.batch.size() < S->max_slots) {
+                Query *q = S->pending.front();
+                const int64_t ns = (int64_t)q->seeds.size();
+                if (!L.batch.empty() && (q->solo || seeds + ns > L.max_seed ||
+                                         reserved + q->reserve > L.pool_cap))
+                    break;
+                S->pending.pop_front();
+                L.batch.push_back(q);
+                seeds += ns;
+                reserved += q->reserve;
+                if (q->solo)
+                    break;
+            }
+            if (L.batch.empty())
+                continue;
+            L.busy = true;
+            S->in_flight += (int64_t)L.batch.size();
+            S->stats.batches += 1;
+            S->stats.max_batch = std::max<int32_t>(S->stats.max_batch, (int32_t)L.batch.size());
+            int32_t nbusy = 0;
+            for (Lane &M : S->lanes)
+                nbusy += M.busy ? 1 : 0;
+            S->stats.max_lanes_busy = std::max(S->stats.max_lanes_busy, nbusy);
+            L.t_start = now_ns();
+            lk.unlock();
+            const lcd_status s = launch_lane(S, L);
+            std::string msg = s != LCD_OK ? std::string(lcd_last_error()) : std::string();
+            lk.lock();
+            progress = true;
+            if (s != LCD_OK) {
+                // nothing was left running that the event does not cover:
+                // wait for the stream, then fail the batch
+                lk.unlock();
+                (void)hipStreamSynchronize(L.st);
+                lk.lock();
+                L.slab[0].dirty = L.slab[1].dirty = true;
+                for (Query *qq : L.batch) {
+                    qq->status = s;
+                    qq->msg = msg;
+                    qq->done = true;
+                    S->stats.failed += 1;
+                }
+                S->in_flight -= (int64_t)L.batch.size();
+                L.batch.clear();
+                L.busy = false;
+                S->cv_done.notify_all();
+            }
+        }
+        if (progress)
+            continue;
+        bool any = false;
+        for (Lane &L : S->lanes)
+            any |= L.busy;
+        if (any)
+            S->cv_work.wait_for(lk, std::chrono::microseconds(20));
+        else
+            S->cv_work.wait(lk, [S] { return S->stop || !S->pending.empty(); });
+    }
+    // fail whatever is still queued
+    for (Query *q : S->pending) {
+        q->status = LCD_ESTATE;
+        q->msg = "server destroyed";
+        q->done = true;
+    }
+    S->pending.clear();
+    S->cv_done.notify_all();
+}
+
+lcd_status lane_init(lcd_server *S, Lane &L, int id, int32_t max_q, int64_t max_seed,
+                     int64_t pool_cap, int32_t slots1, int32_t slots2) {
+    L.id = id;
+    L.max_q = max_q;
+    L.max_seed = max_seed;
+    L.pool_cap = pool_cap;
+    HIPCHK(hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&L.done, hipEventDisableTiming));
+    CHK(dev_alloc(&L.alpha, max_q));
+    CHK(dev_alloc(&L.seed_ptr, (size_t)max_q + 1));
+    CHK(dev_alloc(&L.seed_nodes, (size_t)max_seed));
+    CHK(dev_alloc(&L.rec.off, max_q));
+    CHK(dev_alloc(&L.rec.cnt, max_q));
+    CHK(dev_alloc(&L.rec.K, max_q));
+    CHK(dev_alloc(&L.rec.V, max_q));
+    CHK(dev_alloc(&L.rec.f, max_q));
+    CHK(dev_alloc(&L.rec.ctr, 4 * (size_t)max_q));
+    CHK(dev_alloc(&L.pool, (size_t)pool_cap));
+    CHK(dev_alloc(&L.ctl, 1));
+    CHK(dev_alloc(&L.cursor, kCursorWords));
+    CHK(dev_alloc(&L.work[0], max_q));
+    CHK(dev_alloc(&L.work[1], max_q));
+    CHK(host_alloc(&L.h_alpha, max_q));
+    CHK(host_alloc(&L.h_seed_ptr, (size_t)max_q + 1));
+    CHK(host_alloc(&L.h_seed_nodes, (size_t)max_seed));
+    CHK(host_alloc(&L.h_off, max_q));
+    CHK(host_alloc(&L.h_cnt, max_q));
+    CHK(host_alloc(&L.h_K, max_q));
+    CHK(host_alloc(&L.h_V, max_q));
+    CHK(host_alloc(&L.h_f, max_q));
+    CHK(host_alloc(&L.h_ctr, 4 * (size_t)max_q));
+    CHK(host_alloc(&L.h_cursor, kCursorWords));
+    CHK(host_alloc(&L.h_pool, (size_t)pool_cap));
+    if (S->tp.use1)
+        CHK(ensure_slab(L.slab[0], S->tp.cap1, slots1, L.st));
+    if (S->tp.use2)
+        CHK(ensure_slab(L.slab[1], S->tp.cap2, slots2, L.st));
+    HIPCHK(hipStreamSynchronize(L.st));
+    return LCD_OK;
+}
+
+void server_release(lcd_server *S) {
+    for (Lane &L : S->lanes)
+        lane_release(L);
+    for (auto &kv : S->tickets)
+        delete kv.second;
+    delete S;
+}
+
+}  // namespace
+
+extern "C" {
+
+lcd_status lcd_server_create(const lcd_graph *g, int64_t mem_budget, int32_t max_slots,
+                             const lcd_params *params, lcd_server **out) {
+    if (!out)
+        return fail(LCD_EINVAL, "out is null");
+    *out = nullptr;
+    if (!g)
+        return fail(LCD_EINVAL, "null graph");
+    if (mem_budget < 0 || max_slots < 0)
+        return fail(LCD_EINVAL, "mem_budget and max_slots must be >= 0");
+    lcd_params prm;
+    lcd_params_default(&prm);
+    if (params)
+        prm = *params;
+    if (prm.watchdog_ms == 0)
+        prm.watchdog_ms = 20000;
+    if (mem_budget == 0)
+        mem_budget = (int64_t)1 << 30;
+    if (max_slots == 0)
+        max_slots = 1024;
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != g->device)
+        return fail(LCD_EINVAL, "the graph lives on device %d, the current device is %d", g->device, dev);
+    size_t free_b = 0, total_b = 0;
+    HIPCHK(hipMemGetInfo(&free_b, &total_b));
+    if ((int64_t)free_b < mem_budget)
+        return fail(LCD_ENOMEM, "mem_budget %lld exceeds the free device memory %lld",
+                    (long long)mem_budget, (long long)free_b);
+    lcd_server *S = new (std::nothrow) lcd_server();
+    if (!S)
+        return fail(LCD_ENOMEM, "host allocation failed");
+    S->g = g;
+    S->prm = prm;
+    S->max_slots = max_slots;
+    S->mem_budget = mem_budget;
+    lcd_status s = plan_tiers(g->dev, g->n, prm, S->tp);
+    if (s != LCD_OK) {
+        delete S;
+        return s;
+    }
+    // lanes and their sizes from the budget: every lane can hold any single
+    // query (pool >= n, one table of each spill tier)
+    const int n_lanes = 4;
+    const int32_t max_q = std::max<int32_t>(1, std::min<int32_t>(256, max_slots));
+    const int64_t max_seed = std::max<int64_t>(65536, (int64_t)g->n);
+    const int64_t pool_cap = std::max<int64_t>((int64_t)g->n, 1 << 20);
+    const int64_t tb1 = S->tp.use1 ? (table_bytes(S->tp.cap1, next_pow2_bits(2 * (int64_t)S->tp.cap1)) + 255) / 256 * 256 : 0;
+    const int64_t tb2 = S->tp.use2 ? (table_bytes(S->tp.cap2, next_pow2_bits(2 * (int64_t)S->tp.cap2)) + 255) / 256 * 256 : 0;
+    const int64_t fixed = lane_bytes(max_q, max_seed, pool_cap);
+    const int64_t per_lane = mem_budget / n_lanes;
+    const int64_t left = per_lane - fixed - tb1 - tb2;
+    if (left < 0) {
+        delete S;
+        return fail(LCD_ENOMEM, "mem_budget %lld is below the %lld bytes four lanes need on this graph",
+                    (long long)mem_budget, (long long)(n_lanes * (fixed + tb1 + tb2)));
+    }
+    // spend what is left on more spill tables: first tier, then the largest
+    int32_t slots1 = S->tp.use1 ? (int32_t)std::min<int64_t>(256, 1 + (left / 2) / std::max<int64_t>(tb1, 1)) : 0;
+    int64_t left2 = left - (S->tp.use1 ? (slots1 - 1) * tb1 : 0);
+    int32_t slots2 = S->tp.use2 ? (int32_t)std::min<int64_t>(8, 1 + left2 / std::max<int64_t>(tb2, 1)) : 0;
+    S->lanes.resize(n_lanes);
+    for (int i = 0; i < n_lanes; ++i) {
+        s = lane_init(S, S->lanes[i], i, max_q, max_seed, pool_cap, slots1, slots2);
+        if (s != LCD_OK) {
+            server_release(S);
+            return s;
+        }
+    }
+    S->mem_held = n_lanes * (fixed + (int64_t)slots1 * tb1 + (int64_t)slots2 * tb2);
+    S->stats.lanes = n_lanes;
+    S->stats.max_slots = max_slots;
+    S->stats.mem_held = S->mem_held;
+    S->stats.spill_tables[0] = slots1;
+    S->stats.spill_tables[1] = slots2;
+    try {
+        S->worker = std::thread(worker_main, S);
+    } catch (...) {
+        server_release(S);
+        return fail(LCD_ENOMEM, "could not start the server thread");
+    }
+    *out = S;
+    return LCD_OK;
+}
+
+lcd_status lcd_server_submit(lcd_server *S, const int32_t *seeds, int32_t n, double alpha,
+                             uint64_t *ticket) {
+    if (!S || !ticket)
+        return fail(LCD_EINVAL, "null argument");
+    if (n < 1 || !seeds)
+        return fail(LCD_EINVAL, "a query needs at least one seed node");
+    if (!std::isfinite(alpha) || alpha < 0.0 || alpha > 1000.0)
+        return fail(LCD_EINVAL, "alpha must be finite and in [0, 1000]");
+    Query *q = new (std::nothrow) Query();
+    if (!q)
+        return fail(LCD_ENOMEM, "host allocation failed");
+    q->seeds.assign(seeds, seeds + n);
+    std::vector<int32_t> srt(q->seeds);
+    std::sort(srt.begin(), srt.end());
+    for (int32_t i = 0; i < n; ++i) {
+        if (srt[i] < 0 || srt[i] >= S->g->n || (i > 0 && srt[i] == srt[i - 1])) {
+            delete q;
+            return fail(LCD_EINVAL, "seed nodes must be distinct ids in [0, n)");
+        }
+    }
+    if ((int64_t)n > S->lanes[0].max_seed) {
+        delete q;
+        return fail(LCD_EINVAL, "a query may hold at most %lld seed nodes", (long long)S->lanes[0].max_seed);
+    }
+    q->alpha = alpha;
+    q->reserve = std::min<int64_t>(S->lanes[0].pool_cap, 4 * (int64_t)n + 2048);
+    q->info.t_submit_ns = now_ns();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->stop) {
+            delete q;
+            return fail(LCD_ESTATE, "server is shutting down");
+        }
+        q->ticket = S->next_ticket++;
+        S->tickets[q->ticket] = q;
+        S->pending.push_back(q);
+        S->stats.submitted += 1;
+        *ticket = q->ticket;
+    }
+    S->cv_work.notify_one();
+    return LCD_OK;
+}
+
+lcd_status lcd_server_poll(lcd_server *S, uint64_t ticket, int32_t *members, int32_t cap,
+                           lcd_query_info *info) {
+    if (!S)
+        return fail(LCD_EINVAL, "null server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->tickets.find(ticket);
+    if (it == S->tickets.end())
+        return fail(LCD_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    Query *q = it->second;
+    if (!q->done)
+        return LCD_EAGAIN;
+    if (q->status != LCD_OK) {
+        const lcd_status s = fail(q->status, "%s", q->msg.c_str());
+        S->tickets.erase(it);
+        delete q;
+        return s;
+    }
+    if (info)
+        *info = q->info;
+    if ((int64_t)cap < (int64_t)q->members.size() || (!members && !q->members.empty()))
+        return fail(LCD_ECAPACITY, "the result has %zu members, the buffer holds %d",
+                    q->members.size(), cap);
+    if (!q->members.empty())
+        std::memcpy(members, q->members.data(), sizeof(int32_t) * q->members.size());
+    S->tickets.erase(it);
+    delete q;
+    return LCD_OK;
+}
+
+lcd_status lcd_server_wait(lcd_server *S, uint64_t ticket, int32_t timeout_ms) {
+    if (!S)
+        return fail(LCD_EINVAL, "null server");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->tickets.find(ticket);
+    if (it == S->tickets.end())
+        return fail(LCD_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    Query *q = it->second;
+    auto ready = [q] { return q->done; };
+    if (timeout_ms < 0)
+        S->cv_done.wait(lk, ready);
+    else if (!S->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready))
+        return LCD_EAGAIN;
+    return LCD_OK;
+}
+
+lcd_status lcd_server_get_stats(lcd_server *S, lcd_server_stats *out) {
+    if (!S || !out)
+        return fail(LCD_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    *out = S->stats;
+    out->pending = (int64_t)S->pending.size();
+    out->in_flight = S->in_flight;
+    return LCD_OK;
+}
+
+lcd_status lcd_server_destroy(lcd_server *S) {
+    if (!S)
+        return LCD_OK;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv_work.notify_all();
+    if (S->worker.joinable())
+        S->worker.join();
+    server_release(S);
+    return LCD_OK;
+}
+
+}  // extern "C"

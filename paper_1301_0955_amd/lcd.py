@@ -63,6 +63,29 @@ class lcd_sweep_stats(ctypes.Structure):
         return d
 
 
+class lcd_query_info(ctypes.Structure):
+    _fields_ = [("n_members", ctypes.c_int32), ("batch_size", ctypes.c_int32),
+                ("k_in", ctypes.c_int64), ("vol", ctypes.c_int64), ("f", ctypes.c_double),
+                ("ctr", ctypes.c_uint64 * 4), ("t_submit_ns", ctypes.c_int64),
+                ("t_start_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64),
+                ("lane", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class lcd_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("requeued", ctypes.c_int64), ("pending", ctypes.c_int64),
+                ("in_flight", ctypes.c_int64), ("mem_held", ctypes.c_int64),
+                ("lanes", ctypes.c_int32), ("max_slots", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("max_lanes_busy", ctypes.c_int32),
+                ("spill_tables", ctypes.c_int32 * 2)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "spill_tables"}
+        d["spill_tables"] = list(self.spill_tables)
+        return d
+
+
 _lib = None
 P = ctypes.c_void_p
 
@@ -97,6 +120,15 @@ def library() -> ctypes.CDLL:
         "lcd_log_device": (st, [P, P, ctypes.c_int64, P]),
         "lcd_device_info": (st, [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
                                  ctypes.POINTER(ctypes.c_int64), ctypes.c_char_p, ctypes.c_int32]),
+        "lcd_server_create": (st, [P, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(lcd_params),
+                                   ctypes.POINTER(P)]),
+        "lcd_server_submit": (st, [P, P, ctypes.c_int32, ctypes.c_double,
+                                   ctypes.POINTER(ctypes.c_uint64)]),
+        "lcd_server_poll": (st, [P, ctypes.c_uint64, P, ctypes.c_int32,
+                                 ctypes.POINTER(lcd_query_info)]),
+        "lcd_server_wait": (st, [P, ctypes.c_uint64, ctypes.c_int32]),
+        "lcd_server_get_stats": (st, [P, ctypes.POINTER(lcd_server_stats)]),
+        "lcd_server_destroy": (st, [P]),
         "lcd_last_error": (ctypes.c_char_p, []),
         "lcd_version": (ctypes.c_char_p, []),
     }
@@ -365,3 +397,84 @@ def sweep_to_numpy(res: Result) -> dict:
     _, ctr = res.counters(per_record=True)
     return dict(members=members, off=offs, cnt=cnt, K=K, V=V, f=f,
                 ctr=ctr.cpu().numpy().astype(np.uint64), n_sets=ns, n_scales=S)
+
+
+# ---------------------------------------------------------------------------
+# Query server
+# ---------------------------------------------------------------------------
+
+class Server:
+    """lcd_server_*: (seed set, alpha) queries answered by a resident graph,
+    batched as they arrive by the library's worker thread."""
+
+    def __init__(self, graph: "Graph", mem_budget: int = 0, max_slots: int = 0, **kw):
+        lib = library()
+        prm = make_params(**kw) if kw else None
+        h = P()
+        _check(lib.lcd_server_create(graph._h, int(mem_budget), int(max_slots),
+                                     ctypes.byref(prm) if prm is not None else None,
+                                     ctypes.byref(h)), "lcd_server_create")
+        self._h = h
+        self.graph = graph
+
+    def submit(self, seeds, alpha: float) -> int:
+        a = np.ascontiguousarray(seeds, dtype=np.int32)
+        t = ctypes.c_uint64()
+        _check(library().lcd_server_submit(self._h, a.ctypes.data_as(P), a.size, float(alpha),
+                                           ctypes.byref(t)), "lcd_server_submit")
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while the query runs, else a dict with members and info."""
+        lib = library()
+        info = lcd_query_info()
+        s = lib.lcd_server_poll(self._h, ticket, None, 0, ctypes.byref(info))
+        if s == LCD_EAGAIN:
+            return None
+        if s == LCD_ECAPACITY or (s == LCD_OK and info.n_members > 0):
+            mem = np.zeros(max(info.n_members, 1), np.int32)
+            s = lib.lcd_server_poll(self._h, ticket, mem.ctypes.data_as(P), mem.size,
+                                    ctypes.byref(info))
+            _check(s, "lcd_server_poll")
+            mem = mem[:info.n_members]
+        else:
+            _check(s, "lcd_server_poll")
+            mem = np.zeros(0, np.int32)
+        return dict(members=mem, K=info.k_in, V=info.vol, f=info.f,
+                    ctr=np.array(list(info.ctr), dtype=np.uint64),
+                    t_submit_ns=info.t_submit_ns, t_start_ns=info.t_start_ns,
+                    t_done_ns=info.t_done_ns, batch_size=info.batch_size, lane=info.lane)
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> bool:
+        s = library().lcd_server_wait(self._h, ticket, int(timeout_ms))
+        if s == LCD_EAGAIN:
+            return False
+        _check(s, "lcd_server_wait")
+        return True
+
+    def result(self, ticket: int, timeout_ms: int = -1):
+        if not self.wait(ticket, timeout_ms):
+            raise TimeoutError("query %d not done after %d ms" % (ticket, timeout_ms))
+        return self.poll(ticket)
+
+    def stats(self) -> dict:
+        st = lcd_server_stats()
+        _check(library().lcd_server_get_stats(self._h, ctypes.byref(st)), "lcd_server_get_stats")
+        return st.as_dict()
+
+    def close(self):
+        if self._h:
+            _check(library().lcd_server_destroy(self._h), "lcd_server_destroy")
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

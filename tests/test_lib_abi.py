@@ -79,3 +79,24 @@ def test_graph_validation_rejects(lib, case):
     st, msg = _upload(lib, n, rp, col, w)
     assert st == 1, (case, st, msg)     # LCD_EINVAL
     assert msg
+
+
+def test_server_rejects_null_arguments(lib):
+    """Argument checks of the server entry points that run before any device
+    call."""
+    P = ctypes.c_void_p
+    lib.lcd_server_create.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P, ctypes.POINTER(P)]
+    lib.lcd_server_submit.argtypes = [P, P, ctypes.c_int32, ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_uint64)]
+    lib.lcd_server_poll.argtypes = [P, ctypes.c_uint64, P, ctypes.c_int32, P]
+    lib.lcd_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.c_int32]
+    lib.lcd_server_destroy.argtypes = [P]
+    h = P()
+    assert lib.lcd_server_create(None, 0, 0, None, ctypes.byref(h)) == 1
+    assert lib.lcd_server_create(None, 0, 0, None, None) == 1
+    t = ctypes.c_uint64()
+    seeds = np.array([0], np.int32)
+    assert lib.lcd_server_submit(None, seeds.ctypes.data_as(P), 1, 0.5, ctypes.byref(t)) == 1
+    assert lib.lcd_server_poll(None, 1, None, 0, None) == 1
+    assert lib.lcd_server_wait(None, 1, 0) == 1
+    assert lib.lcd_server_destroy(None) == 0
