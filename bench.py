@@ -92,6 +92,124 @@ def cpu_baseline(g, sp, sn, sc, stride, got_res):
                 seconds=dt, parity_on_sample=parity)
 
 
+def percentiles(x):
+    x = np.asarray(x, dtype=np.float64)
+    if x.size == 0:
+        return {}
+    p = np.percentile(x, [50, 90, 99, 99.9])
+    return dict(p50=round(float(p[0]), 4), p90=round(float(p[1]), 4), p99=round(float(p[2]), 4),
+                p999=round(float(p[3]), 4), mean=round(float(x.mean()), 4), max=round(float(x.max()), 4))
+
+
+def serve_bench(lcd, G, g, qps, seconds, warmup_s, oracle_sample, seed=1):
+    """Open-loop Poisson stream of (seed set, alpha) queries against the
+    query server; latency = completion stamp - scheduled arrival."""
+    import oracle
+    from paper_1301_0955_amd import workloads as W
+    n = int(round(qps * (warmup_s + seconds)))
+    t_arr, sets, alphas = W.query_stream(g, n, qps, max_size=256, seed=seed)
+    srv = lcd.Server(G, max_slots=1024)
+    for i in range(8):                      # first launches of the query kernels
+        srv.result(srv.submit(sets[i], alphas[i]))
+    st0 = srv.stats()
+    sched = np.zeros(n, np.int64)
+    tickets = []
+    base = time.monotonic_ns() + 20_000_000
+    next_log = 2.0
+    for i in range(n):
+        target = base + int(t_arr[i] * 1e9)
+        while True:
+            now = time.monotonic_ns()
+            if now >= target:
+                break
+            if target - now > 2_000_000:
+                time.sleep(0.001)
+        sched[i] = target
+        tickets.append(srv.submit(sets[i], alphas[i]))
+        if t_arr[i] >= next_log:
+            log("serving: %.0f s of %.0f submitted (%d queries)" % (t_arr[i], warmup_s + seconds, i + 1))
+            next_log += 2.0
+    res = []
+    for t in tickets:
+        res.append(srv.result(t, 120_000))
+    st = srv.stats()
+    srv.close()
+    meas = np.nonzero(t_arr >= warmup_s)[0]
+    lat_ms = np.array([(res[i]["t_done_ns"] - sched[i]) * 1e-6 for i in meas])
+    queue_ms = np.array([(res[i]["t_start_ns"] - sched[i]) * 1e-6 for i in meas])
+    first = sched[meas[0]]
+    last = max(res[i]["t_done_ns"] for i in meas)
+    batches = st["batches"] - st0["batches"]
+    out = dict(
+        workload="lfr3-1M resident; Poisson arrivals at %g queries/s; seed sets = BFS prefixes of "
+                 "log-uniform size in [1, 256]; alpha log-uniform on [0.5, 1]; one fixpoint growth per "
+                 "query" % qps,
+        offered_qps=qps, seconds=seconds, warmup_s=warmup_s, queries=int(meas.size),
+        achieved_qps=round(meas.size / ((last - first) * 1e-9), 1),
+        latency_ms=percentiles(lat_ms), queue_ms=percentiles(queue_ms),
+        mean_seed_size=round(float(np.mean([len(sets[i]) for i in meas])), 2),
+        mean_members=round(float(np.mean([res[i]["members"].size for i in meas])), 2),
+        batches=int(batches), mean_batch=round((st["completed"] - st0["completed"]) / max(batches, 1), 2),
+        max_batch=st["max_batch"], max_lanes_busy=st["max_lanes_busy"], lanes=st["lanes"],
+        requeued=st["requeued"], failed=st["failed"], server_mem_bytes=st["mem_held"])
+    # the oracle on a sample of the same queries: per-query CPU latency and parity
+    if oracle_sample > 0:
+        o = oracle.Oracle.from_graph(g)
+        pick = meas[np.linspace(0, meas.size - 1, min(oracle_sample, meas.size)).astype(np.int64)]
+        cpu_ms = []
+        ok = True
+        for i in pick.tolist():
+            t0 = time.perf_counter()
+            per, K, V, f, ctr, _ = o.run_set(sets[i], np.array([alphas[i]]))
+            cpu_ms.append((time.perf_counter() - t0) * 1e3)
+            r = res[i]
+            if (not np.array_equal(per[0], r["members"]) or int(K[0]) != r["K"] or int(V[0]) != r["V"]
+                    or not np.array_equal(ctr[0], r["ctr"])):
+                ok = False
+        out["cpu_oracle"] = dict(kind="oracle", cores=1, queries=int(pick.size),
+                                 latency_ms=percentiles(cpu_ms),
+                                 note="service time of one query on one host core, no queueing")
+        out["parity_on_sample"] = "bit-exact" if ok else "MISMATCH"
+    return out
+
+
+def sweep_compare(lcd, G, g, sp, sn, sc, steps, prm):
+    """Persistent all-scales launch vs the per-scale launch loop on one
+    workload (device time of each, identical results required)."""
+    import torch
+    d_sc = torch.as_tensor(sc, dtype=torch.float64, device="cuda")
+    d_sp = torch.as_tensor(sp, dtype=torch.int32, device="cuda")
+    d_sn = torch.as_tensor(sn, dtype=torch.int32, device="cuda")
+    r = lcd.lcd_sweep(G, d_sc, d_sp, d_sn, **prm)
+    r.free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rs = [lcd.lcd_sweep(G, d_sc, d_sp, d_sn, **prm) for _ in range(steps)]
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    sts = [x.stats() for x in rs]
+    tot = rs[0].counters()
+    ids = np.arange(0, sp.size - 1, 997, dtype=np.int32)
+    a = rs[0].sets_to_numpy(ids)
+    for x in rs:
+        x.free()
+    rl = lcd.lcd_sweep(G, d_sc, d_sp, d_sn, mode=lcd.LCD_PER_SCALE_LOOP, **prm)
+    lst = rl.stats()
+    b = rl.sets_to_numpy(ids)
+    tot_l = rl.counters()
+    rl.free()
+    same = (tot == tot_l and np.array_equal(a["members"], b["members"]) and np.array_equal(a["K"], b["K"])
+            and np.array_equal(a["ctr"], b["ctr"]))
+    ms = float(np.mean([x["ms_total"] for x in sts]))
+    return dict(ms_per_sweep_wall=round(wall * 1e3, 3), sweep_ms_device=round(ms, 3),
+                ms_main=round(float(np.mean([x["ms_main"] for x in sts])), 3),
+                ms_spill=round(float(np.mean([x["ms_spill"] for x in sts])), 3),
+                gains=int(tot[0]), gains_per_s=tot[0] / (wall), spilled_sets=sts[0]["n_spilled"],
+                lds_capacity=sts[0]["lds_capacity"],
+                per_scale_loop_ms_device=round(lst["ms_total"], 3), per_scale_loop_launches=lst["launches"],
+                persistent_speedup=round(lst["ms_total"] / ms, 3), identical_results=bool(same))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +223,13 @@ def main():
                     help="oracle sample stride (0 = sized for ~15 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-loop-compare", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the 1M-node sweep comparison")
+    ap.add_argument("--no-serve", action="store_true", help="skip the query-serving run")
+    ap.add_argument("--serve-qps", type=float, default=2000.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-warmup", type=float, default=2.0)
+    ap.add_argument("--serve-oracle", type=int, default=300,
+                    help="queries the oracle re-runs for CPU latency and parity")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -194,6 +319,29 @@ def main():
         cpu = cpu_baseline(g, sp, sn, sc, stride, got)
         log("cpu baseline: %s" % cpu["sample"])
 
+    large = serving = None
+    if not (args.no_large and args.no_serve) and args.workload != "large":
+        t0 = time.perf_counter()
+        from paper_1301_0955_amd import workloads as W
+        gl, spl, snl, scl = W.workload_large()
+        log("lfr3-1M ready in %.1f s: n=%d nnz=%d sets=%d scales=%d"
+            % (time.perf_counter() - t0, gl.n, gl.nnz, spl.size - 1, scl.size))
+        GL = lcd.Graph.from_workload(gl)
+        if not args.no_large:
+            large = sweep_compare(lcd, GL, gl, spl, snl, scl, 2, {})
+            large["workload"] = ("lfr3-1M: 1,000,000-node 3-level LFR-style graph (mean degree 15, "
+                                 "max 200, mixing 0.25, weights 1..16), rule-1 seeds (%d), 64 scales "
+                                 "on [0.5,1]" % (spl.size - 1))
+            log("lfr3-1M sweep: %.1f ms device, per-scale loop %.1f ms"
+                % (large["sweep_ms_device"], large["per_scale_loop_ms_device"]))
+        if not args.no_serve:
+            serving = serve_bench(lcd, GL, gl, args.serve_qps, args.serve_seconds, args.serve_warmup,
+                                  args.serve_oracle)
+            log("serving: p50 %.3f ms, p99 %.3f ms at %.0f offered, %.0f achieved queries/s"
+                % (serving["latency_ms"]["p50"], serving["latency_ms"]["p99"], serving["offered_qps"],
+                   serving["achieved_qps"]))
+        GL.free()
+
     out = {
         "metric": METRIC,
         "value": gains / (ms_step * 1e-3),
@@ -219,6 +367,8 @@ def main():
         "roofline": roofline,
         "per_scale_loop": loop,
         "cpu_baseline": cpu,
+        "large_sweep": large,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 
