@@ -26,6 +26,8 @@ METRIC = ("candidate-node gains/s + full multi-scale sweep time; "
           "p50/p99 seed-query latency")
 HBM_PEAK_GBS = 8000.0
 RECORD_BYTES = 8 + 4 + 8 + 8 + 8 + 32   # off, cnt, K, V, f, four counters
+KERNEL_OF_KIND = {0: "sweep_lds_kernel", 1: "sweep_global_kernel", 2: "sweep_team_lds_kernel",
+                  3: "sweep_team_global_kernel"}
 
 
 def log(msg):
@@ -177,6 +179,9 @@ def sweep_compare(lcd, G, g, sp, sn, sc, steps, prm):
     """Persistent all-scales launch vs the per-scale launch loop on one
     workload (device time of each, identical results required)."""
     import torch
+    t0 = time.perf_counter()
+    tuned = lcd.lcd_tune(G, sc, sp, sn)
+    log("lfr3-1M autotuned in %.1f s: %s" % (time.perf_counter() - t0, tuned["best"]))
     d_sc = torch.as_tensor(sc, dtype=torch.float64, device="cuda")
     d_sp = torch.as_tensor(sp, dtype=torch.int32, device="cuda")
     d_sn = torch.as_tensor(sn, dtype=torch.int32, device="cuda")
@@ -202,8 +207,10 @@ def sweep_compare(lcd, G, g, sp, sn, sc, steps, prm):
             and np.array_equal(a["ctr"], b["ctr"]))
     ms = float(np.mean([x["ms_total"] for x in sts]))
     return dict(ms_per_sweep_wall=round(wall * 1e3, 3), sweep_ms_device=round(ms, 3),
-                ms_main=round(float(np.mean([x["ms_main"] for x in sts])), 3),
-                ms_spill=round(float(np.mean([x["ms_spill"] for x in sts])), 3),
+                ms_tier=[round(float(np.mean([x["ms_tier"][k] for x in sts])), 3)
+                         for k in range(sts[0]["tiers"])],
+                tier_kernels=[KERNEL_OF_KIND[k] for k in sts[0]["tier_kind"][:sts[0]["tiers"]]],
+                tuned=tuned["best"],
                 gains=int(tot[0]), gains_per_s=tot[0] / (wall), spilled_sets=sts[0]["n_spilled"],
                 lds_capacity=sts[0]["lds_capacity"],
                 per_scale_loop_ms_device=round(lst["ms_total"], 3), per_scale_loop_launches=lst["launches"],
@@ -223,6 +230,7 @@ def main():
                     help="oracle sample stride (0 = sized for ~15 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-loop-compare", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (static sizing)")
     ap.add_argument("--no-large", action="store_true", help="skip the 1M-node sweep comparison")
     ap.add_argument("--no-serve", action="store_true", help="skip the query-serving run")
     ap.add_argument("--serve-qps", type=float, default=2000.0)
@@ -254,50 +262,77 @@ def main():
     d_sn = torch.as_tensor(sn, dtype=torch.int32, device="cuda")
     prm = dict(lds_capacity=args.lds_capacity, waves_per_block=args.waves_per_block,
                blocks_per_cu=args.blocks_per_cu)
+    tuned = None
+    if not any(prm.values()) and not args.no_tune:
+        t0 = time.perf_counter()
+        tuned = lcd.lcd_tune(G, sc, sp, sn)
+        log("autotuned in %.1f s: %s (sample of every %d-th set)"
+            % (time.perf_counter() - t0, tuned["best"], tuned["sample_stride"]))
     torch.cuda.synchronize()
 
+    # one result object; every step re-runs the whole sweep into it (inputs
+    # and outputs stay on the device; the first call allocates)
+    res = lcd.lcd_sweep(G, d_sc, d_sp, d_sn, **prm)
     for i in range(args.warmup):
-        r = lcd.lcd_sweep(G, d_sc, d_sp, d_sn, **prm)
-        st = r.stats()
-        r.free()
-        log("warmup %d: device %.2f ms (main %.2f, spill %.2f), spilled %d, reruns %d"
-            % (i, st["ms_total"], st["ms_main"], st["ms_spill"], st["n_spilled"], st["reruns"]))
-
-    results = []
+        st = res.rerun().stats()
+        log("warmup %d: device %.2f ms, tiers %s ms, spilled %d, reruns %d"
+            % (i, st["ms_total"], [round(x, 2) for x in st["ms_tier"][:st["tiers"]]],
+               st["n_spilled"], st["reruns"]))
     torch.cuda.synchronize()
+    stats = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        results.append(lcd.lcd_sweep(G, d_sc, d_sp, d_sn, **prm))
+        stats.append(res.rerun().stats())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = 1e3 * wall / max(args.steps, 1)
-    stats = [r.stats() for r in results]
-    totals = results[0].counters()
+    totals = res.counters()
     log("timed %d steps: %.2f ms/step wall" % (args.steps, ms_step))
-    got = lcd.sweep_to_numpy(results[0])
-    for r in results:
-        r.free()
+    got = lcd.sweep_to_numpy(res)
+    res.free()
+
+    # the same sweep captured in a hipGraph and replayed
+    rg = lcd.lcd_sweep(G, d_sc, d_sp, d_sn, use_graph=1, **prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        rg.rerun()
+    torch.cuda.synchronize()
+    graph_ms = 1e3 * (time.perf_counter() - t0) / max(args.steps, 1)
+    graph_same = bool(np.array_equal(rg.counters(), totals))
+    rg.free()
+    # a fresh call each step (allocation, seed upload, launch, statistics)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(2):
+        lcd.lcd_sweep(G, d_sc, d_sp, d_sn, **prm).free()
+    fresh_ms = 1e3 * (time.perf_counter() - t0) / 2
+    log("hipGraph replay %.2f ms/step, fresh call %.2f ms" % (graph_ms, fresh_ms))
 
     gains = totals[0]
-    ms_main = float(np.mean([s["ms_main"] for s in stats]))
-    ms_spill = float(np.mean([s["ms_spill"] for s in stats]))
     ms_dev = float(np.mean([s["ms_total"] for s in stats]))
     st0 = stats[0]
     S = sc.size
     weighted = g.w is not None
-    t0s, t1s, t2s = st0["tier"]
-    b_main = algorithmic_bytes(t0s, weighted, int(sn.size) if t0s["sets_finished"] else 0,
-                               t0s["sets_finished"] * S)
-    b_spill = (algorithmic_bytes(t1s, weighted, 0, t1s["sets_finished"] * S)
-               + algorithmic_bytes(t2s, weighted, 0, t2s["sets_finished"] * S))
-    if ms_main >= ms_spill:
-        kname, kbytes, kms = "sweep_lds_kernel", b_main, ms_main
-    else:
-        kname, kbytes, kms = "sweep_global_kernel", b_spill, ms_spill
+    nt = st0["tiers"]
+    ms_tier = [float(np.mean([s["ms_tier"][k] for s in stats])) for k in range(nt)]
+    k_dom = int(np.argmax(ms_tier))
+    t_dom = st0["tier"][k_dom]
+    kbytes = algorithmic_bytes(t_dom, weighted, int(sn.size) if k_dom == 0 else 0,
+                               t_dom["sets_finished"] * S)
+    kname = KERNEL_OF_KIND[st0["tier_kind"][k_dom]]
+    kms = ms_tier[k_dom]
     achieved = kbytes / (kms * 1e-3) / 1e9
-    roofline = dict(bound="hbm", kernel=kname, achieved=round(achieved, 2), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 6), traffic=None,
-                    algorithmic_bytes=int(kbytes), kernel_ms=round(kms, 4))
+    roofline = dict(bound="hbm", kernel=kname, tier=k_dom, achieved=round(achieved, 3), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 7), traffic=None,
+                    algorithmic_bytes=int(kbytes), kernel_ms=round(kms, 4),
+                    tiers=[dict(kernel=KERNEL_OF_KIND[st0["tier_kind"][k]],
+                                table_entries=st0["tier_capacity"][k], ms=round(ms_tier[k], 3),
+                                sets_finished=st0["tier"][k]["sets_finished"],
+                                algorithmic_bytes=int(algorithmic_bytes(
+                                    st0["tier"][k], weighted, int(sn.size) if k == 0 else 0,
+                                    st0["tier"][k]["sets_finished"] * S)))
+                           for k in range(nt)])
 
     loop = None
     if not args.no_loop_compare:
@@ -358,7 +393,11 @@ def main():
         "config": {"workload": desc, "n": g.n, "nnz": g.nnz, "seed_sets": int(sp.size - 1),
                    "scales": int(S), "graph_sha256": g.sha256()[:16],
                    "lds_capacity": st0["lds_capacity"], "waves_per_block": st0["waves_per_block"],
-                   "grid_blocks": st0["grid_blocks"]},
+                   "grid_blocks": st0["grid_blocks"], "tiers": nt,
+                   "tuned": tuned["best"] if tuned else None},
+        "hipgraph_ms_per_step": round(graph_ms, 4),
+        "hipgraph_identical_counters": graph_same,
+        "fresh_call_ms": round(fresh_ms, 3),
         "sweep_ms_device": round(ms_dev, 4),
         "gains_per_step": int(gains),
         "counters": {"G": totals[0], "R": totals[1], "M": totals[2], "C": totals[3]},

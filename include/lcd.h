@@ -74,19 +74,32 @@ typedef struct lcd_server lcd_server;
 typedef struct {
     uint32_t k_prune;        /* removal passes per growth call; 0 = unbounded */
     int32_t mode;            /* LCD_PERSISTENT or LCD_PER_SCALE_LOOP */
-    int32_t lds_capacity;    /* table entries per community held in LDS; 0 = default */
+    int32_t lds_capacity;    /* tier 0: table entries per community held in LDS;
+                                0 = tuned (lcd_tune) or 512 */
     int32_t waves_per_block; /* communities (one wave each) per workgroup; 0 = default */
     int32_t blocks_per_cu;   /* resident workgroups per compute unit; 0 = default */
-    int32_t use_graph;       /* 1: capture the launch sequence in a hipGraph and replay it */
+    int32_t use_graph;       /* 1 (persistent mode): capture the sweep's launch sequence
+                                (fill kernels and every tier) in a hipGraph, launch
+                                it, and replay it on lcd_result_rerun() */
     int64_t pool_hint;       /* initial member-pool size in entries; 0 = estimate */
     int32_t watchdog_ms;     /* wall-clock budget of one seed set; past it the sweep
                                 stops with LCD_EDEVICE.  0 = default (20000);
                                 negative = no budget at all (tests the error path) */
-    int32_t pad;
+    int32_t spill_mode;      /* sets whose table outgrows tier 0: 0 = workgroup tiers
+                                (one workgroup per community: an LDS table of
+                                team_capacity entries, then global-memory tables);
+                                1 = one-wave global-memory tiers; 2 = one-wave
+                                global tables of 16,384 entries, then workgroups
+                                on tables that hold every node */
+    int32_t team_capacity;   /* spill_mode 0: entries of the workgroup tier's LDS table;
+                                0 = max(1,024, 2 lds_capacity), within one workgroup's LDS */
+    int32_t team_waves;      /* waves per community in the workgroup tiers, 1..8;
+                                0 = 4 */
 } lcd_params;
 
-/* Work of one table tier (0 = LDS, 1 and 2 = global-memory tiers),
- * counted over the seed sets that tier finished. */
+/* Work of one table tier (0 = one wave per community with an LDS table; the
+ * later tiers hold larger tables, see lcd_params.spill_mode), counted over
+ * the seed sets that tier finished. */
 typedef struct {
     int64_t rows_gathered;    /* CSR rows read: one per move and per initial member */
     int64_t row_entries;      /* total length of those rows */
@@ -98,18 +111,22 @@ typedef struct {
 /* Timing and bookkeeping of one sweep (filled by lcd_result_stats). */
 typedef struct {
     double ms_total;          /* device time of the whole sweep (hipEvents on the caller's stream) */
-    double ms_main;           /* device time of the LDS-resident sweep kernel(s) */
-    double ms_spill;          /* device time of the global-memory tiers */
-    int64_t n_spilled;        /* seed sets finished by a global-memory tier */
-    int64_t n_spilled_big;    /* ... of which by the largest tier */
+    double ms_main;           /* device time of tier 0 */
+    double ms_spill;          /* device time of the later tiers */
+    int64_t n_spilled;        /* seed sets that left tier 0 */
+    int64_t n_spilled_big;    /* ... of which reached the last tier */
     int64_t pool_used;        /* member-pool entries written */
     int32_t reruns;           /* relaunches after the member pool had to grow */
     int32_t lds_capacity;     /* table entries per community in LDS actually used */
     int32_t waves_per_block;
     int32_t grid_blocks;      /* workgroups of the LDS-resident launch */
     int32_t launches;         /* kernel launches of the sweep (excluding readout) */
-    int32_t pad;
-    lcd_tier_stats tier[3];
+    int32_t tiers;            /* tiers in the launch chain */
+    lcd_tier_stats tier[4];
+    double ms_tier[4];        /* device time of each tier (persistent mode, no hipGraph) */
+    int32_t tier_kind[4];     /* 0 one wave + LDS table, 1 one wave + global table,
+                                 2 workgroup + LDS table, 3 workgroup + global table */
+    int32_t tier_capacity[4]; /* table entries per community of each tier */
 } lcd_sweep_stats;
 
 /* Fill *p with the defaults (k_prune 0, persistent mode, autotuned sizes). */
@@ -157,6 +174,35 @@ lcd_status lcd_sweep(const lcd_graph *g, const double *scales, int32_t n_scales,
                      int32_t mem_kind, const lcd_params *params, void *stream,
                      lcd_result **out);
 
+/* Result of lcd_tune(). */
+typedef struct {
+    lcd_params best;          /* the chosen sizing (the graph keeps it) */
+    double ms_best;           /* device time of one sweep of the sample with it */
+    int32_t n_tried;
+    int32_t sample_stride;    /* every sample_stride-th seed set was timed */
+    int32_t full_checked;     /* 1: the three fastest were re-timed on every set */
+    int32_t pad;
+    double ms[16];            /* device time of the sample per candidate */
+    lcd_params tried[16];
+} lcd_tune_report;
+
+/*
+ * Autotuner: time one sweep of a sample of the given seed sets (every
+ * stride-th set, at most ~16k sets) with each of a fixed list of launch
+ * sizings (tier-0 LDS table, spill mode, workgroup table, waves per
+ * community) and keep the fastest on the graph.  Later lcd_sweep() and
+ * lcd_server_create() calls whose params leave every sizing field at 0 use
+ * it.  k_prune and watchdog_ms come from base (NULL = defaults).  Results
+ * of a sweep never depend on the sizing; only the time does.  Blocking;
+ * runs about 2 x 10 sample sweeps.
+ */
+lcd_status lcd_tune(lcd_graph *g, const double *scales, int32_t n_scales, const int32_t *seed_ptr,
+                    const int32_t *seed_nodes, int32_t n_sets, int32_t mem_kind, const lcd_params *base,
+                    void *stream, lcd_tune_report *report);
+
+/* Forget the tuned sizing (later calls use the static defaults). */
+lcd_status lcd_graph_untune(lcd_graph *g);
+
 /* Sweep shape and the total number of members listed at one scale. */
 lcd_status lcd_result_shape(const lcd_result *r, int32_t *n_sets, int32_t *n_scales);
 lcd_status lcd_result_sizes(const lcd_result *r, int32_t scale_idx, int64_t *total_members);
@@ -203,6 +249,16 @@ lcd_status lcd_result_sets(const lcd_result *r, const int32_t *set_ids, int32_t 
                            uint64_t *ctr);
 
 lcd_status lcd_result_stats(const lcd_result *r, lcd_sweep_stats *out);
+
+/*
+ * Run the same sweep again (same graph, scales and seed sets, still on the
+ * device) into the same result, overwriting it; with use_graph the captured
+ * hipGraph is replayed (captured again if the member pool or the graph's
+ * spill tables were reallocated since).  Sweeps of one graph must not run
+ * concurrently: they share its spill-tier tables.  Blocking.
+ */
+lcd_status lcd_result_rerun(lcd_result *r, void *stream);
+
 lcd_status lcd_result_free(lcd_result *r);
 
 /* ------------------------------------------------------------------------

@@ -75,12 +75,13 @@ lcd_status ensure_slab(Slab &sl, int32_t cap, int32_t slots, hipStream_t st) {
 }
 
 lcd_status plan_tiers(const DevInfo &dev, int32_t n, const lcd_params &p, TierPlan &tp) {
-    int32_t cap = p.lds_capacity > 0 ? p.lds_capacity : 1024;
+    int32_t cap = p.lds_capacity > 0 ? p.lds_capacity : 512;
     if (cap % 64 != 0 || cap < 64 || cap > 8192)
         return fail(LCD_EINVAL, "lds_capacity must be a multiple of 64 in [64, 8192]");
-    tp.cap0 = cap;
-    tp.hbits0 = next_pow2_bits(2 * (int64_t)cap);
-    const int64_t tb = table_bytes(cap, tp.hbits0);
+    if (p.spill_mode < 0 || p.spill_mode > 2)
+        return fail(LCD_EINVAL, "spill_mode must be 0, 1 or 2");
+    const int32_t hbits0 = next_pow2_bits(2 * (int64_t)cap);
+    const int64_t tb = table_bytes(cap, hbits0);
     int32_t wpb = p.waves_per_block > 0 ? p.waves_per_block
                                         : (int32_t)std::max<int64_t>(1, std::min<int64_t>(4, dev.lds_block / tb));
     if (wpb > 4)
@@ -91,61 +92,117 @@ lcd_status plan_tiers(const DevInfo &dev, int32_t n, const lcd_params &p, TierPl
     int32_t bpc = p.blocks_per_cu > 0 ? p.blocks_per_cu
                                       : (int32_t)std::max<int64_t>(1, dev.lds_cu / (wpb * tb));
     bpc = std::min(bpc, 32);
-    tp.wpb0 = wpb;
-    tp.blocks0 = dev.cus * bpc;
-    // spill tiers: a 16k-entry tier with many tables, then one that holds
-    // every node of the graph
+    tp.n = 0;
+    tp.t[tp.n++] = TierSpec{TIER_WAVE_LDS, cap, hbits0, wpb, dev.cus * bpc, 0, -1};
     const int64_t need = std::max<int64_t>(64, n);
-    tp.cap1 = (int32_t)std::min<int64_t>(16384, ((int64_t)1 << next_pow2_bits(need)));
-    tp.cap2 = (int32_t)((int64_t)1 << next_pow2_bits(need));
-    tp.use1 = tp.cap1 > cap && n > cap;
-    tp.use2 = tp.cap2 > std::max(cap, tp.cap1) && n > tp.cap1;
+    const int32_t capn = (int32_t)((int64_t)1 << next_pow2_bits(need));
+    int32_t have = cap;   // largest table so far
+    auto add_global = [&](int32_t kind, int32_t c, int32_t waves, int32_t slots, int32_t slab) {
+        tp.t[tp.n++] = TierSpec{kind, c, next_pow2_bits(2 * (int64_t)c), waves, 0, slots, slab};
+        have = c;
+    };
+    if (p.team_waves < 0 || 64 * p.team_waves > kTeamMaxThreads)
+        return fail(LCD_EINVAL, "team_waves must be in [0, %d]", kTeamMaxThreads / 64);
+    const int32_t team_waves = p.team_waves > 0 ? p.team_waves : 4;
+    // workgroups of a workgroup tier that stay resident on the whole chip
+    auto resident = [&](int32_t kind, int32_t waves, size_t lds) -> int32_t {
+        int32_t nb = 0;
+        if (tier_blocks_per_cu(kind, waves, lds, &nb) != hipSuccess || nb < 1)
+            nb = 1;
+        return dev.cus * nb;
+    };
+    if (p.spill_mode == 1 || p.spill_mode == 2) {
+        const int32_t c1 = std::min<int32_t>(16384, capn);
+        if (c1 > have && n > have)
+            add_global(TIER_WAVE_GLOBAL, c1, 4, 4096, 0);
+        if (capn > have && n > have) {
+            int64_t slots = ((int64_t)4 << 30) / slab_stride(capn);
+            if (p.spill_mode == 1)
+                add_global(TIER_WAVE_GLOBAL, capn, 4, (int32_t)std::max<int64_t>(4, std::min<int64_t>(256, slots)), 1);
+            else
+                add_global(TIER_TEAM_GLOBAL, capn, team_waves,
+                           (int32_t)std::max<int64_t>(4, std::min<int64_t>(resident(TIER_TEAM_GLOBAL, team_waves, 0), slots)), 1);
+        }
+        return LCD_OK;
+    }
+    // workgroup tiers: an LDS table per workgroup, then global tables
+    int32_t cl = std::max(1024, 2 * cap);
+    if (p.team_capacity > 0) {
+        cl = p.team_capacity;
+        if (cl % 64 != 0 || cl > 8192 ||
+            table_bytes(cl, next_pow2_bits(2 * (int64_t)cl)) + 1024 > dev.lds_block)
+            return fail(LCD_EINVAL, "team_capacity must be a multiple of 64 whose table fits one workgroup's LDS");
+    } else {
+        while (cl > 64 && table_bytes(cl, next_pow2_bits(2 * (int64_t)cl)) + 1024 > dev.lds_block)
+            cl >>= 1;
+    }
+    if (cl > have && n > have) {
+        const int32_t hb = next_pow2_bits(2 * (int64_t)cl);
+        tp.t[tp.n++] = TierSpec{TIER_TEAM_LDS, cl, hb, team_waves,
+                                resident(TIER_TEAM_LDS, team_waves, (size_t)table_bytes(cl, hb)), 0, -1};
+        have = cl;
+    }
+    const int32_t c2 = std::min<int32_t>(16384, capn);
+    if (c2 > have && n > have)
+        add_global(TIER_TEAM_GLOBAL, c2, team_waves, resident(TIER_TEAM_GLOBAL, team_waves, 0), 0);
+    if (capn > have && n > have) {
+        int64_t slots = ((int64_t)4 << 30) / slab_stride(capn);
+        add_global(TIER_TEAM_GLOBAL, capn, team_waves,
+                   (int32_t)std::max<int64_t>(4, std::min<int64_t>(resident(TIER_TEAM_GLOBAL, team_waves, 0), slots)), 1);
+    }
     return LCD_OK;
 }
 
 lcd_status enqueue_tiers(const SweepArgs &a0, const TierPlan &tp, int32_t blocks0, Slab *slabs,
-                         int32_t *const work[2], hipStream_t st, hipEvent_t *ev,
-                         int32_t *launches) {
-    SweepArgs a = a0;
-    if (ev)
-        HIPCHK(hipEventRecord(ev[0], st));
-    a.tier = 0;
-    a.in_from = 0;
-    a.work_in = nullptr;
-    a.work_out = tp.use1 ? work[0] : (tp.use2 ? work[1] : nullptr);
-    a.cap = tp.cap0;
-    a.hbits = tp.hbits0;
-    a.gtab = nullptr;
-    a.gtab_stride = 0;
-    a.n_slots = 0;
-    HIPCHK(launch_sweep(a, blocks0, tp.wpb0, st));
-    *launches += 1;
-    if (ev)
-        HIPCHK(hipEventRecord(ev[1], st));
-    // spill tiers read their item count from the tier that pushed to them
-    int from = 0;
-    for (int k = 0; k < 2; ++k) {
-        const bool use = k == 0 ? tp.use1 : tp.use2;
-        if (!use)
-            continue;
-        const Slab &sl = slabs[k];
-        SweepArgs b = a;
-        b.tier = k + 1;
-        b.in_from = from;
-        b.work_in = work[k];
-        b.work_out = (k == 0 && tp.use2) ? work[1] : nullptr;
-        b.cap = sl.cap;
-        b.hbits = sl.hbits;
-        b.gtab = sl.buf;
-        b.gtab_stride = sl.stride;
-        b.n_slots = sl.slots;
-        HIPCHK(launch_sweep(b, (sl.slots + 3) / 4, 4, st));
+                         int32_t *const *work, hipStream_t st, hipEvent_t *ev, int32_t *launches) {
+    for (int k = 0; k < tp.n; ++k) {
+        const TierSpec &T = tp.t[k];
+        if (ev)
+            HIPCHK(hipEventRecord(ev[k], st));
+        SweepArgs b = a0;
+        b.tier = k;
+        b.kind = T.kind;
+        b.in_from = k > 0 ? k - 1 : 0;
+        b.work_in = k > 0 ? work[k - 1] : nullptr;
+        b.work_out = k + 1 < tp.n ? work[k] : nullptr;
+        b.cap = T.cap;
+        b.hbits = T.hbits;
+        int32_t blocks = k == 0 ? blocks0 : T.blocks;
+        if (T.slab >= 0) {
+            const Slab &sl = slabs[T.slab];
+            if (sl.cap != T.cap || !sl.buf)
+                return fail(LCD_EDEVICE, "tier %d: table workspace not prepared", k);
+            b.gtab = sl.buf;
+            b.gtab_stride = sl.stride;
+            b.n_slots = sl.slots;
+            blocks = T.kind == TIER_WAVE_GLOBAL ? (sl.slots + T.waves - 1) / T.waves : sl.slots;
+        } else {
+            b.gtab = nullptr;
+            b.gtab_stride = 0;
+            b.n_slots = 0;
+        }
+        HIPCHK(launch_sweep(b, blocks, T.waves, st));
         *launches += 1;
-        from = k + 1;
     }
     if (ev)
-        HIPCHK(hipEventRecord(ev[2], st));
+        HIPCHK(hipEventRecord(ev[tp.n], st));
     return LCD_OK;
+}
+
+bool params_are_auto(const lcd_params &p) {
+    return p.lds_capacity == 0 && p.waves_per_block == 0 && p.blocks_per_cu == 0 && p.spill_mode == 0 &&
+           p.team_capacity == 0 && p.team_waves == 0;
+}
+
+void apply_tuned(const lcd_graph *g, lcd_params &p) {
+    if (!g->tuned || !params_are_auto(p))
+        return;
+    p.lds_capacity = g->tuned_prm.lds_capacity;
+    p.waves_per_block = g->tuned_prm.waves_per_block;
+    p.blocks_per_cu = g->tuned_prm.blocks_per_cu;
+    p.spill_mode = g->tuned_prm.spill_mode;
+    p.team_capacity = g->tuned_prm.team_capacity;
+    p.team_waves = g->tuned_prm.team_waves;
 }
 
 }  // namespace lcd
@@ -166,26 +223,24 @@ struct lcd_result {
     int32_t n_ctl = 0;
     unsigned long long *cursor = nullptr;
     uint32_t *err = nullptr;
-    int32_t *work[2] = {nullptr, nullptr};
+    int32_t *work[kMaxTiers - 1] = {nullptr, nullptr, nullptr};
     std::vector<double> scales_h;
     lcd_sweep_stats stats{};
+    // use_graph: the captured launch sequence and the buffers it refers to
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    // buffer addresses and sizes baked into the captured launches (a freed
+    // and reallocated buffer can come back at the same address)
+    int64_t cap_key[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace {
 
-// global-memory tables of the first spill tier: enough that the sets which
-// outgrow their LDS table in a typical sweep run in one round
-constexpr int32_t kSpillSlots = 4096;
 
 lcd_status prepare_slabs(lcd_graph *g, const TierPlan &tp, hipStream_t st) {
-    if (tp.use1)
-        CHK(ensure_slab(g->slab[0], tp.cap1, kSpillSlots, st));
-    if (tp.use2) {
-        const int64_t tb2 = table_bytes(tp.cap2, next_pow2_bits(2 * (int64_t)tp.cap2));
-        int64_t slots = ((int64_t)4 << 30) / tb2;
-        slots = std::max<int64_t>(4, std::min<int64_t>(256, slots));
-        CHK(ensure_slab(g->slab[1], tp.cap2, (int32_t)slots, st));
-    }
+    for (int k = 0; k < tp.n; ++k)
+        if (tp.t[k].slab >= 0)
+            CHK(ensure_slab(g->slab[tp.t[k].slab], tp.t[k].cap, tp.t[k].slots, st));
     return LCD_OK;
 }
 
@@ -212,7 +267,68 @@ lcd_status run_group(lcd_result *r, const TierPlan &tp, int32_t s_begin, int32_t
     a.err = r->err;
     a.budget_ticks = r->prm.watchdog_ms < 0 ? 0 : g->dev.wall_khz * (int64_t)r->prm.watchdog_ms;
     a.stat = r->cursor + 2;
-    return enqueue_tiers(a, tp, tp.blocks0, g->slab, r->work, st, ev, &r->stats.launches);
+    return enqueue_tiers(a, tp, tp.t[0].blocks, g->slab, r->work, st, ev, &r->stats.launches);
+}
+
+void capture_key(const lcd_result *r, int64_t key[8]) {
+    const lcd_graph *g = r->g;
+    key[0] = (int64_t)(intptr_t)g->slab[0].buf;
+    key[1] = g->slab[0].stride * g->slab[0].slots + g->slab[0].cap;
+    key[2] = (int64_t)(intptr_t)g->slab[1].buf;
+    key[3] = g->slab[1].stride * g->slab[1].slots + g->slab[1].cap;
+    key[4] = (int64_t)(intptr_t)r->pool;
+    key[5] = r->pool_cap;
+    key[6] = 0;
+    key[7] = 0;
+}
+
+void drop_graph(lcd_result *r) {
+    if (r->gexec)
+        (void)hipGraphExecDestroy(r->gexec);
+    if (r->graph)
+        (void)hipGraphDestroy(r->graph);
+    r->gexec = nullptr;
+    r->graph = nullptr;
+}
+
+// Capture the whole persistent sweep (queue and counter reset by fill
+// kernels, then every tier) into a hipGraph on a private stream.
+lcd_status capture_sweep(lcd_result *r, const TierPlan &tp) {
+    drop_graph(r);
+    hipStream_t cs = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    lcd_status s = LCD_OK;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        e = launch_zero_bytes(r->ctl, (int64_t)sizeof(Counters) * r->n_ctl, cs);
+        if (e == hipSuccess)
+            e = launch_zero_bytes(r->cursor, 8 * kCursorWords, cs);
+        if (e == hipSuccess)
+            s = run_group(r, tp, 0, r->S, 0, cs, nullptr);
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        if (e == hipSuccess && s == LCD_OK && e2 == hipSuccess) {
+            e = hipGraphInstantiate(&r->gexec, graph, nullptr, nullptr, 0);
+            if (e == hipSuccess)
+                r->graph = graph;
+            else
+                (void)hipGraphDestroy(graph);
+        } else {
+            if (graph)
+                (void)hipGraphDestroy(graph);
+            if (e == hipSuccess)
+                e = e2;
+        }
+    }
+    (void)hipStreamDestroy(cs);
+    if (s != LCD_OK)
+        return s;
+    if (e != hipSuccess) {
+        r->gexec = nullptr;
+        return fail(LCD_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+    }
+    capture_key(r, r->cap_key);
+    return LCD_OK;
 }
 
 lcd_status run_sweep(lcd_result *r, hipStream_t st) {
@@ -221,42 +337,74 @@ lcd_status run_sweep(lcd_result *r, hipStream_t st) {
     CHK(plan_tiers(g->dev, g->n, r->prm, tp));
     CHK(prepare_slabs(g, tp, st));
     r->stats = lcd_sweep_stats{};
-    r->stats.lds_capacity = tp.cap0;
-    r->stats.waves_per_block = tp.wpb0;
-    r->stats.grid_blocks = tp.blocks0;
-    hipEvent_t ev[4];
+    r->stats.lds_capacity = tp.t[0].cap;
+    r->stats.waves_per_block = tp.t[0].waves;
+    r->stats.grid_blocks = tp.t[0].blocks;
+    r->stats.tiers = tp.n;
+    for (int k = 0; k < tp.n; ++k) {
+        r->stats.tier_kind[k] = tp.t[k].kind;
+        r->stats.tier_capacity[k] = tp.t[k].cap;
+    }
+    // ev[0 .. n]: before each tier and after the last; ev[kMaxTiers + 1]:
+    // before the work-queue reset
+    hipEvent_t ev[kMaxTiers + 2];
     for (auto &e : ev)
         HIPCHK(hipEventCreate(&e));
+    hipEvent_t &ev_begin = ev[kMaxTiers + 1];
+    hipEvent_t &ev_end = ev[tp.n];
     lcd_status status = LCD_OK;
     for (int attempt = 0; attempt < 8; ++attempt) {
         r->stats.launches = 0;
+        const bool use_graph = r->prm.use_graph != 0 && r->prm.mode == LCD_PERSISTENT && r->n_sets > 0;
+        if (use_graph) {
+            int64_t key[8];
+            capture_key(r, key);
+            if (!r->gexec || std::memcmp(key, r->cap_key, sizeof(key)) != 0)
+                CHK(capture_sweep(r, tp));
+        }
+        r->stats.launches = 0;
+        HIPCHK(hipEventRecord(ev_begin, st));
+        const bool timed = r->n_sets > 0 && r->prm.mode != LCD_PER_SCALE_LOOP && !use_graph;
+        if (use_graph) {
+            // zero fills and every tier, as captured
+            HIPCHK(hipGraphLaunch(r->gexec, st));
+            r->stats.launches = 2 + tp.n;
+            HIPCHK(hipEventRecord(ev_end, st));
+        } else {
         // zero the work queues, the pool cursor and the error word
         HIPCHK(launch_zero_bytes(r->ctl, (int64_t)sizeof(Counters) * r->n_ctl, st));
         HIPCHK(launch_zero_bytes(r->cursor, 8 * kCursorWords, st));
-        HIPCHK(hipEventRecord(ev[3], st));
-        float ms_main = 0.f, ms_spill = 0.f;
         if (r->n_sets > 0) {
             if (r->prm.mode == LCD_PER_SCALE_LOOP) {
                 for (int32_t s = 0; s < r->S; ++s) {
                     CHK(run_group(r, tp, s, s + 1, s, st, nullptr));
                 }
-                HIPCHK(hipEventRecord(ev[2], st));
+                HIPCHK(hipEventRecord(ev_end, st));
             } else {
                 CHK(run_group(r, tp, 0, r->S, 0, st, ev));
             }
         } else {
-            HIPCHK(hipEventRecord(ev[2], st));
+            HIPCHK(hipEventRecord(ev_end, st));
         }
-        HIPCHK(hipEventSynchronize(ev[2]));
+        }
+        HIPCHK(hipEventSynchronize(ev_end));
         unsigned long long cur[kCursorWords] = {};
         HIPCHK(hipMemcpy(cur, r->cursor, 8 * kCursorWords, hipMemcpyDeviceToHost));
         std::vector<Counters> ctl(r->n_ctl);
         HIPCHK(hipMemcpy(ctl.data(), r->ctl, sizeof(Counters) * r->n_ctl, hipMemcpyDeviceToHost));
-        float ms_total = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms_total, ev[3], ev[2]));
-        if (r->n_sets > 0 && r->prm.mode != LCD_PER_SCALE_LOOP) {
+        float ms_total = 0.f, ms_main = 0.f, ms_spill = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms_total, ev_begin, ev_end));
+        for (int k = 0; k < kMaxTiers; ++k)
+            r->stats.ms_tier[k] = 0.0;
+        if (timed) {
             HIPCHK(hipEventElapsedTime(&ms_main, ev[0], ev[1]));
-            HIPCHK(hipEventElapsedTime(&ms_spill, ev[1], ev[2]));
+            if (tp.n > 1)
+                HIPCHK(hipEventElapsedTime(&ms_spill, ev[1], ev_end));
+            for (int k = 0; k < tp.n; ++k) {
+                float x = 0.f;
+                HIPCHK(hipEventElapsedTime(&x, ev[k], ev[k + 1]));
+                r->stats.ms_tier[k] = x;
+            }
         }
         const uint32_t err = (uint32_t)(cur[1] & 0xffffffffu);
         if (err) {
@@ -272,12 +420,12 @@ lcd_status run_sweep(lcd_result *r, hipStream_t st) {
         int64_t sp = 0, spb = 0;
         for (auto &c : ctl) {
             sp += c.ovf_count[0];
-            spb += tp.use1 && tp.use2 ? c.ovf_count[1] : (tp.use2 ? c.ovf_count[0] : 0);
+            spb += tp.n >= 3 ? c.ovf_count[tp.n - 2] : 0;
         }
         r->stats.n_spilled = sp;
         r->stats.n_spilled_big = spb;
         r->stats.pool_used = (int64_t)cur[0];
-        for (int t = 0; t < 3; ++t) {
+        for (int t = 0; t < kMaxTiers; ++t) {
             r->stats.tier[t].rows_gathered = (int64_t)cur[2 + 5 * t];
             r->stats.tier[t].row_entries = (int64_t)cur[3 + 5 * t];
             r->stats.tier[t].entries_created = (int64_t)cur[4 + 5 * t];
@@ -289,6 +437,7 @@ lcd_status run_sweep(lcd_result *r, hipStream_t st) {
         // the pool was too small: grow it and run again
         r->stats.reruns += 1;
         int64_t want = std::max<int64_t>((int64_t)cur[0] + (int64_t)cur[0] / 8 + 1024, 2 * r->pool_cap);
+        drop_graph(r);
         dev_free(r->pool);
         r->pool_cap = 0;
         CHK(dev_alloc(&r->pool, (size_t)want));
@@ -306,6 +455,7 @@ lcd_status run_sweep(lcd_result *r, hipStream_t st) {
 void result_release(lcd_result *r) {
     if (!r)
         return;
+    drop_graph(r);
     dev_free(r->scales);
     dev_free(r->seed_ptr);
     dev_free(r->seed_nodes);
@@ -318,8 +468,8 @@ void result_release(lcd_result *r) {
     dev_free(r->pool);
     dev_free(r->ctl);
     dev_free(r->cursor);
-    dev_free(r->work[0]);
-    dev_free(r->work[1]);
+    for (auto &w : r->work)
+        dev_free(w);
     delete r;
 }
 
@@ -507,6 +657,7 @@ lcd_status lcd_sweep(const lcd_graph *g, const double *scales, int32_t n_scales,
         return fail(LCD_EINVAL, "unknown mode %d", prm.mode);
     if (prm.watchdog_ms == 0)
         prm.watchdog_ms = 20000;
+    apply_tuned(g, prm);
     hipStream_t st = (hipStream_t)stream;
     std::vector<double> sc;
     CHK(fetch(sc, scales, (size_t)n_scales, mem_kind, st));
@@ -563,7 +714,8 @@ lcd_status lcd_sweep(const lcd_graph *g, const double *scales, int32_t n_scales,
         (s = dev_alloc(&r->ctl, (size_t)r->n_ctl)) != LCD_OK ||
         (s = dev_alloc(&r->cursor, kCursorWords)) != LCD_OK ||
         (s = dev_alloc(&r->work[0], (size_t)std::max(n_sets, 1))) != LCD_OK ||
-        (s = dev_alloc(&r->work[1], (size_t)std::max(n_sets, 1))) != LCD_OK) {
+        (s = dev_alloc(&r->work[1], (size_t)std::max(n_sets, 1))) != LCD_OK ||
+        (s = dev_alloc(&r->work[2], (size_t)std::max(n_sets, 1))) != LCD_OK) {
         result_release(r);
         return s;
     }
@@ -587,6 +739,110 @@ lcd_status lcd_sweep(const lcd_graph *g, const double *scales, int32_t n_scales,
         return s;
     }
     *out = r;
+    return LCD_OK;
+}
+
+lcd_status lcd_tune(lcd_graph *g, const double *scales, int32_t n_scales, const int32_t *seed_ptr,
+                    const int32_t *seed_nodes, int32_t n_sets, int32_t mem_kind, const lcd_params *base,
+                    void *stream, lcd_tune_report *report) {
+    if (!g)
+        return fail(LCD_EINVAL, "null graph");
+    if (n_sets < 1 || n_scales < 1)
+        return fail(LCD_EINVAL, "tuning needs at least one seed set and one scale");
+    if (mem_kind != LCD_MEM_HOST && mem_kind != LCD_MEM_DEVICE)
+        return fail(LCD_EINVAL, "unknown mem_kind %d", mem_kind);
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<double> sc;
+    std::vector<int32_t> sp, sn;
+    CHK(fetch(sc, scales, (size_t)n_scales, mem_kind, st));
+    CHK(fetch(sp, seed_ptr, (size_t)n_sets + 1, mem_kind, st));
+    if (sp[0] != 0 || sp[n_sets] < sp[0])
+        return fail(LCD_EINVAL, "malformed seed_ptr");
+    CHK(fetch(sn, seed_nodes, (size_t)sp[n_sets], mem_kind, st));
+    // a deterministic sample: every stride-th seed set, at most ~16k sets
+    const int32_t stride = std::max<int32_t>(1, n_sets / 16384);
+    std::vector<int32_t> sp2{0}, sn2;
+    for (int32_t j = 0; j < n_sets; j += stride) {
+        if (sp[j + 1] < sp[j])
+            return fail(LCD_EINVAL, "seed_ptr decreases at set %d", j);
+        sn2.insert(sn2.end(), sn.begin() + sp[j], sn.begin() + sp[j + 1]);
+        sp2.push_back((int32_t)sn2.size());
+    }
+    const int32_t ns2 = (int32_t)sp2.size() - 1;
+    lcd_params b;
+    lcd_params_default(&b);
+    if (base)
+        b = *base;
+    b.mode = LCD_PERSISTENT;
+    // candidate sizings: {tier-0 table, spill mode, workgroup LDS table, waves per community}
+    static const int32_t cand[][4] = {
+        {256, 0, 1024, 2}, {256, 0, 1024, 4}, {512, 0, 1024, 2}, {512, 0, 1024, 4},
+        {512, 0, 2048, 4}, {1024, 0, 2048, 4}, {256, 2, 0, 8}, {512, 2, 0, 8},
+        {512, 1, 0, 0},    {1024, 1, 0, 0},
+    };
+    const int nc = (int)(sizeof(cand) / sizeof(cand[0]));
+    lcd_tune_report rep{};
+    rep.sample_stride = stride;
+    auto time_one = [&](const lcd_params &q, const std::vector<int32_t> &p_, const std::vector<int32_t> &n_,
+                        int32_t ns, int reps, double *ms) -> lcd_status {
+        double best = 1e300;
+        for (int r = 0; r < reps; ++r) {
+            lcd_result *res = nullptr;
+            CHK(lcd_sweep(g, sc.data(), n_scales, p_.data(), n_.data(), ns, LCD_MEM_HOST, &q, stream, &res));
+            best = std::min(best, res->stats.ms_total);
+            lcd_result_free(res);
+        }
+        *ms = best;
+        return LCD_OK;
+    };
+    int bestc = -1;
+    for (int c = 0; c < nc && c < 16; ++c) {
+        lcd_params q = b;
+        q.lds_capacity = cand[c][0];
+        q.spill_mode = cand[c][1];
+        q.team_capacity = cand[c][2];
+        q.team_waves = cand[c][3];
+        q.waves_per_block = 0;
+        q.blocks_per_cu = 0;
+        double ms = 0.0;
+        CHK(time_one(q, sp2, sn2, ns2, 2, &ms));
+        rep.tried[rep.n_tried] = q;
+        rep.ms[rep.n_tried] = ms;
+        rep.n_tried += 1;
+        if (bestc < 0 || ms < rep.ms[bestc])
+            bestc = c;
+    }
+    // a sampled timing can rank close candidates differently from the full
+    // sweep: when the full sweep is short, re-time the leaders on every set
+    if (stride > 1 && rep.ms[bestc] * stride < 1500.0) {
+        std::vector<int> order(rep.n_tried);
+        for (int i = 0; i < rep.n_tried; ++i)
+            order[i] = i;
+        std::sort(order.begin(), order.end(), [&](int x, int y) { return rep.ms[x] < rep.ms[y]; });
+        double best_full = 1e300;
+        for (int i = 0; i < std::min(3, rep.n_tried); ++i) {
+            double ms = 0.0;
+            CHK(time_one(rep.tried[order[i]], sp, sn, n_sets, 1, &ms));
+            if (ms < best_full) {
+                best_full = ms;
+                bestc = order[i];
+            }
+        }
+        rep.full_checked = 1;
+    }
+    rep.best = rep.tried[bestc];
+    rep.ms_best = rep.ms[bestc];
+    g->tuned_prm = rep.best;
+    g->tuned = true;
+    if (report)
+        *report = rep;
+    return LCD_OK;
+}
+
+lcd_status lcd_graph_untune(lcd_graph *g) {
+    if (!g)
+        return fail(LCD_EINVAL, "null graph");
+    g->tuned = false;
     return LCD_OK;
 }
 
@@ -831,6 +1087,12 @@ lcd_status lcd_result_stats(const lcd_result *r, lcd_sweep_stats *out) {
         return fail(LCD_EINVAL, "null argument");
     *out = r->stats;
     return LCD_OK;
+}
+
+lcd_status lcd_result_rerun(lcd_result *r, void *stream) {
+    if (!r)
+        return fail(LCD_EINVAL, "null result");
+    return run_sweep(r, (hipStream_t)stream);
 }
 
 lcd_status lcd_result_free(lcd_result *r) {

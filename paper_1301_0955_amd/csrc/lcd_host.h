@@ -99,30 +99,55 @@ struct Slab {
 };
 
 // pool cursor, error word, then 5 statistics per tier
-constexpr int kCursorWords = 2 + 5 * 3 + 1;
+constexpr int kCursorWords = 2 + 5 * kMaxTiers;
 
-struct TierPlan {
-    int32_t cap0, hbits0, wpb0, blocks0;
-    int32_t cap1, cap2;
-    bool use1, use2;
+// One tier of the launch chain.
+struct TierSpec {
+    int32_t kind;      // TIER_*
+    int32_t cap;       // table entries per community
+    int32_t hbits;     // hash slots = 2^hbits
+    int32_t waves;     // waves per workgroup
+    int32_t blocks;    // workgroups of an LDS tier (tier 0: the full-size grid)
+    int32_t slots;     // global tiers: tables wanted in the slab
+    int32_t slab;      // global tiers: slab index; -1 for LDS tiers
 };
 
-// LDS table size, waves per block and grid of the LDS tier, and which
-// global-memory tiers a graph of n nodes needs.
+struct TierPlan {
+    int32_t n = 0;
+    TierSpec t[kMaxTiers];
+};
+
+inline int64_t slab_stride(int32_t cap) {
+    return (table_bytes(cap, next_pow2_bits(2 * (int64_t)cap)) + 255) / 256 * 256;
+}
+
+// The tier chain for a graph of n nodes: tier 0 one wave per community with
+// an LDS table (lds_capacity entries), then tiers with larger tables.
+// spill_mode 0: workgroup tiers (LDS table of 4,096 entries, global tables of
+// 16,384 entries, global tables that hold every node); 1: one-wave global
+// tiers (16,384 entries x 4,096 tables, then every node).
 lcd_status plan_tiers(const DevInfo &dev, int32_t n, const lcd_params &p, TierPlan &tp);
 
 // (Re)allocate a slab for cap entries x slots tables and mark every hash
 // slot empty; a clean slab of the same shape is kept as it is.
 lcd_status ensure_slab(Slab &sl, int32_t cap, int32_t slots, hipStream_t st);
 
-// Enqueue one launch group on st: the LDS tier over a.n_sets items with
-// blocks0 workgroups, then every global-memory tier tp enables, each fed by
-// the overflow queue of the tier before it.  ev (3 events, or null) is
-// recorded before the LDS tier, between the tiers and at the end.
+// Enqueue one launch group on st: every tier of tp in order, tier k > 0 fed
+// by the overflow queue work[k - 1] of the tier before it; tier 0 runs with
+// blocks0 workgroups.  ev (3 events, or null) is recorded before tier 0,
+// after it and at the end.
 lcd_status enqueue_tiers(const SweepArgs &a, const TierPlan &tp, int32_t blocks0, Slab *slabs,
-                         int32_t *const work[2], hipStream_t st, hipEvent_t *ev,
-                         int32_t *launches);
+                         int32_t *const *work, hipStream_t st, hipEvent_t *ev, int32_t *launches);
 
+}  // namespace lcd
+
+struct lcd_graph;
+
+namespace lcd {
+// Launch parameters all left at 0: the sizing fields come from the graph's
+// tuned set when lcd_tune() has run on it.
+bool params_are_auto(const lcd_params &p);
+void apply_tuned(const lcd_graph *g, lcd_params &p);
 }  // namespace lcd
 
 struct lcd_graph {
@@ -142,10 +167,9 @@ struct lcd_graph {
     int64_t pool_hint = 0;
     // batch graphs: node and edge offsets of each member graph (host copy)
     std::vector<int64_t> node_off, edge_off;
-    // tuned launch parameters, keyed by the sweep shape they were tuned on
+    // launch sizing chosen by lcd_tune() for this graph
     bool tuned = false;
-    int32_t tuned_n_sets = 0, tuned_S = 0;
-    int32_t tuned_cap = 0, tuned_wpb = 0;
+    lcd_params tuned_prm{};
 };
 
 static inline lcd::GraphDev graph_dev(const lcd_graph *g) {

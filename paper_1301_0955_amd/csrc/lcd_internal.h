@@ -73,7 +73,19 @@ struct SweepArgs {
     int32_t n_slots;          // global tiers: number of tables
     int64_t budget_ticks;     // watchdog: wall-clock ticks one seed set may take
     const double *alpha_set;  // query kernels: one scale per set (S = 1); nullptr for sweeps
+    int32_t kind;             // TIER_* below: which kernel runs this tier
 };
+
+// Table tiers.  A set starts in tier 0 and moves to the next tier (starting
+// over from its seeds) when its table would overflow.
+enum : int32_t {
+    TIER_WAVE_LDS = 0,        // one wave per community, table in LDS
+    TIER_WAVE_GLOBAL = 1,     // one wave per community, table in global memory
+    TIER_TEAM_LDS = 2,        // one workgroup per community, table in LDS
+    TIER_TEAM_GLOBAL = 3      // one workgroup per community, table in global memory
+};
+constexpr int kMaxTiers = 4;
+constexpr int kTeamMaxThreads = 512;
 
 // Bytes per table entry (dense arrays + scratch) and per hash slot.
 constexpr int kEntryBytes = 4 /*node*/ + 4 /*d|flags*/ + 4 /*k*/ + 8 /*rank*/ + 4 /*scratch*/;
@@ -91,6 +103,9 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 hipError_t launch_zero_bytes(void *p, int64_t bytes, hipStream_t st);
 hipError_t launch_sweep(const SweepArgs &a, int32_t blocks, int32_t waves_per_block,
                         hipStream_t st);
+// Resident workgroups per compute unit of a tier kernel (TIER_* kind) at the
+// given waves per workgroup and dynamic LDS bytes.
+hipError_t tier_blocks_per_cu(int32_t kind, int32_t waves, size_t lds_bytes, int32_t *out);
 // readout
 hipError_t launch_scale_scan(const Records &rec, int32_t S, int32_t s, int32_t n_sets,
                              int32_t *comm_ptr, hipStream_t st);

@@ -793,6 +793,644 @@ __global__ void __launch_bounds__(256) query_global_kernel(SweepArgs A) {
 }
 
 // ---------------------------------------------------------------------------
+// Team growth: one workgroup of up to kTeamMaxWaves waves grows one
+// community, for sets whose table outgrew the one-wave tier.  Same exact
+// queue emulation, decisions and outputs as run_wave; every table scan is
+// split over all threads of the workgroup and the per-wave results are
+// combined through LDS.  Every branch that decides how many barriers a
+// thread reaches depends only on values that all threads computed
+// identically or read from LDS after a barrier.
+// ---------------------------------------------------------------------------
+
+constexpr int kTeamMaxWaves = 8;
+
+struct TeamSh {
+    double r[kTeamMaxWaves];
+    int32_t u[kTeamMaxWaves];
+    int32_t i[kTeamMaxWaves];
+    unsigned long long v[kTeamMaxWaves];
+    unsigned long long off;
+    int32_t count;    // dense entries claimed (may pass cap on overflow)
+    int32_t m;        // members gathered for emission
+    int32_t bidx;     // broadcast dense index
+    uint32_t item;
+    uint32_t ovf;
+    uint32_t stop;
+    uint32_t abort;
+};
+
+struct TeamId {
+    int tid, nt, lane, wid, nw;
+};
+
+__device__ __forceinline__ uint64_t team_sum(TeamSh &sh, const TeamId &id, uint64_t v) {
+    v = wave_sum(v);
+    if (id.lane == 0)
+        sh.v[id.wid] = v;
+    __syncthreads();
+    uint64_t s = 0;
+    for (int w = 0; w < id.nw; ++w)
+        s += sh.v[w];
+    __syncthreads();
+    return s;
+}
+
+__device__ __forceinline__ uint32_t team_or(TeamSh &sh, const TeamId &id, uint32_t v) {
+    v = wave_or(v);
+    if (id.lane == 0)
+        sh.v[id.wid] = v;
+    __syncthreads();
+    uint32_t s = 0;
+    for (int w = 0; w < id.nw; ++w)
+        s |= (uint32_t)sh.v[w];
+    __syncthreads();
+    return s;
+}
+
+// Watchdog decided by thread 0 and broadcast, so that all threads leave
+// their loops together.
+__device__ __forceinline__ bool team_over_budget(TeamSh &sh, const TeamId &id, St &st) {
+    __syncthreads();
+    if (id.tid == 0 && wall_clock64() - st.t0 > st.budget)
+        sh.stop = 1u;
+    __syncthreads();
+    if (sh.stop) {
+        st.err |= ERR_TIMEOUT;
+        return true;
+    }
+    return false;
+}
+
+// Dense index of u for every active thread, inserting absent ids (all
+// active ids of one call are distinct).  All probes finish before any
+// insert.  On overflow sh.ovf is set (read it after the call).
+template <bool GLOBAL>
+__device__ int32_t team_ensure(const Tab &t, TeamSh &sh, St &st, const Ctx &c, bool act, int32_t u) {
+    int32_t idx = act ? tab_find<GLOBAL>(t, u, st.err) : -1;
+    __syncthreads();
+    if (act && idx < 0) {
+        const int32_t k = atomicAdd(&sh.count, 1);
+        if (k >= t.cap) {
+            atomicOr(&sh.ovf, 1u);
+        } else {
+            idx = k;
+            t.node[idx] = u;
+            t.kv[idx] = c.kdeg[u];
+            t.dv[idx] = 0u;
+            st.inserted += 1;
+            uint32_t p = hash_of(u, t.hbits);
+            uint32_t it = 0;
+            for (; it <= t.hmask; ++it) {
+                if (atomicCAS(&t.hs[p], -1, idx) == -1)
+                    break;
+                p = (p + 1) & t.hmask;
+            }
+            if (it > t.hmask)
+                st.err |= ERR_PROBE;
+        }
+    }
+    __syncthreads();
+    return idx;
+}
+
+template <bool GLOBAL, int MODE>
+__device__ void team_row(const Tab &t, TeamSh &sh, St &st, const Ctx &c, const TeamId &id, int32_t n) {
+    const int32_t beg = c.row_ptr[n];
+    const int32_t end = c.row_ptr[n + 1];
+    st.rows += 1;
+    st.row_len += (uint64_t)(end - beg);
+    for (int32_t base = beg; base < end; base += id.nt) {
+        const int32_t j = base + id.tid;
+        const bool act = j < end;
+        const int32_t u = act ? c.col[j] : 0;
+        const int32_t wt = act ? (c.w ? (int32_t)c.w[j] : 1) : 0;
+        int32_t idx;
+        if constexpr (MODE == ROW_REMOVE) {
+            idx = act ? tab_find<GLOBAL>(t, u, st.err) : -1;
+            if (act && idx < 0)
+                st.err |= ERR_MISSING;
+        } else {
+            idx = team_ensure<GLOBAL>(t, sh, st, c, act, u);
+            if (sh.ovf) {
+                st.ovf = true;
+                return;
+            }
+        }
+        if (act && idx >= 0) {
+            const uint32_t v = t.dv[idx];
+            int32_t d = (int32_t)(v & kDMask);
+            if constexpr (MODE == ROW_REMOVE) {
+                d -= wt;
+                t.dv[idx] = (v & ~kDMask) | (uint32_t)d;
+            } else if constexpr (MODE == ROW_INIT) {
+                d += wt;
+                t.dv[idx] = (v & ~kDMask) | (uint32_t)d;
+            } else {
+                d += wt;
+                if (v & kMember) {
+                    t.dv[idx] = (v & ~kDMask) | (uint32_t)d;
+                } else {
+                    const bool queued = (v & kLive) && !before(t.rk[idx], u, st.pr, st.pu);
+                    if (!queued)
+                        st.Gl += 1;
+                    const int32_t k = t.kv[idx];
+                    t.rk[idx] = rank_of(c, d, k, st.alpha);
+                    st.Rl += 1;
+                    t.dv[idx] = (uint32_t)d | kLive | kFresh;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    st.count = min(sh.count, t.cap);
+}
+
+// Block argmax of (rank, -id); also reads d|flags and k of the winner
+// before the closing barrier, so that thread 0 may update the winner's flags
+// right after it without another barrier.
+__device__ __forceinline__ void team_pick_max(TeamSh &sh, const TeamId &id, const Tab &t, double &r,
+                                              int32_t &u, int32_t &i, uint32_t &v, int32_t &k) {
+    wave_argmax(r, u, i);
+    if (id.lane == 0) {
+        sh.r[id.wid] = r;
+        sh.u[id.wid] = u;
+        sh.i[id.wid] = i;
+    }
+    __syncthreads();
+    r = sh.r[0];
+    u = sh.u[0];
+    i = sh.i[0];
+    for (int w = 1; w < id.nw; ++w) {
+        if (before(sh.r[w], sh.u[w], r, u)) {
+            r = sh.r[w];
+            u = sh.u[w];
+            i = sh.i[w];
+        }
+    }
+    if (i >= 0) {
+        v = t.dv[i];
+        k = t.kv[i];
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void team_pick_min(TeamSh &sh, const TeamId &id, const Tab &t, int32_t &u,
+                                              int32_t &i, uint32_t &v, int32_t &k) {
+    wave_argmin(u, i);
+    if (id.lane == 0) {
+        sh.u[id.wid] = u;
+        sh.i[id.wid] = i;
+    }
+    __syncthreads();
+    u = sh.u[0];
+    i = sh.i[0];
+    for (int w = 1; w < id.nw; ++w) {
+        if (sh.u[w] < u) {
+            u = sh.u[w];
+            i = sh.i[w];
+        }
+    }
+    if (i >= 0) {
+        v = t.dv[i];
+        k = t.kv[i];
+    }
+    __syncthreads();
+}
+
+// Entries each thread loads ahead in a table scan (independent loads in
+// flight per thread; the scans are latency-bound).
+constexpr int kScanAhead = 4;
+
+// One call of the growth function (Algorithm 1) by the whole workgroup.
+template <bool GLOBAL>
+__device__ int64_t team_grow(const Tab &t, TeamSh &sh, St &st, const Ctx &c, const TeamId &id,
+                             uint32_t k_prune) {
+    int64_t moves = 0;
+    bool creation = true;
+    for (;;) {
+        double br = -__builtin_huge_val();
+        int32_t bu = INT32_MAX;
+        int32_t bi = -1;
+        for (int32_t base = id.tid; base < st.count; base += kScanAhead * id.nt) {
+            uint32_t vv[kScanAhead];
+            double rr[kScanAhead];
+            int32_t nn[kScanAhead], kk[kScanAhead];
+#pragma unroll
+            for (int q = 0; q < kScanAhead; ++q) {
+                const int32_t i = base + q * id.nt;
+                vv[q] = 0u;
+                rr[q] = 0.0;
+                nn[q] = 0;
+                kk[q] = 0;
+                if (i < st.count) {
+                    vv[q] = t.dv[i];
+                    rr[q] = t.rk[i];
+                    nn[q] = t.node[i];
+                    kk[q] = t.kv[i];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kScanAhead; ++q) {
+                const int32_t i = base + q * id.nt;
+                if (i >= st.count)
+                    continue;
+                uint32_t v = vv[q];
+                double r = rr[q];
+                if (creation) {
+                    // the queue is built from every non-member with a link into c
+                    if ((v & kMember) || (v & kDMask) == 0) {
+                        if (v & (kLive | kFresh))
+                            t.dv[i] = v & ~(kLive | kFresh);
+                        continue;
+                    }
+                    r = rank_of(c, (int32_t)(v & kDMask), kk[q], st.alpha);
+                    t.rk[i] = r;
+                    st.Rl += 1;
+                    st.Gl += 1;
+                    v = (v | kLive) & ~kFresh;
+                    t.dv[i] = v;
+                } else {
+                    if (!(v & kLive))
+                        continue;
+                    if (v & kFresh) {
+                        v &= ~kFresh;
+                        t.dv[i] = v;
+                    } else if (before(r, nn[q], st.pr, st.pu)) {
+                        t.dv[i] = v & ~kLive;      // popped and rejected last step
+                        continue;
+                    }
+                }
+                if (before(r, nn[q], br, bu) && improves_add(st, (int32_t)(v & kDMask), kk[q])) {
+                    br = r;
+                    bu = nn[q];
+                    bi = i;
+                }
+            }
+        }
+        creation = false;
+        uint32_t v = 0;
+        int32_t k = 0;
+        team_pick_max(sh, id, t, br, bu, bi, v, k);
+        if (bi < 0)
+            break;
+        // add the best improving node; no thread reads its flags again
+        // before the barriers of the row update below
+        const int32_t d = (int32_t)(v & kDMask);
+        if (id.tid == 0)
+            t.dv[bi] = (v | kMember) & ~(kLive | kFresh);
+        st.K += 2 * (int64_t)d;
+        st.V += k;
+        st.nmem += 1;
+        st.M += 1;
+        moves += 1;
+        st.pr = br;
+        st.pu = bu;
+        set_logs(st);
+        team_row<GLOBAL, ROW_ADD>(t, sh, st, c, id, bu);
+        if (st.ovf)
+            return moves;
+        if ((int64_t)st.M > st.move_limit) {
+            st.err |= ERR_LIMIT;
+            return moves;
+        }
+        if ((st.M & 15) == 0 && team_over_budget(sh, id, st))
+            return moves;
+    }
+    if (moves == 0)
+        return 0;
+    // removal passes over the members in ascending id
+    for (uint32_t pass = 0; k_prune == 0 || pass < k_prune; ++pass) {
+        st.Gu += (uint64_t)st.nmem;
+        int32_t cursor = -1;
+        bool removed = false;
+        for (;;) {
+            int32_t cu = INT32_MAX;
+            int32_t ci = -1;
+            for (int32_t base = id.tid; base < st.count; base += kScanAhead * id.nt) {
+                uint32_t vv[kScanAhead];
+                int32_t nn[kScanAhead], kk[kScanAhead];
+#pragma unroll
+                for (int q = 0; q < kScanAhead; ++q) {
+                    const int32_t i = base + q * id.nt;
+                    vv[q] = 0u;
+                    nn[q] = 0;
+                    kk[q] = 0;
+                    if (i < st.count) {
+                        vv[q] = t.dv[i];
+                        nn[q] = t.node[i];
+                        kk[q] = t.kv[i];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < kScanAhead; ++q) {
+                    const int32_t i = base + q * id.nt;
+                    if (i >= st.count || !(vv[q] & kMember))
+                        continue;
+                    const int32_t u = nn[q];
+                    if (u <= cursor || u >= cu)
+                        continue;
+                    if (improves_remove(st, (int32_t)(vv[q] & kDMask), kk[q])) {
+                        cu = u;
+                        ci = i;
+                    }
+                }
+            }
+            uint32_t v = 0;
+            int32_t k = 0;
+            team_pick_min(sh, id, t, cu, ci, v, k);
+            if (ci < 0)
+                break;
+            const int32_t d = (int32_t)(v & kDMask);
+            if (id.tid == 0)
+                t.dv[ci] = v & ~kMember;
+            st.K -= 2 * (int64_t)d;
+            st.V -= k;
+            st.nmem -= 1;
+            st.M += 1;
+            moves += 1;
+            set_logs(st);
+            team_row<GLOBAL, ROW_REMOVE>(t, sh, st, c, id, cu);
+            removed = true;
+            cursor = cu;
+            if ((int64_t)st.M > st.move_limit) {
+                st.err |= ERR_LIMIT;
+                return moves;
+            }
+            if ((st.M & 15) == 0 && team_over_budget(sh, id, st))
+                return moves;
+        }
+        if (!removed)
+            break;
+    }
+    return moves;
+}
+
+// Ascending sort of a[0..m) by the workgroup (same network as wave_sort).
+__device__ void team_sort(int32_t *a, int32_t m, const TeamId &id) {
+    int32_t P = 1;
+    while (P < m)
+        P <<= 1;
+    const int32_t half_n = P >> 1;
+    for (int32_t k = 2; k <= P; k <<= 1) {
+        const int32_t hk = k >> 1;
+        for (int32_t q = id.tid; q < half_n; q += id.nt) {
+            const int32_t blk = q / hk;
+            const int32_t off = q - blk * hk;
+            const int32_t i = blk * k + off;
+            const int32_t l = blk * k + k - 1 - off;
+            if (l < m) {
+                const int32_t x = a[i], y = a[l];
+                if (x > y) {
+                    a[i] = y;
+                    a[l] = x;
+                }
+            }
+        }
+        __syncthreads();
+        for (int32_t j = k >> 2; j >= 1; j >>= 1) {
+            for (int32_t q = id.tid; q < half_n; q += id.nt) {
+                const int32_t i = (q / j) * 2 * j + (q % j);
+                const int32_t l = i + j;
+                if (l < m) {
+                    const int32_t x = a[i], y = a[l];
+                    if (x > y) {
+                        a[i] = y;
+                        a[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <bool GLOBAL, bool PERSET>
+__device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh) {
+    TeamId id;
+    id.tid = (int)threadIdx.x;
+    id.nt = (int)blockDim.x;
+    id.lane = id.tid & 63;
+    id.wid = id.tid >> 6;
+    id.nw = id.nt >> 6;
+    Ctx c;
+    c.row_ptr = A.g.row_ptr;
+    c.col = A.g.col;
+    c.w = A.g.w;
+    c.kdeg = A.g.kdeg;
+    c.logtab = A.g.logtab;
+    c.logtab_last = A.g.logtab_n - 1;
+    const uint32_t n_items = A.tier == 0 ? (uint32_t)A.n_sets : A.ctl->ovf_count[A.in_from];
+    for (;;) {
+        __syncthreads();
+        if (id.tid == 0) {
+            sh.item = atomicAdd(&A.ctl->work_next[A.tier], 1u);
+            sh.abort = __hip_atomic_load(A.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_TIMEOUT;
+            sh.count = 0;
+            sh.ovf = 0u;
+            sh.stop = 0u;
+        }
+        if constexpr (!GLOBAL) {
+            for (uint32_t i = id.tid; i <= t.hmask; i += id.nt)
+                t.hs[i] = -1;
+        }
+        __syncthreads();
+        const uint32_t item = sh.item;
+        if (item >= n_items || sh.abort)
+            break;
+        const int32_t set = A.tier == 0 ? (int32_t)item : A.work_in[item];
+
+        St st;
+        st.count = 0;
+        st.nmem = 0;
+        st.K = 0;
+        st.V = 0;
+        st.LK = st.LV = 0.0;
+        st.alpha = 0.0;
+        st.pr = 0.0;
+        st.pu = 0;
+        st.Gl = st.Rl = 0;
+        st.Gu = 0;
+        st.M = 0;
+        st.ovf = false;
+        st.err = 0;
+        st.move_limit = 8 * (int64_t)A.g.n + 65536;
+        st.t0 = wall_clock64();
+        st.budget = (uint64_t)A.budget_ticks;
+        st.rows = st.row_len = st.inserted = st.written = 0;
+
+        const int32_t *init = nullptr;
+        int32_t n_init = 0;
+        bool bad = false;
+        if (A.resume) {
+            const int64_t r = (int64_t)set * A.S + (A.s_begin - 1);
+            const int64_t off = A.rec.off[r];
+            n_init = A.rec.cnt[r];
+            if (off < 0 || off + n_init > A.pool_cap)
+                bad = true;
+            else
+                init = A.pool + off;
+        } else {
+            init = A.seed_nodes + A.seed_ptr[set];
+            n_init = A.seed_ptr[set + 1] - A.seed_ptr[set];
+        }
+        for (int32_t q = 0; q < n_init && !bad; ++q) {
+            const int32_t u = init[q];
+            const int32_t idx = team_ensure<GLOBAL>(t, sh, st, c, id.tid == 0, u);
+            if (sh.ovf) {
+                st.ovf = true;
+                break;
+            }
+            if (id.tid == 0)
+                sh.bidx = idx;
+            __syncthreads();
+            const int32_t i0 = sh.bidx;
+            const uint32_t v = t.dv[i0];
+            __syncthreads();
+            if (id.tid == 0)
+                t.dv[i0] = v | kMember;
+            st.K += 2 * (int64_t)(v & kDMask);
+            st.V += c.kdeg[u];
+            st.nmem += 1;
+            st.count = min(sh.count, t.cap);
+            __syncthreads();
+            team_row<GLOBAL, ROW_INIT>(t, sh, st, c, id, u);
+            if (st.ovf)
+                break;
+        }
+        st.err = team_or(sh, id, st.err);
+
+        int64_t last_off = -1;
+        int32_t last_cnt = 0;
+        for (int32_t s = A.s_begin; s < A.s_end && !st.ovf && !bad && !st.err; ++s) {
+            if constexpr (PERSET)
+                st.alpha = A.alpha_set[set];
+            else
+                st.alpha = A.scales[s];
+            set_logs(st);
+            st.Gl = st.Rl = 0;
+            st.Gu = 0;
+            st.M = 0;
+            uint64_t calls = 0;
+            int64_t moved = 0;
+            for (;;) {
+                calls += 1;
+                const int64_t mv = team_grow<GLOBAL>(t, sh, st, c, id, A.k_prune);
+                st.err = team_or(sh, id, st.err);
+                moved += mv;
+                if (st.ovf || st.err || mv == 0)
+                    break;
+                if ((int64_t)calls > st.move_limit) {
+                    st.err |= ERR_LIMIT;
+                    break;
+                }
+                if (team_over_budget(sh, id, st))
+                    break;
+            }
+            if (st.ovf || st.err)
+                break;
+            const int64_t r = (int64_t)set * A.S + s;
+            const uint64_t G = team_sum(sh, id, (uint64_t)st.Gl) + st.Gu;
+            const uint64_t R = team_sum(sh, id, (uint64_t)st.Rl);
+            if (s == A.s_begin || moved > 0) {
+                if (id.tid == 0)
+                    sh.m = 0;
+                __syncthreads();
+                for (int32_t i = id.tid; i < st.count; i += id.nt) {
+                    if (t.dv[i] & kMember) {
+                        const int32_t p = atomicAdd(&sh.m, 1);
+                        t.scr[p] = t.node[i];
+                    }
+                }
+                __syncthreads();
+                const int32_t m = sh.m;
+                team_sort(t.scr, m, id);
+                if (id.tid == 0)
+                    sh.off = atomicAdd(A.pool_cursor, (unsigned long long)m);
+                __syncthreads();
+                const unsigned long long off = sh.off;
+                if ((int64_t)off + m <= A.pool_cap) {
+                    for (int32_t i = id.tid; i < m; i += id.nt)
+                        A.pool[off + i] = t.scr[i];
+                }
+                last_off = (int64_t)off;
+                last_cnt = m;
+                st.written += (uint64_t)m;
+                __syncthreads();
+            }
+            if (id.tid == 0) {
+                A.rec.off[r] = last_off;
+                A.rec.cnt[r] = last_cnt;
+                A.rec.K[r] = st.K;
+                A.rec.V[r] = st.V;
+                A.rec.f[r] = st.K == 0 ? 0.0 : (double)st.K / pow((double)st.V, st.alpha);
+                A.rec.ctr[4 * r + 0] = G;
+                A.rec.ctr[4 * r + 1] = R;
+                A.rec.ctr[4 * r + 2] = st.M;
+                A.rec.ctr[4 * r + 3] = calls;
+            }
+        }
+        const uint64_t inserted = team_sum(sh, id, st.inserted);
+        if (id.tid == 0) {
+            if (st.ovf) {
+                if (A.work_out) {
+                    const uint32_t pos = atomicAdd(&A.ctl->ovf_count[A.tier], 1u);
+                    A.work_out[pos] = set;
+                } else {
+                    atomicOr(A.err, ERR_CAPACITY);
+                }
+            }
+            if (st.err)
+                atomicOr(A.err, st.err);
+            if (!st.ovf) {
+                unsigned long long *sx = A.stat + 5 * A.tier;
+                atomicAdd(&sx[0], (unsigned long long)st.rows);
+                atomicAdd(&sx[1], (unsigned long long)st.row_len);
+                atomicAdd(&sx[2], (unsigned long long)inserted);
+                atomicAdd(&sx[3], (unsigned long long)st.written);
+                atomicAdd(&sx[4], 1ull);
+            }
+        }
+        if constexpr (GLOBAL) {
+            // leave the slab's hash empty for the next community
+            const int32_t cnt = min(sh.count, t.cap);
+            for (int32_t i = id.tid; i < cnt; i += id.nt) {
+                uint32_t p = hash_of(t.node[i], t.hbits);
+                for (uint32_t it = 0; it <= t.hmask; ++it) {
+                    if (hs_load<GLOBAL>(&t.hs[p]) == i) {
+                        hs_store<GLOBAL>(&t.hs[p], -1);
+                        break;
+                    }
+                    p = (p + 1) & t.hmask;
+                }
+            }
+        }
+    }
+}
+
+template <bool PERSET>
+__device__ __forceinline__ void team_lds_entry(const SweepArgs &A) {
+    extern __shared__ __align__(16) char smem[];
+    __shared__ TeamSh sh;
+    Tab t = carve(smem, A.cap, A.hbits);
+    run_team<false, PERSET>(A, t, sh);
+}
+
+template <bool PERSET>
+__device__ __forceinline__ void team_global_entry(const SweepArgs &A) {
+    __shared__ TeamSh sh;
+    const int slot = blockIdx.x;
+    if (slot >= A.n_slots)
+        return;
+    Tab t = carve(A.gtab + (int64_t)slot * A.gtab_stride, A.cap, A.hbits);
+    run_team<true, PERSET>(A, t, sh);
+}
+
+__global__ void __launch_bounds__(512) sweep_team_lds_kernel(SweepArgs A) { team_lds_entry<false>(A); }
+__global__ void __launch_bounds__(512) sweep_team_global_kernel(SweepArgs A) { team_global_entry<false>(A); }
+__global__ void __launch_bounds__(512) query_team_lds_kernel(SweepArgs A) { team_lds_entry<true>(A); }
+__global__ void __launch_bounds__(512) query_team_global_kernel(SweepArgs A) { team_global_entry<true>(A); }
+
+// ---------------------------------------------------------------------------
 // Graph preparation
 // ---------------------------------------------------------------------------
 __global__ void degrees_kernel(const int32_t *row_ptr, const uint8_t *w, int32_t *kdeg, int32_t n) {
@@ -1070,15 +1708,51 @@ hipError_t launch_sweep(const SweepArgs &a, int32_t blocks, int32_t waves_per_bl
     const bool q = a.alpha_set != nullptr;
     if (q && (a.S != 1 || a.s_begin != 0 || a.s_end != 1 || a.resume))
         return hipErrorInvalidValue;
-    if (a.tier == 0) {
+    const dim3 grid(blocks), block(64 * waves_per_block);
+    switch (a.kind) {
+    case TIER_WAVE_LDS: {
+        if (waves_per_block < 1 || waves_per_block > 4)
+            return hipErrorInvalidValue;
         const size_t smem = (size_t)waves_per_block * (size_t)table_bytes(a.cap, a.hbits);
-        hipLaunchKernelGGL(q ? query_lds_kernel : sweep_lds_kernel, dim3(blocks),
-                           dim3(64 * waves_per_block), smem, st, a);
-    } else {
-        hipLaunchKernelGGL(q ? query_global_kernel : sweep_global_kernel, dim3(blocks),
-                           dim3(64 * waves_per_block), 0, st, a);
+        hipLaunchKernelGGL(q ? query_lds_kernel : sweep_lds_kernel, grid, block, smem, st, a);
+        break;
+    }
+    case TIER_WAVE_GLOBAL:
+        if (waves_per_block < 1 || waves_per_block > 4 || a.gtab == nullptr)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(q ? query_global_kernel : sweep_global_kernel, grid, block, 0, st, a);
+        break;
+    case TIER_TEAM_LDS: {
+        if (waves_per_block < 1 || 64 * waves_per_block > kTeamMaxThreads)
+            return hipErrorInvalidValue;
+        const size_t smem = (size_t)table_bytes(a.cap, a.hbits);
+        hipLaunchKernelGGL(q ? query_team_lds_kernel : sweep_team_lds_kernel, grid, block, smem, st, a);
+        break;
+    }
+    case TIER_TEAM_GLOBAL:
+        if (waves_per_block < 1 || 64 * waves_per_block > kTeamMaxThreads || a.gtab == nullptr)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(q ? query_team_global_kernel : sweep_team_global_kernel, grid, block, 0, st, a);
+        break;
+    default:
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t tier_blocks_per_cu(int32_t kind, int32_t waves, size_t lds_bytes, int32_t *out) {
+    const void *f = nullptr;
+    switch (kind) {
+    case TIER_WAVE_LDS: f = reinterpret_cast<const void *>(&sweep_lds_kernel); break;
+    case TIER_WAVE_GLOBAL: f = reinterpret_cast<const void *>(&sweep_global_kernel); break;
+    case TIER_TEAM_LDS: f = reinterpret_cast<const void *>(&sweep_team_lds_kernel); break;
+    case TIER_TEAM_GLOBAL: f = reinterpret_cast<const void *>(&sweep_team_global_kernel); break;
+    default: return hipErrorInvalidValue;
+    }
+    int nb = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64 * waves, lds_bytes);
+    *out = nb;
+    return e;
 }
 
 hipError_t launch_scale_scan(const Records &rec, int32_t S, int32_t s, int32_t n_sets,

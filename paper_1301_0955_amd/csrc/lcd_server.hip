@@ -92,7 +92,7 @@ struct Lane {
     int32_t *pool = nullptr;
     Counters *ctl = nullptr;
     unsigned long long *cursor = nullptr;
-    int32_t *work[2] = {nullptr, nullptr};
+    int32_t *work[kMaxTiers - 1] = {nullptr, nullptr, nullptr};
     Slab slab[2];
     // pinned host staging
     double *h_alpha = nullptr;
@@ -125,8 +125,8 @@ void lane_release(Lane &L) {
     dev_free(L.pool);
     dev_free(L.ctl);
     dev_free(L.cursor);
-    dev_free(L.work[0]);
-    dev_free(L.work[1]);
+    for (auto &w : L.work)
+        dev_free(w);
     dev_free(L.slab[0].buf);
     dev_free(L.slab[1].buf);
     host_free(L.h_alpha);
@@ -197,10 +197,11 @@ lcd_status launch_lane(lcd_server *S, Lane &L) {
     HIPCHK(hipMemcpyAsync(L.seed_nodes, L.h_seed_nodes, sizeof(int32_t) * pos, hipMemcpyHostToDevice, st));
     HIPCHK(launch_zero_bytes(L.ctl, (int64_t)sizeof(Counters), st));
     HIPCHK(launch_zero_bytes(L.cursor, 8 * kCursorWords, st));
-    if (S->tp.use1)
-        CHK(ensure_slab(L.slab[0], L.slab[0].cap, L.slab[0].slots, st));
-    if (S->tp.use2)
-        CHK(ensure_slab(L.slab[1], L.slab[1].cap, L.slab[1].slots, st));
+    for (int k = 0; k < S->tp.n; ++k)
+        if (S->tp.t[k].slab >= 0) {
+            Slab &sl = L.slab[S->tp.t[k].slab];
+            CHK(ensure_slab(sl, sl.cap, sl.slots, st));
+        }
     SweepArgs a{};
     a.g = graph_dev(g);
     a.scales = L.alpha;
@@ -221,7 +222,8 @@ lcd_status launch_lane(lcd_server *S, Lane &L) {
     a.err = (uint32_t *)(L.cursor + 1);
     a.stat = L.cursor + 2;
     a.budget_ticks = S->prm.watchdog_ms < 0 ? 0 : g->dev.wall_khz * (int64_t)S->prm.watchdog_ms;
-    const int32_t blocks0 = std::min<int32_t>(S->tp.blocks0, (nq + S->tp.wpb0 - 1) / S->tp.wpb0);
+    const TierSpec &T0 = S->tp.t[0];
+    const int32_t blocks0 = std::min<int32_t>(T0.blocks, (nq + T0.waves - 1) / T0.waves);
     int32_t launches = 0;
     CHK(enqueue_tiers(a, S->tp, blocks0, L.slab, L.work, st, nullptr, &launches));
     HIPCHK(hipMemcpyAsync(L.h_off, L.rec.off, sizeof(int64_t) * nq, hipMemcpyDeviceToHost, st));
@@ -412,7 +414,7 @@ void worker_main(lcd_server *S) {
 }
 
 lcd_status lane_init(lcd_server *S, Lane &L, int id, int32_t max_q, int64_t max_seed,
-                     int64_t pool_cap, int32_t slots1, int32_t slots2) {
+                     int64_t pool_cap, const int32_t *slots) {
     L.id = id;
     L.max_q = max_q;
     L.max_seed = max_seed;
@@ -431,8 +433,8 @@ lcd_status lane_init(lcd_server *S, Lane &L, int id, int32_t max_q, int64_t max_
     CHK(dev_alloc(&L.pool, (size_t)pool_cap));
     CHK(dev_alloc(&L.ctl, 1));
     CHK(dev_alloc(&L.cursor, kCursorWords));
-    CHK(dev_alloc(&L.work[0], max_q));
-    CHK(dev_alloc(&L.work[1], max_q));
+    for (auto &w : L.work)
+        CHK(dev_alloc(&w, max_q));
     CHK(host_alloc(&L.h_alpha, max_q));
     CHK(host_alloc(&L.h_seed_ptr, (size_t)max_q + 1));
     CHK(host_alloc(&L.h_seed_nodes, (size_t)max_seed));
@@ -444,10 +446,9 @@ lcd_status lane_init(lcd_server *S, Lane &L, int id, int32_t max_q, int64_t max_
     CHK(host_alloc(&L.h_ctr, 4 * (size_t)max_q));
     CHK(host_alloc(&L.h_cursor, kCursorWords));
     CHK(host_alloc(&L.h_pool, (size_t)pool_cap));
-    if (S->tp.use1)
-        CHK(ensure_slab(L.slab[0], S->tp.cap1, slots1, L.st));
-    if (S->tp.use2)
-        CHK(ensure_slab(L.slab[1], S->tp.cap2, slots2, L.st));
+    for (int k = 0; k < S->tp.n; ++k)
+        if (S->tp.t[k].slab >= 0)
+            CHK(ensure_slab(L.slab[S->tp.t[k].slab], S->tp.t[k].cap, slots[S->tp.t[k].slab], L.st));
     HIPCHK(hipStreamSynchronize(L.st));
     return LCD_OK;
 }
@@ -499,6 +500,8 @@ lcd_status lcd_server_create(const lcd_graph *g, int64_t mem_budget, int32_t max
     S->prm = prm;
     S->max_slots = max_slots;
     S->mem_budget = mem_budget;
+    apply_tuned(g, prm);
+    S->prm = prm;
     lcd_status s = plan_tiers(g->dev, g->n, prm, S->tp);
     if (s != LCD_OK) {
         delete S;
@@ -510,34 +513,40 @@ lcd_status lcd_server_create(const lcd_graph *g, int64_t mem_budget, int32_t max
     const int32_t max_q = std::max<int32_t>(1, std::min<int32_t>(256, max_slots));
     const int64_t max_seed = std::max<int64_t>(65536, (int64_t)g->n);
     const int64_t pool_cap = std::max<int64_t>((int64_t)g->n, 1 << 20);
-    const int64_t tb1 = S->tp.use1 ? (table_bytes(S->tp.cap1, next_pow2_bits(2 * (int64_t)S->tp.cap1)) + 255) / 256 * 256 : 0;
-    const int64_t tb2 = S->tp.use2 ? (table_bytes(S->tp.cap2, next_pow2_bits(2 * (int64_t)S->tp.cap2)) + 255) / 256 * 256 : 0;
+    // global-memory tables of the spill tiers: one of each per lane at least,
+    // then what the budget allows (half for the first global tier)
+    int64_t tb[2] = {0, 0};
+    for (int k = 0; k < S->tp.n; ++k)
+        if (S->tp.t[k].slab >= 0)
+            tb[S->tp.t[k].slab] = slab_stride(S->tp.t[k].cap);
     const int64_t fixed = lane_bytes(max_q, max_seed, pool_cap);
     const int64_t per_lane = mem_budget / n_lanes;
-    const int64_t left = per_lane - fixed - tb1 - tb2;
+    const int64_t left = per_lane - fixed - tb[0] - tb[1];
     if (left < 0) {
         delete S;
         return fail(LCD_ENOMEM, "mem_budget %lld is below the %lld bytes four lanes need on this graph",
-                    (long long)mem_budget, (long long)(n_lanes * (fixed + tb1 + tb2)));
+                    (long long)mem_budget, (long long)(n_lanes * (fixed + tb[0] + tb[1])));
     }
-    // spend what is left on more spill tables: first tier, then the largest
-    int32_t slots1 = S->tp.use1 ? (int32_t)std::min<int64_t>(256, 1 + (left / 2) / std::max<int64_t>(tb1, 1)) : 0;
-    int64_t left2 = left - (S->tp.use1 ? (slots1 - 1) * tb1 : 0);
-    int32_t slots2 = S->tp.use2 ? (int32_t)std::min<int64_t>(8, 1 + left2 / std::max<int64_t>(tb2, 1)) : 0;
+    int32_t slots[2] = {0, 0};
+    if (tb[0])
+        slots[0] = (int32_t)std::min<int64_t>(256, 1 + (left / 2) / tb[0]);
+    const int64_t left2 = left - (tb[0] ? (slots[0] - 1) * tb[0] : 0);
+    if (tb[1])
+        slots[1] = (int32_t)std::min<int64_t>(32, 1 + left2 / tb[1]);
     S->lanes.resize(n_lanes);
     for (int i = 0; i < n_lanes; ++i) {
-        s = lane_init(S, S->lanes[i], i, max_q, max_seed, pool_cap, slots1, slots2);
+        s = lane_init(S, S->lanes[i], i, max_q, max_seed, pool_cap, slots);
         if (s != LCD_OK) {
             server_release(S);
             return s;
         }
     }
-    S->mem_held = n_lanes * (fixed + (int64_t)slots1 * tb1 + (int64_t)slots2 * tb2);
+    S->mem_held = n_lanes * (fixed + (int64_t)slots[0] * tb[0] + (int64_t)slots[1] * tb[1]);
     S->stats.lanes = n_lanes;
     S->stats.max_slots = max_slots;
     S->stats.mem_held = S->mem_held;
-    S->stats.spill_tables[0] = slots1;
-    S->stats.spill_tables[1] = slots2;
+    S->stats.spill_tables[0] = slots[0];
+    S->stats.spill_tables[1] = slots[1];
     try {
         S->worker = std::thread(worker_main, S);
     } catch (...) {

@@ -36,7 +36,8 @@ class lcd_params(ctypes.Structure):
                 ("lds_capacity", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("pool_hint", ctypes.c_int64), ("watchdog_ms", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("spill_mode", ctypes.c_int32), ("team_capacity", ctypes.c_int32),
+                ("team_waves", ctypes.c_int32)]
 
 
 class lcd_tier_stats(ctypes.Structure):
@@ -54,13 +55,27 @@ class lcd_sweep_stats(ctypes.Structure):
                 ("n_spilled_big", ctypes.c_int64), ("pool_used", ctypes.c_int64),
                 ("reruns", ctypes.c_int32), ("lds_capacity", ctypes.c_int32),
                 ("waves_per_block", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
-                ("launches", ctypes.c_int32), ("pad", ctypes.c_int32),
-                ("tier", lcd_tier_stats * 3)]
+                ("launches", ctypes.c_int32), ("tiers", ctypes.c_int32),
+                ("tier", lcd_tier_stats * 4), ("ms_tier", ctypes.c_double * 4),
+                ("tier_kind", ctypes.c_int32 * 4), ("tier_capacity", ctypes.c_int32 * 4)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("pad", "tier")}
+        arrays = ("tier", "ms_tier", "tier_kind", "tier_capacity")
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in arrays}
         d["tier"] = [t.as_dict() for t in self.tier]
+        for k in arrays[1:]:
+            d[k] = list(getattr(self, k))
         return d
+
+
+class lcd_tune_report(ctypes.Structure):
+    _fields_ = [("best", lcd_params), ("ms_best", ctypes.c_double), ("n_tried", ctypes.c_int32),
+                ("sample_stride", ctypes.c_int32), ("full_checked", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("ms", ctypes.c_double * 16), ("tried", lcd_params * 16)]
+
+
+def _params_dict(p: lcd_params) -> dict:
+    return {k: getattr(p, k) for k, _ in lcd_params._fields_}
 
 
 class lcd_query_info(ctypes.Structure):
@@ -117,6 +132,7 @@ def library() -> ctypes.CDLL:
         "lcd_result_sets": (st, [P, P, ctypes.c_int32, P, P, P, ctypes.c_int64,
                                  ctypes.POINTER(ctypes.c_int64), P, P, P, P]),
         "lcd_result_free": (st, [P]),
+        "lcd_result_rerun": (st, [P, P]),
         "lcd_log_device": (st, [P, P, ctypes.c_int64, P]),
         "lcd_device_info": (st, [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
                                  ctypes.POINTER(ctypes.c_int64), ctypes.c_char_p, ctypes.c_int32]),
@@ -129,6 +145,9 @@ def library() -> ctypes.CDLL:
         "lcd_server_wait": (st, [P, ctypes.c_uint64, ctypes.c_int32]),
         "lcd_server_get_stats": (st, [P, ctypes.POINTER(lcd_server_stats)]),
         "lcd_server_destroy": (st, [P]),
+        "lcd_tune": (st, [P, P, ctypes.c_int32, P, P, ctypes.c_int32, ctypes.c_int32,
+                          ctypes.POINTER(lcd_params), P, ctypes.POINTER(lcd_tune_report)]),
+        "lcd_graph_untune": (st, [P]),
         "lcd_last_error": (ctypes.c_char_p, []),
         "lcd_version": (ctypes.c_char_p, []),
     }
@@ -231,6 +250,9 @@ class Graph:
                                         ctypes.byref(vol)), "lcd_graph_info")
         return dict(n=n.value, nnz=nnz.value, max_degree=mk.value, volume=vol.value)
 
+    def untune(self):
+        _check(library().lcd_graph_untune(self._h), "lcd_graph_untune")
+
     def free(self):
         if getattr(self, "_h", None):
             library().lcd_graph_free(self._h)
@@ -318,6 +340,11 @@ class Result:
         return dict(members=mem[:need.value], off=off[:R], cnt=cnt[:R], K=K[:R], V=V[:R], f=f[:R],
                     ctr=ctr[:R * 4].reshape(R, 4), n_sets=ids.size, n_scales=S)
 
+    def rerun(self):
+        """lcd_result_rerun: the same sweep again into this result."""
+        _check(library().lcd_result_rerun(self._h, _stream()), "lcd_result_rerun")
+        return self
+
     def stats(self) -> dict:
         s = lcd_sweep_stats()
         _check(library().lcd_result_stats(self._h, ctypes.byref(s)), "lcd_result_stats")
@@ -337,7 +364,8 @@ class Result:
 
 def make_params(k_prune: int = 0, mode: int = LCD_PERSISTENT, lds_capacity: int = 0,
                 waves_per_block: int = 0, blocks_per_cu: int = 0, use_graph: int = 0,
-                pool_hint: int = 0, watchdog_ms: int = 0) -> lcd_params:
+                pool_hint: int = 0, watchdog_ms: int = 0, spill_mode: int = 0,
+                team_capacity: int = 0, team_waves: int = 0) -> lcd_params:
     p = lcd_params()
     library().lcd_params_default(ctypes.byref(p))
     p.k_prune = k_prune
@@ -349,6 +377,9 @@ def make_params(k_prune: int = 0, mode: int = LCD_PERSISTENT, lds_capacity: int 
     p.pool_hint = pool_hint
     if watchdog_ms:
         p.watchdog_ms = watchdog_ms
+    p.spill_mode = spill_mode
+    p.team_capacity = team_capacity
+    p.team_waves = team_waves
     return p
 
 
@@ -397,6 +428,25 @@ def sweep_to_numpy(res: Result) -> dict:
     _, ctr = res.counters(per_record=True)
     return dict(members=members, off=offs, cnt=cnt, K=K, V=V, f=f,
                 ctr=ctr.cpu().numpy().astype(np.uint64), n_sets=ns, n_scales=S)
+
+
+def lcd_tune(graph: "Graph", scales, seed_ptr, seed_nodes, **base) -> dict:
+    """Autotune the launch sizing for this graph and seed sets (the graph
+    keeps the choice for later sweeps with default params)."""
+    lib = library()
+    sc = np.ascontiguousarray(scales, dtype=np.float64)
+    sp = np.ascontiguousarray(seed_ptr, dtype=np.int32)
+    sn = np.ascontiguousarray(seed_nodes, dtype=np.int32)
+    prm = make_params(**base)
+    rep = lcd_tune_report()
+    _check(lib.lcd_tune(graph._h, sc.ctypes.data_as(P), sc.size, sp.ctypes.data_as(P),
+                        sn.ctypes.data_as(P), sp.size - 1, LCD_MEM_HOST, ctypes.byref(prm), _stream(),
+                        ctypes.byref(rep)), "lcd_tune")
+    keys = ("lds_capacity", "spill_mode", "team_capacity", "team_waves")
+    return dict(best={k: getattr(rep.best, k) for k in keys}, ms_best=rep.ms_best,
+                sample_stride=rep.sample_stride, full_checked=bool(rep.full_checked),
+                tried=[dict({k: getattr(rep.tried[i], k) for k in keys}, ms=round(rep.ms[i], 3))
+                       for i in range(rep.n_tried)])
 
 
 # ---------------------------------------------------------------------------

@@ -79,13 +79,23 @@ def test_small_workload_per_scale_loop(L, mode):
     assert st["launches"] >= scales.size
 
 
-def test_small_workload_spill_tiers(L):
-    # a 64-entry LDS table forces nearly every community into the
-    # global-memory tiers
+@pytest.mark.parametrize("label,kw", [
+    ("workgroup tiers: 4096-entry LDS table", dict(lds_capacity=64)),
+    ("workgroup tiers: global tables", dict(lds_capacity=64, team_capacity=128)),
+    ("workgroup tiers: one wave per workgroup", dict(lds_capacity=64, team_capacity=128, team_waves=1)),
+    ("workgroup tiers: three waves", dict(lds_capacity=128, team_capacity=256, team_waves=3)),
+    ("one-wave global tiers", dict(lds_capacity=64, spill_mode=1)),
+    ("one-wave global tier, then workgroups", dict(lds_capacity=64, spill_mode=2)),
+])
+def test_small_workload_spill_tiers(L, label, kw):
+    # a 64-entry tier-0 table sends nearly every community to the later tiers
     g, sp, sn, scales = W.workload_small()
-    got, ref, st = run_both(L, g, sp, sn, scales, lds_capacity=64)
+    _say("spill: %s" % label)
+    got, ref, st = run_both(L, g, sp, sn, scales, **kw)
     assert st["n_spilled"] > 900
-    compare_results(got, ref, label="spill")
+    compare_results(got, ref, label=label)
+    _say("  tiers %d, sets finished per tier %s, %.2f ms"
+         % (st["tiers"], [t["sets_finished"] for t in st["tier"]], st["ms_total"]))
 
 
 def test_small_workload_k_prune_1(L):

@@ -53,18 +53,22 @@ def test_medium_workload_sampled(L):
     assert st["n_spilled"] > 0          # the global-memory tier is exercised too
 
 
-@pytest.mark.parametrize("cap", [256, 2048])
-def test_medium_workload_other_capacities(L, cap):
+@pytest.mark.parametrize("kw", [dict(lds_capacity=256), dict(lds_capacity=2048),
+                                dict(lds_capacity=512, spill_mode=1),
+                                dict(lds_capacity=64, team_capacity=1024, team_waves=4)])
+def test_medium_workload_other_configs(L, kw):
     g, sp, sn, scales = W.workload_medium()
-    st, k = _sampled(L, g, sp, sn, scales, 64, lds_capacity=cap)
-    _say("medium cap %d: %d sampled sets match" % (cap, k))
+    st, k = _sampled(L, g, sp, sn, scales, 64, **kw)
+    _say("medium %s: %d sampled sets match; sets finished per tier %s"
+         % (kw, k, [t["sets_finished"] for t in st["tier"]]))
 
 
 def test_large_workload_sampled(L):
     g, sp, sn, scales = W.workload_large()
     _say("large: %d sets x %d scales" % (sp.size - 1, scales.size))
     st, k = _sampled(L, g, sp, sn, scales, 2048)
-    _say("large: %d sampled sets match; %.0f ms device" % (k, st["ms_total"]))
+    _say("large: %d sampled sets match; %.0f ms device; sets finished per tier %s"
+         % (k, st["ms_total"], [t["sets_finished"] for t in st["tier"]]))
 
 
 def test_resume_equals_full_sweep(L):
