@@ -133,7 +133,7 @@ def serve_bench(lcd, G, g, qps, seconds, warmup_s, oracle_sample, seed=1):
     from paper_1301_0955_amd import workloads as W
     n = int(round(qps * (warmup_s + seconds)))
     t_arr, sets, alphas = W.query_stream(g, n, qps, max_size=256, seed=seed)
-    srv = lcd.Server(G, max_slots=1024)
+    srv = lcd.Server(G, max_slots=8192)
     for i in range(8):                      # first launches of the query kernels
         srv.result(srv.submit(sets[i], alphas[i]))
     st0 = srv.stats()
@@ -176,6 +176,8 @@ def serve_bench(lcd, G, g, qps, seconds, warmup_s, oracle_sample, seed=1):
         mean_members=round(float(np.mean([res[i]["members"].size for i in meas])), 2),
         batches=int(batches), mean_batch=round((st["completed"] - st0["completed"]) / max(batches, 1), 2),
         max_batch=st["max_batch"], max_lanes_busy=st["max_lanes_busy"], lanes=st["lanes"],
+        stage_lanes=st["spill_lanes"], forwarded=st["forwarded"] - st0["forwarded"],
+        later_stage_batches=st["spill_batches"] - st0["spill_batches"],
         requeued=st["requeued"], failed=st["failed"], server_mem_bytes=st["mem_held"])
     # the oracle on a sample of the same queries: per-query CPU latency and parity
     if oracle_sample > 0:

@@ -274,6 +274,9 @@ lcd_status lcd_result_free(lcd_result *r);
  * admits waiting queries into any idle launch lane (each lane a HIP stream
  * with its own buffers), limited by max_slots queries in flight and by the
  * lane's member pool, so batches of several lanes run on the device at once.
+ * Entry lanes run tier 0 (one wave per query, LDS table); queries whose
+ * table outgrows it go on to spill lanes running the larger tiers, so that
+ * a few large communities do not hold back the batches of small ones.
  * ------------------------------------------------------------------------ */
 
 /* Outcome of one query (filled by lcd_server_poll). */
@@ -292,15 +295,18 @@ typedef struct {
 
 typedef struct {
     int64_t submitted, completed, failed;
-    int64_t batches;          /* launches of query batches */
+    int64_t batches;          /* launches of query batches (both lane kinds) */
     int64_t requeued;         /* queries run again alone after a pool overflow */
-    int64_t pending;          /* waiting for a lane now */
+    int64_t pending;          /* waiting for an entry lane now */
     int64_t in_flight;        /* admitted and not finished now */
     int64_t mem_held;         /* device bytes the server holds */
-    int32_t lanes, max_slots;
+    int64_t forwarded;        /* queries that outgrew tier 0 and went to a spill lane */
+    int64_t spill_batches;    /* launches of spill lanes */
+    int32_t lanes, spill_lanes, max_slots;
     int32_t max_batch;        /* largest batch launched */
     int32_t max_lanes_busy;   /* most lanes with a batch on the device at once */
-    int32_t spill_tables[2];  /* global-memory tables per lane, per spill tier */
+    int32_t spill_tables[2];  /* global-memory tables per spill lane, per global tier */
+    int32_t pad;
 } lcd_server_stats;
 
 /*

@@ -153,9 +153,12 @@ lcd_status plan_tiers(const DevInfo &dev, int32_t n, const lcd_params &p, TierPl
     return LCD_OK;
 }
 
-lcd_status enqueue_tiers(const SweepArgs &a0, const TierPlan &tp, int32_t blocks0, Slab *slabs,
-                         int32_t *const *work, hipStream_t st, hipEvent_t *ev, int32_t *launches) {
-    for (int k = 0; k < tp.n; ++k) {
+lcd_status enqueue_tiers(const SweepArgs &a0, const TierPlan &tp, int first, int last, int32_t blocks0,
+                         Slab *slabs, int32_t *const *work, hipStream_t st, hipEvent_t *ev,
+                         int32_t *launches) {
+    if (first < 0 || last > tp.n || first > last)
+        return fail(LCD_EINVAL, "tier range [%d, %d) outside the plan of %d tiers", first, last, tp.n);
+    for (int k = first; k < last; ++k) {
         const TierSpec &T = tp.t[k];
         if (ev)
             HIPCHK(hipEventRecord(ev[k], st));
@@ -185,7 +188,7 @@ lcd_status enqueue_tiers(const SweepArgs &a0, const TierPlan &tp, int32_t blocks
         *launches += 1;
     }
     if (ev)
-        HIPCHK(hipEventRecord(ev[tp.n], st));
+        HIPCHK(hipEventRecord(ev[last], st));
     return LCD_OK;
 }
 
@@ -267,7 +270,7 @@ lcd_status run_group(lcd_result *r, const TierPlan &tp, int32_t s_begin, int32_t
     a.err = r->err;
     a.budget_ticks = r->prm.watchdog_ms < 0 ? 0 : g->dev.wall_khz * (int64_t)r->prm.watchdog_ms;
     a.stat = r->cursor + 2;
-    return enqueue_tiers(a, tp, tp.t[0].blocks, g->slab, r->work, st, ev, &r->stats.launches);
+    return enqueue_tiers(a, tp, 0, tp.n, tp.t[0].blocks, g->slab, r->work, st, ev, &r->stats.launches);
 }
 
 void capture_key(const lcd_result *r, int64_t key[8]) {

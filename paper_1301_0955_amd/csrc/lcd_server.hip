@@ -77,8 +77,16 @@ void host_free(T *&p) {
     p = nullptr;
 }
 
+// A stage runs the tiers [first, last) of the plan; queries whose table
+// overflows its last tier go on to the next stage.
+struct Stage {
+    int first = 0, last = 0;
+};
+constexpr int kMaxStages = 2;
+
 struct Lane {
     int id = 0;
+    int stage = 0;
     hipStream_t st = nullptr;
     hipEvent_t done = nullptr;
     int32_t max_q = 0;
@@ -106,6 +114,8 @@ struct Lane {
     uint64_t *h_ctr = nullptr;
     unsigned long long *h_cursor = nullptr;
     int32_t *h_pool = nullptr;
+    Counters *h_ctl = nullptr;
+    int32_t *h_work0 = nullptr;
     // batch in flight
     std::vector<Query *> batch;
     bool busy = false;
@@ -140,6 +150,8 @@ void lane_release(Lane &L) {
     host_free(L.h_ctr);
     host_free(L.h_cursor);
     host_free(L.h_pool);
+    host_free(L.h_ctl);
+    host_free(L.h_work0);
     if (L.done)
         (void)hipEventDestroy(L.done);
     if (L.st)
@@ -167,7 +179,10 @@ struct lcd_server {
     std::mutex mu;
     std::condition_variable cv_work;
     std::condition_variable cv_done;
-    std::deque<Query *> pending;
+    std::deque<Query *> pending;         // submitted, waiting for a stage-0 lane
+    Stage stages[kMaxStages];
+    int n_stages = 1;
+    std::deque<Query *> forwarded[kMaxStages];   // waiting for a lane of stage k (k >= 1)
     std::unordered_map<uint64_t, Query *> tickets;
     uint64_t next_ticket = 1;
     int64_t in_flight = 0;
@@ -179,6 +194,9 @@ struct lcd_server {
 namespace {
 
 // Launch the batch already placed in L.batch; called without the lock.
+// An entry lane runs tier 0 only; the sets that overflow it are listed in
+// work[0] and leave for a spill lane.  A spill lane runs the later tiers on
+// its whole batch, fed as if tier 0 had pushed every set.
 lcd_status launch_lane(lcd_server *S, Lane &L) {
     const lcd_graph *g = S->g;
     const int32_t nq = (int32_t)L.batch.size();
@@ -195,10 +213,21 @@ lcd_status launch_lane(lcd_server *S, Lane &L) {
     HIPCHK(hipMemcpyAsync(L.alpha, L.h_alpha, sizeof(double) * nq, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(L.seed_ptr, L.h_seed_ptr, sizeof(int32_t) * (nq + 1), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(L.seed_nodes, L.h_seed_nodes, sizeof(int32_t) * pos, hipMemcpyHostToDevice, st));
-    HIPCHK(launch_zero_bytes(L.ctl, (int64_t)sizeof(Counters), st));
     HIPCHK(launch_zero_bytes(L.cursor, 8 * kCursorWords, st));
+    const Stage &G = S->stages[L.stage];
+    if (G.first > 0) {
+        // as if tier first-1 had pushed every set of the batch
+        std::memset(L.h_ctl, 0, sizeof(Counters));
+        L.h_ctl->ovf_count[G.first - 1] = (uint32_t)nq;
+        for (int32_t i = 0; i < nq; ++i)
+            L.h_work0[i] = i;
+        HIPCHK(hipMemcpyAsync(L.ctl, L.h_ctl, sizeof(Counters), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(L.work[G.first - 1], L.h_work0, sizeof(int32_t) * nq, hipMemcpyHostToDevice, st));
+    } else {
+        HIPCHK(launch_zero_bytes(L.ctl, (int64_t)sizeof(Counters), st));
+    }
     for (int k = 0; k < S->tp.n; ++k)
-        if (S->tp.t[k].slab >= 0) {
+        if (S->tp.t[k].slab >= 0 && L.slab[S->tp.t[k].slab].buf) {
             Slab &sl = L.slab[S->tp.t[k].slab];
             CHK(ensure_slab(sl, sl.cap, sl.slots, st));
         }
@@ -225,7 +254,7 @@ lcd_status launch_lane(lcd_server *S, Lane &L) {
     const TierSpec &T0 = S->tp.t[0];
     const int32_t blocks0 = std::min<int32_t>(T0.blocks, (nq + T0.waves - 1) / T0.waves);
     int32_t launches = 0;
-    CHK(enqueue_tiers(a, S->tp, blocks0, L.slab, L.work, st, nullptr, &launches));
+    CHK(enqueue_tiers(a, S->tp, G.first, G.last, blocks0, L.slab, L.work, st, nullptr, &launches));
     HIPCHK(hipMemcpyAsync(L.h_off, L.rec.off, sizeof(int64_t) * nq, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(L.h_cnt, L.rec.cnt, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(L.h_K, L.rec.K, sizeof(int64_t) * nq, hipMemcpyDeviceToHost, st));
@@ -233,13 +262,20 @@ lcd_status launch_lane(lcd_server *S, Lane &L) {
     HIPCHK(hipMemcpyAsync(L.h_f, L.rec.f, sizeof(double) * nq, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(L.h_ctr, L.rec.ctr, sizeof(uint64_t) * 4 * nq, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(L.h_cursor, L.cursor, 8 * kCursorWords, hipMemcpyDeviceToHost, st));
+    if (G.last < S->tp.n) {
+        HIPCHK(hipMemcpyAsync(L.h_ctl, L.ctl, sizeof(Counters), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(L.h_work0, L.work[G.last - 1], sizeof(int32_t) * nq, hipMemcpyDeviceToHost, st));
+    }
     HIPCHK(hipEventRecord(L.done, st));
     return LCD_OK;
 }
 
 // The lane's batch has finished on the device: fetch member lists and fill
-// the queries.  Called without the lock; returns the queries to run again.
-lcd_status collect_lane(lcd_server *S, Lane &L, std::vector<Query *> &again) {
+// the queries.  Called without the lock.  `again`: queries to run again
+// alone (the batch outgrew the lane's pool); `forward`: queries that
+// overflowed the last tier of the lane's stage.
+lcd_status collect_lane(lcd_server *S, Lane &L, std::vector<Query *> &again,
+                        std::vector<Query *> &forward) {
     const int32_t nq = (int32_t)L.batch.size();
     const uint32_t err = (uint32_t)(L.h_cursor[1] & 0xffffffffu);
     if (err) {
@@ -247,6 +283,17 @@ lcd_status collect_lane(lcd_server *S, Lane &L, std::vector<Query *> &again) {
         return fail(err & ERR_CAPACITY ? LCD_ECAPACITY : LCD_EDEVICE,
                     "query kernel reported error bits 0x%x%s", err,
                     err & ERR_TIMEOUT ? " (watchdog: a query ran past its time budget)" : "");
+    }
+    std::vector<char> spilled((size_t)nq, 0);
+    const Stage &G = S->stages[L.stage];
+    if (G.last < S->tp.n) {
+        const uint32_t nf = std::min<uint32_t>(L.h_ctl->ovf_count[G.last - 1], (uint32_t)nq);
+        for (uint32_t j = 0; j < nf; ++j) {
+            const int32_t i = L.h_work0[j];
+            if (i < 0 || i >= nq)
+                return fail(LCD_EDEVICE, "overflow list holds set %d of a batch of %d", i, nq);
+            spilled[i] = 1;
+        }
     }
     const int64_t used = std::min<int64_t>((int64_t)L.h_cursor[0], L.pool_cap);
     if (used > 0) {
@@ -256,6 +303,10 @@ lcd_status collect_lane(lcd_server *S, Lane &L, std::vector<Query *> &again) {
     const int64_t t_done = now_ns();
     for (int32_t i = 0; i < nq; ++i) {
         Query *q = L.batch[i];
+        if (spilled[i]) {
+            forward.push_back(q);
+            continue;
+        }
         const int64_t off = L.h_off[i];
         const int32_t cnt = L.h_cnt[i];
         if (off < 0 || off + cnt > L.pool_cap) {
@@ -272,13 +323,32 @@ lcd_status collect_lane(lcd_server *S, Lane &L, std::vector<Query *> &again) {
         q->info.f = L.h_f[i];
         for (int c = 0; c < 4; ++c)
             q->info.ctr[c] = L.h_ctr[4 * i + c];
-        q->info.t_start_ns = L.t_start;
         q->info.t_done_ns = t_done;
         q->info.batch_size = nq;
         q->info.lane = L.id;
         q->status = LCD_OK;
     }
     return LCD_OK;
+}
+
+// Fill L.batch from queue (FIFO) within the lane's limits.  Lock held.
+void admit(lcd_server *S, Lane &L, std::deque<Query *> &queue, bool count_slots) {
+    int64_t seeds = 0, reserved = 0;
+    while (!queue.empty() && (int32_t)L.batch.size() < L.max_q &&
+           (!count_slots || S->in_flight < S->max_slots)) {
+        Query *q = queue.front();
+        const int64_t ns = (int64_t)q->seeds.size();
+        if (!L.batch.empty() && (q->solo || seeds + ns > L.max_seed || reserved + q->reserve > L.pool_cap))
+            break;
+        queue.pop_front();
+        L.batch.push_back(q);
+        if (count_slots)
+            S->in_flight += 1;
+        seeds += ns;
+        reserved += q->reserve;
+        if (q->solo)
+            break;
+    }
 }
 
 void worker_main(lcd_server *S) {
@@ -292,12 +362,12 @@ void worker_main(lcd_server *S) {
                 continue;
             lk.unlock();
             const hipError_t q = hipEventQuery(L.done);
-            std::vector<Query *> again;
+            std::vector<Query *> again, forward;
             lcd_status s = LCD_OK;
             std::string msg;
             bool finished = false;
             if (q == hipSuccess) {
-                s = collect_lane(S, L, again);
+                s = collect_lane(S, L, again, forward);
                 finished = true;
             } else if (q != hipErrorNotReady) {
                 s = fail(LCD_EDEVICE, "query batch failed: %s", hipGetErrorString(q));
@@ -309,11 +379,17 @@ void worker_main(lcd_server *S) {
             if (!finished)
                 continue;
             progress = true;
+            if (s != LCD_OK) {
+                again.clear();
+                forward.clear();
+            }
             for (Query *qq : L.batch) {
-                bool rerun = false;
+                bool moved = false;
                 for (Query *a : again)
-                    rerun |= a == qq;
-                if (rerun)
+                    moved |= a == qq;
+                for (Query *a : forward)
+                    moved |= a == qq;
+                if (moved)
                     continue;
                 if (s != LCD_OK) {
                     qq->status = s;
@@ -323,11 +399,19 @@ void worker_main(lcd_server *S) {
                     S->stats.completed += 1;
                 }
                 qq->done = true;
+                S->in_flight -= 1;
             }
+            // queries to run again keep their place at the front of their stage
+            std::deque<Query *> &back = L.stage == 0 ? S->pending : S->forwarded[L.stage];
             for (auto it = again.rbegin(); it != again.rend(); ++it)
-                S->pending.push_front(*it);
+                back.push_front(*it);
+            if (L.stage + 1 < S->n_stages)
+                for (Query *f : forward)
+                    S->forwarded[L.stage + 1].push_back(f);
+            if (L.stage == 0)
+                S->in_flight -= (int64_t)again.size();   // re-admitted from `pending`
             S->stats.requeued += (int64_t)again.size();
-            S->in_flight -= (int64_t)L.batch.size();
+            S->stats.forwarded += (int64_t)forward.size();
             L.batch.clear();
             L.busy = false;
             S->cv_done.notify_all();
@@ -336,32 +420,29 @@ void worker_main(lcd_server *S) {
             bool any = false;
             for (Lane &L : S->lanes)
                 any |= L.busy;
-            if (!any)
+            bool waiting = false;
+            for (int k = 1; k < S->n_stages; ++k)
+                waiting |= !S->forwarded[k].empty();
+            if (!any && !waiting)
                 break;
         }
-        // 2. admit pending queries into idle lanes
+        // 2. admit waiting queries into idle lanes
         for (Lane &L : S->lanes) {
-            if (S->stop || L.busy || S->pending.empty() || S->in_flight >= S->max_slots)
+            if (L.busy)
                 continue;
-            int64_t seeds = 0, reserved = 0;
-            while (!S->pending.empty() && (int32_t)L.batch.size() < L.max_q &&
-                   S->in_flight + (int64_t)L.batch.size() < S->max_slots) {
-                Query *q = S->pending.front();
-                const int64_t ns = (int64_t)q->seeds.size();
-                if (!L.batch.empty() && (q->solo || seeds + ns > L.max_seed ||
-                                         reserved + q->reserve > L.pool_cap))
-                    break;
-                S->pending.pop_front();
-                L.batch.push_back(q);
-                seeds += ns;
-                reserved += q->reserve;
-                if (q->solo)
-                    break;
+            if (L.stage > 0) {
+                if (S->forwarded[L.stage].empty())
+                    continue;
+                admit(S, L, S->forwarded[L.stage], false);
+                S->stats.spill_batches += 1;
+            } else {
+                if (S->stop || S->pending.empty() || S->in_flight >= S->max_slots)
+                    continue;
+                admit(S, L, S->pending, true);
             }
             if (L.batch.empty())
                 continue;
             L.busy = true;
-            S->in_flight += (int64_t)L.batch.size();
             S->stats.batches += 1;
             S->stats.max_batch = std::max<int32_t>(S->stats.max_batch, (int32_t)L.batch.size());
             int32_t nbusy = 0;
@@ -369,14 +450,15 @@ void worker_main(lcd_server *S) {
                 nbusy += M.busy ? 1 : 0;
             S->stats.max_lanes_busy = std::max(S->stats.max_lanes_busy, nbusy);
             L.t_start = now_ns();
+            for (Query *q : L.batch)
+                if (q->info.t_start_ns == 0)
+                    q->info.t_start_ns = L.t_start;
             lk.unlock();
             const lcd_status s = launch_lane(S, L);
             std::string msg = s != LCD_OK ? std::string(lcd_last_error()) : std::string();
             lk.lock();
             progress = true;
             if (s != LCD_OK) {
-                // nothing was left running that the event does not cover:
-                // wait for the stream, then fail the batch
                 lk.unlock();
                 (void)hipStreamSynchronize(L.st);
                 lk.lock();
@@ -386,8 +468,8 @@ void worker_main(lcd_server *S) {
                     qq->msg = msg;
                     qq->done = true;
                     S->stats.failed += 1;
+                    S->in_flight -= 1;
                 }
-                S->in_flight -= (int64_t)L.batch.size();
                 L.batch.clear();
                 L.busy = false;
                 S->cv_done.notify_all();
@@ -446,8 +528,10 @@ lcd_status lane_init(lcd_server *S, Lane &L, int id, int32_t max_q, int64_t max_
     CHK(host_alloc(&L.h_ctr, 4 * (size_t)max_q));
     CHK(host_alloc(&L.h_cursor, kCursorWords));
     CHK(host_alloc(&L.h_pool, (size_t)pool_cap));
+    CHK(host_alloc(&L.h_ctl, 1));
+    CHK(host_alloc(&L.h_work0, max_q));
     for (int k = 0; k < S->tp.n; ++k)
-        if (S->tp.t[k].slab >= 0)
+        if (S->tp.t[k].slab >= 0 && slots[S->tp.t[k].slab] > 0)
             CHK(ensure_slab(L.slab[S->tp.t[k].slab], S->tp.t[k].cap, slots[S->tp.t[k].slab], L.st));
     HIPCHK(hipStreamSynchronize(L.st));
     return LCD_OK;
@@ -500,49 +584,93 @@ lcd_status lcd_server_create(const lcd_graph *g, int64_t mem_budget, int32_t max
     S->prm = prm;
     S->max_slots = max_slots;
     S->mem_budget = mem_budget;
-    apply_tuned(g, prm);
+    // serving sizing: the tuned sweep sizing favours throughput over many
+    // sets; a query stream wants most queries done by tier 0
+    if (params_are_auto(prm)) {
+        prm.lds_capacity = 1024;
+        prm.team_waves = 8;
+    }
     S->prm = prm;
     lcd_status s = plan_tiers(g->dev, g->n, prm, S->tp);
     if (s != LCD_OK) {
         delete S;
         return s;
     }
-    // lanes and their sizes from the budget: every lane can hold any single
-    // query (pool >= n, one table of each spill tier)
+    // stages: tier 0, then all later tiers.  Four lanes: one for stage 0 and
+    // three for the later stage (all four for stage 0 when the plan has one
+    // tier).  Tier-0 batches take milliseconds; a later-stage batch lasts as
+    // long as its slowest query, so that stage gets the lanes and large batches.
+    S->n_stages = 0;
+    S->stages[S->n_stages++] = Stage{0, 1};
+    if (S->tp.n >= 2)
+        S->stages[S->n_stages++] = Stage{1, S->tp.n};
     const int n_lanes = 4;
-    const int32_t max_q = std::max<int32_t>(1, std::min<int32_t>(256, max_slots));
+    int lane_stage[4] = {0, 0, 0, 0};
+    if (S->n_stages == 2)
+        lane_stage[1] = lane_stage[2] = lane_stage[3] = 1;
+    const int32_t max_q = std::max<int32_t>(1, std::min<int32_t>(1024, max_slots));
     const int64_t max_seed = std::max<int64_t>(65536, (int64_t)g->n);
-    const int64_t pool_cap = std::max<int64_t>((int64_t)g->n, 1 << 20);
-    // global-memory tables of the spill tiers: one of each per lane at least,
-    // then what the budget allows (half for the first global tier)
+    const int64_t pool_cap = std::max<int64_t>((int64_t)g->n, 1 << 22);
     int64_t tb[2] = {0, 0};
+    int32_t want[2] = {0, 0};
     for (int k = 0; k < S->tp.n; ++k)
-        if (S->tp.t[k].slab >= 0)
+        if (S->tp.t[k].slab >= 0) {
             tb[S->tp.t[k].slab] = slab_stride(S->tp.t[k].cap);
+            want[S->tp.t[k].slab] = S->tp.t[k].slots;
+        }
     const int64_t fixed = lane_bytes(max_q, max_seed, pool_cap);
-    const int64_t per_lane = mem_budget / n_lanes;
-    const int64_t left = per_lane - fixed - tb[0] - tb[1];
-    if (left < 0) {
+    // a lane whose stage runs a global tier holds at least one table of it;
+    // the rest of the budget buys more (half for the first global tier)
+    auto stage_uses = [&](int st, int slab) {
+        for (int k = S->stages[st].first; k < S->stages[st].last; ++k)
+            if (S->tp.t[k].slab == slab)
+                return true;
+        return false;
+    };
+    int64_t need_min = n_lanes * fixed;
+    int users[2] = {0, 0};
+    for (int i = 0; i < n_lanes; ++i)
+        for (int sl = 0; sl < 2; ++sl)
+            if (tb[sl] && stage_uses(lane_stage[i], sl)) {
+                need_min += tb[sl];
+                users[sl] += 1;
+            }
+    const int64_t left_all = mem_budget - need_min;
+    if (left_all < 0) {
         delete S;
-        return fail(LCD_ENOMEM, "mem_budget %lld is below the %lld bytes four lanes need on this graph",
-                    (long long)mem_budget, (long long)(n_lanes * (fixed + tb[0] + tb[1])));
+        return fail(LCD_ENOMEM, "mem_budget %lld is below the %lld bytes the lanes need on this graph",
+                    (long long)mem_budget, (long long)need_min);
     }
     int32_t slots[2] = {0, 0};
-    if (tb[0])
-        slots[0] = (int32_t)std::min<int64_t>(256, 1 + (left / 2) / tb[0]);
-    const int64_t left2 = left - (tb[0] ? (slots[0] - 1) * tb[0] : 0);
-    if (tb[1])
-        slots[1] = (int32_t)std::min<int64_t>(32, 1 + left2 / tb[1]);
+    {
+        const int64_t half = left_all / 2;
+        if (users[0])
+            slots[0] = (int32_t)std::min<int64_t>(std::max(1, want[0]), 1 + half / users[0] / tb[0]);
+        const int64_t left2 = left_all - (users[0] ? (int64_t)(slots[0] - 1) * tb[0] * users[0] : 0);
+        if (users[1])
+            slots[1] = (int32_t)std::min<int64_t>(std::max(1, want[1]), 1 + left2 / users[1] / tb[1]);
+    }
     S->lanes.resize(n_lanes);
+    S->mem_held = n_lanes * fixed;
     for (int i = 0; i < n_lanes; ++i) {
-        s = lane_init(S, S->lanes[i], i, max_q, max_seed, pool_cap, slots);
+        Lane &L = S->lanes[i];
+        L.stage = lane_stage[i];
+        int32_t mine[2] = {0, 0};
+        for (int sl = 0; sl < 2; ++sl)
+            if (tb[sl] && stage_uses(L.stage, sl)) {
+                mine[sl] = slots[sl];
+                S->mem_held += (int64_t)slots[sl] * tb[sl];
+            }
+        s = lane_init(S, L, i, max_q, max_seed, pool_cap, mine);
         if (s != LCD_OK) {
             server_release(S);
             return s;
         }
     }
-    S->mem_held = n_lanes * (fixed + (int64_t)slots[0] * tb[0] + (int64_t)slots[1] * tb[1]);
     S->stats.lanes = n_lanes;
+    S->stats.spill_lanes = 0;
+    for (int i = 0; i < n_lanes; ++i)
+        S->stats.spill_lanes += lane_stage[i] > 0 ? 1 : 0;
     S->stats.max_slots = max_slots;
     S->stats.mem_held = S->mem_held;
     S->stats.spill_tables[0] = slots[0];

@@ -91,12 +91,14 @@ class lcd_server_stats(ctypes.Structure):
                 ("failed", ctypes.c_int64), ("batches", ctypes.c_int64),
                 ("requeued", ctypes.c_int64), ("pending", ctypes.c_int64),
                 ("in_flight", ctypes.c_int64), ("mem_held", ctypes.c_int64),
-                ("lanes", ctypes.c_int32), ("max_slots", ctypes.c_int32),
-                ("max_batch", ctypes.c_int32), ("max_lanes_busy", ctypes.c_int32),
-                ("spill_tables", ctypes.c_int32 * 2)]
+                ("forwarded", ctypes.c_int64), ("spill_batches", ctypes.c_int64),
+                ("lanes", ctypes.c_int32), ("spill_lanes", ctypes.c_int32),
+                ("max_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("max_lanes_busy", ctypes.c_int32), ("spill_tables", ctypes.c_int32 * 2),
+                ("pad", ctypes.c_int32)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "spill_tables"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("spill_tables", "pad")}
         d["spill_tables"] = list(self.spill_tables)
         return d
 

@@ -63,11 +63,13 @@ def test_server_mix_equals_alone_and_oracle(L, graph):
             tickets = [srv.submit(s, a) for s, a in queries]
             mix = [srv.result(t, 120_000) for t in tickets]
             st = srv.stats()
-            _say("cap %d: %d queries, %d batches, largest %d, lanes busy at once %d, requeued %d"
-                 % (cap, st["completed"], st["batches"], st["max_batch"], st["max_lanes_busy"],
-                    st["requeued"]))
+            _say("cap %d: %d queries, %d batches (%d on spill lanes), largest %d, lanes busy at once %d, "
+                 "forwarded %d, requeued %d" % (cap, st["completed"], st["batches"], st["spill_batches"],
+                                                st["max_batch"], st["max_lanes_busy"], st["forwarded"],
+                                                st["requeued"]))
             assert st["completed"] == len(queries) and st["failed"] == 0
             assert st["max_lanes_busy"] >= 2        # batches overlapped on the device
+            assert st["forwarded"] > 0              # some queries outgrew tier 0
             for i, ((s, a), got) in enumerate(zip(queries, mix)):
                 ref = _oracle_one(o, s, a)
                 _same(got, ref, ("oracle", cap, i))
