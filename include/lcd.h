@@ -150,6 +150,29 @@ lcd_status lcd_graph_upload(int32_t n, int64_t nnz, const int32_t *row_ptr,
                             const int32_t *col, const uint8_t *w, int32_t mem_kind,
                             void *stream, lcd_graph **out);
 
+/*
+ * Upload n_graphs independent graphs as one resident batch (sweeps over all
+ * of them run in one launch).  Each member graph obeys the rules of
+ * lcd_graph_upload in its own local ids:
+ *   node_off, edge_off  int64[n_graphs+1], starting at 0, non-decreasing:
+ *                       graph i has node_off[i+1]-node_off[i] nodes and
+ *                       edge_off[i+1]-edge_off[i] directed entries
+ *   row_ptr  int32[node_off[n_graphs] + n_graphs]: graph i's local offsets
+ *            (n_i + 1 of them, from 0 to its entry count) at row_ptr + node_off[i] + i
+ *   col      int32[edge_off[n_graphs]]: graph-local neighbour ids, graph i's
+ *            at col + edge_off[i]
+ *   w        uint8[edge_off[n_graphs]] or NULL
+ * The batch is stored as the disjoint union: node u of graph i has batch id
+ * node_off[i] + u, and member lists of sweeps over it use batch ids.
+ */
+lcd_status lcd_graph_upload_batch(int32_t n_graphs, const int64_t *node_off, const int64_t *edge_off,
+                                  const int32_t *row_ptr, const int32_t *col, const uint8_t *w,
+                                  int32_t mem_kind, void *stream, lcd_graph **out);
+
+/* Member graphs of a batch (1 for a plain graph) and node_off[n_graphs+1]
+ * (host memory; may be NULL). */
+lcd_status lcd_graph_batch_info(const lcd_graph *g, int32_t *n_graphs, int64_t *node_off);
+
 /* n, nnz, max weighted degree and total volume (sum of weighted degrees). */
 lcd_status lcd_graph_info(const lcd_graph *g, int32_t *n, int64_t *nnz,
                           int64_t *max_degree, int64_t *volume);
@@ -202,6 +225,18 @@ lcd_status lcd_tune(lcd_graph *g, const double *scales, int32_t n_scales, const 
 
 /* Forget the tuned sizing (later calls use the static defaults). */
 lcd_status lcd_graph_untune(lcd_graph *g);
+
+/*
+ * lcd_sweep over a batch graph with graph-local seeds: seed set j lives in
+ * member graph seed_graph[j] (int32[n_sets], in mem_kind memory) and its
+ * seed ids are local to that graph.  The result is that of lcd_sweep() on
+ * the batch with the seeds translated to batch ids; every community stays
+ * inside its own member graph (no edges join them).
+ */
+lcd_status lcd_sweep_batch(const lcd_graph *g, const double *scales, int32_t n_scales,
+                           const int32_t *seed_ptr, const int32_t *seed_nodes, const int32_t *seed_graph,
+                           int32_t n_sets, int32_t mem_kind, const lcd_params *params, void *stream,
+                           lcd_result **out);
 
 /* Sweep shape and the total number of members listed at one scale. */
 lcd_status lcd_result_shape(const lcd_result *r, int32_t *n_sets, int32_t *n_scales);

@@ -507,22 +507,19 @@ lcd_status lcd_device_info(int32_t *compute_units, int64_t *lds_per_cu, int64_t 
     return LCD_OK;
 }
 
-lcd_status lcd_graph_upload(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col,
-                            const uint8_t *w, int32_t mem_kind, void *stream, lcd_graph **out) {
-    if (!out)
-        return fail(LCD_EINVAL, "out is null");
-    *out = nullptr;
-    if (n < 0 || nnz < 0 || nnz >= ((int64_t)1 << 31))
-        return fail(LCD_EINVAL, "n and nnz must be in [0, 2^31)");
-    if (mem_kind != LCD_MEM_HOST && mem_kind != LCD_MEM_DEVICE)
-        return fail(LCD_EINVAL, "unknown mem_kind %d", mem_kind);
-    hipStream_t st = (hipStream_t)stream;
-    std::vector<int32_t> rp, cl;
+}  // extern "C"
+
+namespace {
+
+// Validate a host CSR and make it resident (the body of lcd_graph_upload).
+lcd_status build_graph(int32_t n, int64_t nnz, const std::vector<int32_t> &rp,
+                       const std::vector<int32_t> &cl, const uint8_t *wp, hipStream_t st,
+                       lcd_graph **out) {
+    const bool has_w = wp != nullptr;
+    const uint8_t *w = wp;
     std::vector<uint8_t> ww;
-    CHK(fetch(rp, row_ptr, (size_t)n + 1, mem_kind, st));
-    CHK(fetch(cl, col, (size_t)nnz, mem_kind, st));
-    if (w)
-        CHK(fetch(ww, w, (size_t)nnz, mem_kind, st));
+    if (has_w)
+        ww.assign(wp, wp + nnz);
     // --- validation ---
     if (rp[0] != 0 || rp[n] != nnz)
         return fail(LCD_EINVAL, "row_ptr must start at 0 and end at nnz");
@@ -604,6 +601,103 @@ lcd_status lcd_graph_upload(int32_t n, int64_t nnz, const int32_t *row_ptr, cons
     if (e != hipSuccess)
         return bail(fail(LCD_EDEVICE, "graph upload: %s", hipGetErrorString(e)));
     *out = g;
+    return LCD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lcd_status lcd_graph_upload(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col,
+                            const uint8_t *w, int32_t mem_kind, void *stream, lcd_graph **out) {
+    if (!out)
+        return fail(LCD_EINVAL, "out is null");
+    *out = nullptr;
+    if (n < 0 || nnz < 0 || nnz >= ((int64_t)1 << 31))
+        return fail(LCD_EINVAL, "n and nnz must be in [0, 2^31)");
+    if (mem_kind != LCD_MEM_HOST && mem_kind != LCD_MEM_DEVICE)
+        return fail(LCD_EINVAL, "unknown mem_kind %d", mem_kind);
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int32_t> rp, cl;
+    std::vector<uint8_t> ww;
+    CHK(fetch(rp, row_ptr, (size_t)n + 1, mem_kind, st));
+    CHK(fetch(cl, col, (size_t)nnz, mem_kind, st));
+    if (w)
+        CHK(fetch(ww, w, (size_t)nnz, mem_kind, st));
+    return build_graph(n, nnz, rp, cl, w ? ww.data() : nullptr, st, out);
+}
+
+lcd_status lcd_graph_upload_batch(int32_t n_graphs, const int64_t *node_off, const int64_t *edge_off,
+                                  const int32_t *row_ptr, const int32_t *col, const uint8_t *w,
+                                  int32_t mem_kind, void *stream, lcd_graph **out) {
+    if (!out)
+        return fail(LCD_EINVAL, "out is null");
+    *out = nullptr;
+    if (n_graphs < 1)
+        return fail(LCD_EINVAL, "n_graphs must be >= 1");
+    if (mem_kind != LCD_MEM_HOST && mem_kind != LCD_MEM_DEVICE)
+        return fail(LCD_EINVAL, "unknown mem_kind %d", mem_kind);
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int64_t> no, eo;
+    CHK(fetch(no, node_off, (size_t)n_graphs + 1, mem_kind, st));
+    CHK(fetch(eo, edge_off, (size_t)n_graphs + 1, mem_kind, st));
+    if (no[0] != 0 || eo[0] != 0)
+        return fail(LCD_EINVAL, "node_off and edge_off must start at 0");
+    for (int32_t i = 0; i < n_graphs; ++i)
+        if (no[i + 1] < no[i] || eo[i + 1] < eo[i])
+            return fail(LCD_EINVAL, "node_off / edge_off decrease at graph %d", i);
+    const int64_t N = no[n_graphs], E = eo[n_graphs];
+    if (N >= ((int64_t)1 << 31) || E >= ((int64_t)1 << 31))
+        return fail(LCD_EINVAL, "total nodes and entries must be below 2^31");
+    std::vector<int32_t> lrp, lcl;
+    std::vector<uint8_t> lw;
+    CHK(fetch(lrp, row_ptr, (size_t)(N + n_graphs), mem_kind, st));
+    CHK(fetch(lcl, col, (size_t)E, mem_kind, st));
+    if (w)
+        CHK(fetch(lw, w, (size_t)E, mem_kind, st));
+    // the disjoint union: graph i's nodes at node_off[i] + local id
+    std::vector<int32_t> rp((size_t)N + 1), cl((size_t)E);
+    for (int32_t i = 0; i < n_graphs; ++i) {
+        const int64_t ni = no[i + 1] - no[i], ei = eo[i + 1] - eo[i];
+        const int32_t *r = lrp.data() + no[i] + i;
+        if (r[0] != 0 || r[ni] != ei)
+            return fail(LCD_EINVAL, "graph %d: row_ptr must start at 0 and end at its %lld entries", i,
+                        (long long)ei);
+        for (int64_t u = 0; u < ni; ++u) {
+            if (r[u + 1] < r[u])
+                return fail(LCD_EINVAL, "graph %d: row_ptr decreases at node %lld", i, (long long)u);
+            rp[no[i] + u] = (int32_t)(eo[i] + r[u]);
+        }
+        for (int64_t j = eo[i]; j < eo[i + 1]; ++j) {
+            const int32_t v = lcl[j];
+            if (v < 0 || v >= ni)
+                return fail(LCD_EINVAL, "graph %d: neighbour id %d out of range", i, v);
+            cl[j] = (int32_t)(no[i] + v);
+        }
+    }
+    rp[N] = (int32_t)E;
+    lcd_graph *g = nullptr;
+    CHK(build_graph((int32_t)N, E, rp, cl, w ? lw.data() : nullptr, st, &g));
+    g->node_off = no;
+    g->edge_off = eo;
+    *out = g;
+    return LCD_OK;
+}
+
+lcd_status lcd_graph_batch_info(const lcd_graph *g, int32_t *n_graphs, int64_t *node_off) {
+    if (!g)
+        return fail(LCD_EINVAL, "null graph");
+    const int32_t k = g->node_off.empty() ? 1 : (int32_t)g->node_off.size() - 1;
+    if (n_graphs)
+        *n_graphs = k;
+    if (node_off) {
+        if (g->node_off.empty()) {
+            node_off[0] = 0;
+            node_off[1] = g->n;
+        } else {
+            std::memcpy(node_off, g->node_off.data(), sizeof(int64_t) * (size_t)(k + 1));
+        }
+    }
     return LCD_OK;
 }
 
@@ -743,6 +837,49 @@ lcd_status lcd_sweep(const lcd_graph *g, const double *scales, int32_t n_scales,
     }
     *out = r;
     return LCD_OK;
+}
+
+lcd_status lcd_sweep_batch(const lcd_graph *g, const double *scales, int32_t n_scales,
+                           const int32_t *seed_ptr, const int32_t *seed_nodes, const int32_t *seed_graph,
+                           int32_t n_sets, int32_t mem_kind, const lcd_params *params, void *stream,
+                           lcd_result **out) {
+    if (!out)
+        return fail(LCD_EINVAL, "out is null");
+    *out = nullptr;
+    if (!g)
+        return fail(LCD_EINVAL, "null graph");
+    if (n_sets < 0)
+        return fail(LCD_EINVAL, "n_sets must be >= 0");
+    if (mem_kind != LCD_MEM_HOST && mem_kind != LCD_MEM_DEVICE)
+        return fail(LCD_EINVAL, "unknown mem_kind %d", mem_kind);
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t k = g->node_off.empty() ? 1 : (int32_t)g->node_off.size() - 1;
+    std::vector<int32_t> sp, sn, sg;
+    std::vector<double> sc;
+    CHK(fetch(sc, scales, (size_t)std::max(n_scales, 0), mem_kind, st));
+    CHK(fetch(sp, seed_ptr, (size_t)n_sets + 1, mem_kind, st));
+    if (sp[0] != 0)
+        return fail(LCD_EINVAL, "seed_ptr[0] must be 0");
+    for (int32_t j = 0; j < n_sets; ++j)
+        if (sp[j + 1] < sp[j])
+            return fail(LCD_EINVAL, "seed_ptr decreases at set %d", j);
+    CHK(fetch(sn, seed_nodes, (size_t)sp[n_sets], mem_kind, st));
+    if (n_sets > 0 && !seed_graph)
+        return fail(LCD_EINVAL, "seed_graph is null");
+    CHK(fetch(sg, seed_graph, (size_t)n_sets, mem_kind, st));
+    for (int32_t j = 0; j < n_sets; ++j) {
+        const int32_t gi = sg[j];
+        if (gi < 0 || gi >= k)
+            return fail(LCD_EINVAL, "seed set %d names graph %d of %d", j, gi, k);
+        const int64_t base = g->node_off.empty() ? 0 : g->node_off[gi];
+        const int64_t ni = g->node_off.empty() ? g->n : g->node_off[gi + 1] - base;
+        for (int32_t q = sp[j]; q < sp[j + 1]; ++q) {
+            if (sn[q] < 0 || sn[q] >= ni)
+                return fail(LCD_EINVAL, "seed node %d of set %d outside graph %d", sn[q], j, gi);
+            sn[q] = (int32_t)(base + sn[q]);
+        }
+    }
+    return lcd_sweep(g, sc.data(), n_scales, sp.data(), sn.data(), n_sets, LCD_MEM_HOST, params, stream, out);
 }
 
 lcd_status lcd_tune(lcd_graph *g, const double *scales, int32_t n_scales, const int32_t *seed_ptr,

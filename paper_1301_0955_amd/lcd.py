@@ -123,6 +123,11 @@ def library() -> ctypes.CDLL:
         "lcd_graph_info": (st, [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
         "lcd_graph_free": (st, [P]),
+        "lcd_graph_upload_batch": (st, [ctypes.c_int32, P, P, P, P, P, ctypes.c_int32, P,
+                                        ctypes.POINTER(P)]),
+        "lcd_graph_batch_info": (st, [P, ctypes.POINTER(ctypes.c_int32), P]),
+        "lcd_sweep_batch": (st, [P, P, ctypes.c_int32, P, P, P, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.POINTER(lcd_params), P, ctypes.POINTER(P)]),
         "lcd_sweep": (st, [P, P, ctypes.c_int32, P, P, ctypes.c_int32, ctypes.c_int32,
                            ctypes.POINTER(lcd_params), P, ctypes.POINTER(P)]),
         "lcd_result_shape": (st, [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
@@ -242,6 +247,42 @@ class Graph:
     @classmethod
     def from_workload(cls, g):
         return cls(g.n, g.row_ptr, g.col, g.w)
+
+    @classmethod
+    def batch(cls, graphs):
+        """lcd_graph_upload_batch: several independent graphs (workload
+        Graph objects, all weighted or all unweighted) as one resident batch."""
+        self = cls.__new__(cls)
+        k = len(graphs)
+        node_off = np.zeros(k + 1, np.int64)
+        edge_off = np.zeros(k + 1, np.int64)
+        for i, g in enumerate(graphs):
+            node_off[i + 1] = node_off[i] + g.n
+            edge_off[i + 1] = edge_off[i] + g.nnz
+        rp = np.ascontiguousarray(np.concatenate([np.asarray(g.row_ptr, np.int32) for g in graphs]))
+        cl = np.ascontiguousarray(np.concatenate([np.asarray(g.col, np.int32) for g in graphs]))
+        weighted = [g.w is not None for g in graphs]
+        if any(weighted) and not all(weighted):
+            raise ValueError("a batch is either all weighted or all unweighted")
+        w = (np.ascontiguousarray(np.concatenate([np.asarray(g.w, np.uint8) for g in graphs]))
+             if all(weighted) else None)
+        h = P()
+        _check(library().lcd_graph_upload_batch(
+            k, node_off.ctypes.data_as(P), edge_off.ctypes.data_as(P), rp.ctypes.data_as(P),
+            cl.ctypes.data_as(P), None if w is None else w.ctypes.data_as(P), LCD_MEM_HOST, _stream(),
+            ctypes.byref(h)), "lcd_graph_upload_batch")
+        self._h = h
+        self.n = int(node_off[-1])
+        return self
+
+    def batch_info(self) -> np.ndarray:
+        """node_off of the member graphs ([0, n] for a plain graph)."""
+        k = ctypes.c_int32()
+        _check(library().lcd_graph_batch_info(self._h, ctypes.byref(k), None), "lcd_graph_batch_info")
+        off = np.zeros(k.value + 1, np.int64)
+        _check(library().lcd_graph_batch_info(self._h, ctypes.byref(k), off.ctypes.data_as(P)),
+               "lcd_graph_batch_info")
+        return off
 
     def info(self) -> dict:
         n = ctypes.c_int32()
@@ -430,6 +471,22 @@ def sweep_to_numpy(res: Result) -> dict:
     _, ctr = res.counters(per_record=True)
     return dict(members=members, off=offs, cnt=cnt, K=K, V=V, f=f,
                 ctr=ctr.cpu().numpy().astype(np.uint64), n_sets=ns, n_scales=S)
+
+
+def lcd_sweep_batch(graph: "Graph", scales, seed_ptr, seed_nodes, seed_graph, params=None, **kw):
+    """lcd_sweep_batch: seeds local to member graph seed_graph[j]; member
+    lists of the result are in batch ids (node_off[graph] + local id)."""
+    lib = library()
+    prm = params if params is not None else make_params(**kw)
+    sc = np.ascontiguousarray(scales, dtype=np.float64)
+    sp = np.ascontiguousarray(seed_ptr, dtype=np.int32)
+    sn = np.ascontiguousarray(seed_nodes, dtype=np.int32)
+    sg = np.ascontiguousarray(seed_graph, dtype=np.int32)
+    h = P()
+    _check(lib.lcd_sweep_batch(graph._h, sc.ctypes.data_as(P), sc.size, sp.ctypes.data_as(P),
+                               sn.ctypes.data_as(P), sg.ctypes.data_as(P), sp.size - 1, LCD_MEM_HOST,
+                               ctypes.byref(prm), _stream(), ctypes.byref(h)), "lcd_sweep_batch")
+    return Result(h, graph.n)
 
 
 def lcd_tune(graph: "Graph", scales, seed_ptr, seed_nodes, **base) -> dict:

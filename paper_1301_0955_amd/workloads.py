@@ -462,3 +462,27 @@ def workload_large(seed: int = 1):
                          levels=3, weighted=True, seed=seed)
     sp, sn = seed_rule1(g, seed)
     return g, sp, sn, log_scales(64)
+
+
+def workload_multigraph(n_graphs: int = 64, nmin: int = 1000, nmax: int = 200_000, seed: int = 1):
+    """Independent graphs for one batched sweep: node counts log-uniform in
+    [nmin, nmax], each generated like the 100k workload (two levels, degree
+    exponent 2.5, mean 20, max 100, mixing 0.3) with weights 1..16; rule-1
+    seeds per graph (local ids); 32 scales on [0.5, 1].  Returns (graphs,
+    seed_ptr, seed_nodes, seed_graph, scales)."""
+    rng = _rng(seed + 7)
+    sizes = np.exp(rng.uniform(math.log(nmin), math.log(nmax), size=n_graphs)).astype(np.int64)
+    graphs, ptr, nodes, which = [], [np.zeros(1, np.int32)], [], []
+    total = 0
+    for i, n in enumerate(sizes.tolist()):
+        g = lfr_hierarchical(int(n), 2.5, 20.0, 100, 1.5, 20, 200, mu=0.3, levels=2,
+                             weighted=True, wmax=16, seed=seed * 1000 + i)
+        sp, sn = seed_rule1(g, seed * 1000 + i)
+        graphs.append(g)
+        ptr.append(sp[1:].astype(np.int64) + total)
+        nodes.append(sn)
+        which.append(np.full(sp.size - 1, i, np.int32))
+        total += int(sn.size)
+    seed_ptr = np.concatenate(ptr).astype(np.int32)
+    return (graphs, seed_ptr, np.concatenate(nodes).astype(np.int32),
+            np.concatenate(which).astype(np.int32), log_scales(32))

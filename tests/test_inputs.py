@@ -92,3 +92,14 @@ def test_query_stream_shape():
     assert np.all((alphas >= 0.5) & (alphas <= 1.0))
     for s in sets[:50]:
         assert np.all(np.diff(s) > 0)
+
+
+def test_multigraph_shape():
+    gs, sp, sn, sg, sc = W.workload_multigraph(5, 300, 2000, seed=3)
+    assert len(gs) == 5 and sc.size == 32
+    assert sp[0] == 0 and sp[-1] == sn.size and np.all(np.diff(sp) >= 1)
+    assert sg.size == sp.size - 1 and np.all(np.diff(sg) >= 0)
+    for j in range(sg.size):
+        assert np.all(sn[sp[j]:sp[j + 1]] < gs[sg[j]].n)
+    for g in gs:
+        assert 300 <= g.n <= 2000 and g.w is not None

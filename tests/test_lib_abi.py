@@ -100,3 +100,28 @@ def test_server_rejects_null_arguments(lib):
     assert lib.lcd_server_poll(None, 1, None, 0, None) == 1
     assert lib.lcd_server_wait(None, 1, 0) == 1
     assert lib.lcd_server_destroy(None) == 0
+
+
+@pytest.mark.parametrize("case", ["local_range", "row_end", "offsets"])
+def test_batch_upload_rejects(lib, case):
+    """Batch upload validates each member graph in its local ids on the host."""
+    P = ctypes.c_void_p
+    lib.lcd_graph_upload_batch.restype = ctypes.c_int
+    lib.lcd_graph_upload_batch.argtypes = [ctypes.c_int32, P, P, P, P, P, ctypes.c_int32, P,
+                                           ctypes.POINTER(P)]
+    # two paths 0-1-2 (local ids)
+    node_off = np.array([0, 3, 6], np.int64)
+    edge_off = np.array([0, 4, 8], np.int64)
+    rp = np.array([0, 1, 3, 4, 0, 1, 3, 4], np.int32)
+    col = np.array([1, 0, 2, 1, 1, 0, 2, 1], np.int32)
+    if case == "local_range":
+        col[5] = 3            # a batch id, not a local one
+    elif case == "row_end":
+        rp[7] = 3
+    elif case == "offsets":
+        edge_off[1] = 5
+    h = P()
+    st = lib.lcd_graph_upload_batch(2, node_off.ctypes.data_as(P), edge_off.ctypes.data_as(P),
+                                    rp.ctypes.data_as(P), col.ctypes.data_as(P), None, 0, None,
+                                    ctypes.byref(h))
+    assert st == 1, (case, st)
