@@ -83,6 +83,8 @@ def lib():
         L.lcdo_run_set.argtypes = [P, P, ctypes.c_int32, P, ctypes.c_int32,
                                    ctypes.c_uint32, P, ctypes.c_int64, P, P, P, P,
                                    P, ctypes.POINTER(Trace)]
+        L.lcdo_seeds.restype = ctypes.c_int64
+        L.lcdo_seeds.argtypes = [P, P, ctypes.c_int, P]
         L.lcdo_run_sets.restype = ctypes.c_int
         L.lcdo_run_sets.argtypes = [P, P, P, ctypes.c_int32, P, ctypes.c_int32,
                                     ctypes.c_uint32, P, ctypes.c_int64, P, P, P, P,
@@ -139,6 +141,16 @@ class Oracle:
             self.close()
         except Exception:
             pass
+
+    def seeds(self, perm, rule: int = 1) -> np.ndarray:
+        """Seed selection of Algorithm 2 (rule 1 or 2) visiting nodes in the
+        order perm; the seeds in order of selection."""
+        perm = np.ascontiguousarray(perm, dtype=np.int32)
+        out = np.empty(max(self.n, 1), dtype=np.int32)
+        k = lib().lcdo_seeds(self._ctx, _ptr(perm), rule, _ptr(out))
+        if k < 0:
+            raise ValueError("perm is not a permutation of the nodes, or rule is not 1 or 2")
+        return out[:k].copy()
 
     def degrees(self) -> np.ndarray:
         p = lib().lcdo_degrees(self._ctx)

@@ -563,3 +563,52 @@ void lcdo_log_many(const uint64_t *x, double *out, int64_t n)
     for (int64_t i = 0; i < n; ++i)
         out[i] = lcdo_log(x[i]);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Seed selection (Sec. 3, initialisation part of Algorithm 2)              */
+/* ------------------------------------------------------------------------ */
+/*
+ * Candidates are the nodes with at least two neighbours.  Nodes are visited
+ * in the order perm[0 .. n) (the random choice of the paper, drawn by the
+ * caller); a visited node that is still a candidate becomes the next seed and
+ * leaves the candidate set together with its neighbours (rule 1), or with
+ * every node at most two hops away (rule 2: neighbours of neighbours too).
+ * Writes the seeds in order of selection to out (room for n ids) and returns
+ * their number; -1 if rule is not 1 or 2 or perm is not a permutation.
+ */
+int64_t lcdo_seeds(const lcdo_ctx *g, const int32_t *perm, int rule, int32_t *out)
+{
+    const int32_t n = g->n;
+    if (rule != 1 && rule != 2)
+        return -1;
+    uint8_t *cand = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
+    if (!cand)
+        return -1;
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t v = perm[i];
+        if (v < 0 || v >= n || cand[v] == 2) {
+            free(cand);
+            return -1;
+        }
+        cand[v] = 2; /* seen once */
+    }
+    for (int32_t u = 0; u < n; ++u)
+        cand[u] = (g->row_ptr[u + 1] - g->row_ptr[u]) >= 2;
+    int64_t ns = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t v = perm[i];
+        if (!cand[v])
+            continue;
+        out[ns++] = v;
+        cand[v] = 0;
+        for (int64_t j = g->row_ptr[v]; j < g->row_ptr[v + 1]; ++j) {
+            const int32_t u = g->col[j];
+            cand[u] = 0;
+            if (rule == 2)
+                for (int64_t q = g->row_ptr[u]; q < g->row_ptr[u + 1]; ++q)
+                    cand[g->col[q]] = 0;
+        }
+    }
+    free(cand);
+    return ns;
+}

@@ -364,6 +364,11 @@ def singleton_seeds(n: int) -> tuple[np.ndarray, np.ndarray]:
     return (np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32))
 
 
+def seed_permutation(g: Graph, seed: int) -> np.ndarray:
+    """The random visiting order of the seed rules (node ids, int32)."""
+    return _rng(seed + 1).permutation(g.n).astype(np.int32)
+
+
 def seed_rule1(g: Graph, seed: int) -> tuple[np.ndarray, np.ndarray]:
     """The paper's first seed rule (Sec. 3, seed initialisation of
     Algorithm 2): candidates are the nodes with at least two neighbours;

@@ -27,12 +27,16 @@ MUTANTS = {
     "volume_misses_new_node": ("g->V += g->k[u];\n    g->size += 1;\n    g->M += 1;",
                                "g->size += 1;\n    g->M += 1;"),
     "margin_dropped": ("return t > 0x1p-40;", "return t >= 0.0;"),
+    "seed_candidates_degree_one": ("cand[u] = (g->row_ptr[u + 1] - g->row_ptr[u]) >= 2;",
+                                   "cand[u] = (g->row_ptr[u + 1] - g->row_ptr[u]) >= 1;"),
+    "seed_rule2_one_hop": ("            if (rule == 2)\n                for (int64_t q",
+                           "            if (rule == 3)\n                for (int64_t q"),
     "rank_uses_d_out": ("lcdo_push(g, lcdo_rank(g->d[u], g->k[u], alpha), u, g->ver[u]);",
                         "lcdo_push(g, lcdo_rank(g->d[u], g->k[u] - g->d[u] + 1, alpha), u, g->ver[u]);"),
 }
 
 PINS = ["tests/test_oracle_bruteforce.py", "tests/test_oracle_replay.py",
-        "tests/test_oracle_limits.py", "tests/test_oracle_audit.py"]
+        "tests/test_oracle_limits.py", "tests/test_oracle_audit.py", "tests/test_oracle_seeds.py"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
