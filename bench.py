@@ -117,6 +117,11 @@ def profiled_traffic(kernel: str, tier_caps, workload_name: str):
     return json.loads(m_tr.group(1)).get(kernel)
 
 
+def W_seed_perm(g):
+    from paper_1301_0955_amd import workloads as W
+    return W.seed_permutation(g, 1)
+
+
 def percentiles(x):
     x = np.asarray(x, dtype=np.float64)
     if x.size == 0:
@@ -396,6 +401,23 @@ def main():
         cpu = cpu_baseline(g, sp, sn, sc, stride, got)
         log("cpu baseline: %s" % cpu["sample"])
 
+    # seed selection (initialisation of Algorithm 2) on the device vs the oracle
+    seeds_info = {}
+    perm = W_seed_perm(g)
+    for rule in (1, 2):
+        t0 = time.perf_counter()
+        dev = lcd.lcd_seeds(G, perm, rule)
+        t_dev = time.perf_counter() - t0
+        entry = dict(seeds=int(dev.size), ms_device_call=round(t_dev * 1e3, 3))
+        if not args.no_cpu_baseline:
+            import oracle
+            t0 = time.perf_counter()
+            ref = oracle.Oracle.from_graph(g).seeds(perm, rule)
+            entry["ms_oracle_1core"] = round((time.perf_counter() - t0) * 1e3, 3)
+            entry["identical"] = bool(np.array_equal(dev, ref))
+        seeds_info["rule%d" % rule] = entry
+    log("seed selection: %s" % seeds_info)
+
     large = serving = None
     if not (args.no_large and args.no_serve) and args.workload != "large":
         t0 = time.perf_counter()
@@ -476,6 +498,7 @@ def main():
         "roofline": roofline,
         "per_scale_loop": loop,
         "cpu_baseline": cpu,
+        "seed_selection": seeds_info,
         "large_sweep": large,
         "serving": serving,
         "multigraph": multi,

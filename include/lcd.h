@@ -227,6 +227,21 @@ lcd_status lcd_tune(lcd_graph *g, const double *scales, int32_t n_scales, const 
 lcd_status lcd_graph_untune(lcd_graph *g);
 
 /*
+ * Seed selection of the initialisation step of Algorithm 2 (Sec. 3) on the
+ * device.  Candidates are the nodes with at least two neighbours; nodes are
+ * visited in the order perm (int32[n], a permutation of 0..n-1: the random
+ * choice, drawn by the caller); a visited node that is still a candidate
+ * becomes a seed and drops its neighbours (rule 1) or every node within two
+ * hops (rule 2) from the candidates.  out_seeds (int32[n], mem_kind memory)
+ * receives the seeds in order of selection, *n_seeds their number; seed j
+ * is the singleton seed set j of a sweep.  Computed in parallel rounds that
+ * give exactly the sequential result.  LCD_EINVAL if perm is not a
+ * permutation.  Blocking.
+ */
+lcd_status lcd_seeds(const lcd_graph *g, int32_t rule, const int32_t *perm, int32_t mem_kind, void *stream,
+                     int32_t *out_seeds, int32_t *n_seeds);
+
+/*
  * lcd_sweep over a batch graph with graph-local seeds: seed set j lives in
  * member graph seed_graph[j] (int32[n_sets], in mem_kind memory) and its
  * seed ids are local to that graph.  The result is that of lcd_sweep() on

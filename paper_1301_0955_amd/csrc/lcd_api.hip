@@ -839,6 +839,97 @@ lcd_status lcd_sweep(const lcd_graph *g, const double *scales, int32_t n_scales,
     return LCD_OK;
 }
 
+lcd_status lcd_seeds(const lcd_graph *g, int32_t rule, const int32_t *perm, int32_t mem_kind, void *stream,
+                     int32_t *out_seeds, int32_t *n_seeds) {
+    if (!g || !out_seeds || !n_seeds)
+        return fail(LCD_EINVAL, "null argument");
+    if (rule != 1 && rule != 2)
+        return fail(LCD_EINVAL, "rule must be 1 or 2");
+    if (mem_kind != LCD_MEM_HOST && mem_kind != LCD_MEM_DEVICE)
+        return fail(LCD_EINVAL, "unknown mem_kind %d", mem_kind);
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t n = g->n;
+    std::vector<int32_t> ph;
+    CHK(fetch(ph, perm, (size_t)n, mem_kind, st));
+    {
+        std::vector<uint8_t> seen((size_t)std::max(n, 1), 0);
+        for (int32_t i = 0; i < n; ++i) {
+            if (ph[i] < 0 || ph[i] >= n || seen[ph[i]])
+                return fail(LCD_EINVAL, "perm is not a permutation of the node ids (entry %d)", i);
+            seen[ph[i]] = 1;
+        }
+    }
+    *n_seeds = 0;
+    if (n == 0)
+        return LCD_OK;
+    const int nb = (int)(((int64_t)n + 1023) / 1024);
+    int32_t *d_perm = nullptr, *pos = nullptr, *flag = nullptr, *at = nullptr, *bs = nullptr, *out = nullptr;
+    uint8_t *stt = nullptr, *sel = nullptr;
+    unsigned *cnt = nullptr;
+    auto release = [&]() {
+        dev_free(d_perm);
+        dev_free(pos);
+        dev_free(flag);
+        dev_free(at);
+        dev_free(bs);
+        dev_free(stt);
+        dev_free(sel);
+        dev_free(cnt);
+        if (mem_kind == LCD_MEM_HOST)
+            dev_free(out);
+    };
+    lcd_status s = LCD_OK;
+    if ((s = dev_alloc(&d_perm, n)) != LCD_OK || (s = dev_alloc(&pos, n)) != LCD_OK ||
+        (s = dev_alloc(&flag, n)) != LCD_OK || (s = dev_alloc(&at, n)) != LCD_OK ||
+        (s = dev_alloc(&bs, (size_t)nb + 1)) != LCD_OK || (s = dev_alloc(&stt, n)) != LCD_OK ||
+        (s = dev_alloc(&sel, n)) != LCD_OK || (s = dev_alloc(&cnt, 1)) != LCD_OK) {
+        release();
+        return s;
+    }
+    if (mem_kind == LCD_MEM_HOST) {
+        if ((s = dev_alloc(&out, n)) != LCD_OK) {
+            release();
+            return s;
+        }
+    } else {
+        out = out_seeds;
+    }
+    hipError_t e = hipMemcpyAsync(d_perm, ph.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = launch_seed_init(g->row_ptr, d_perm, n, pos, stt, st);
+    // each round settles at least the first undecided candidate in visiting
+    // order, so at most n rounds run; usually a few dozen
+    int64_t rounds = 0;
+    for (; e == hipSuccess && rounds <= (int64_t)n; ++rounds) {
+        unsigned undecided = 0;
+        e = launch_zero_bytes(cnt, 4, st);
+        if (e == hipSuccess)
+            e = launch_seed_round(rule, g->row_ptr, g->col, pos, stt, sel, n, cnt, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&undecided, cnt, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e == hipSuccess && undecided == 0)
+            break;
+    }
+    int32_t total = 0;
+    if (e == hipSuccess)
+        e = launch_seed_collect(d_perm, stt, n, flag, at, bs, out, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&total, bs + nb, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && mem_kind == LCD_MEM_HOST)
+        e = hipMemcpyAsync(out_seeds, out, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    release();
+    if (e != hipSuccess)
+        return fail(LCD_EDEVICE, "seed selection: %s", hipGetErrorString(e));
+    if (rounds > (int64_t)n)
+        return fail(LCD_EDEVICE, "seed selection did not settle in %d rounds", n);
+    *n_seeds = total;
+    return LCD_OK;
+}
+
 lcd_status lcd_sweep_batch(const lcd_graph *g, const double *scales, int32_t n_scales,
                            const int32_t *seed_ptr, const int32_t *seed_nodes, const int32_t *seed_graph,
                            int32_t n_sets, int32_t mem_kind, const lcd_params *params, void *stream,

@@ -120,5 +120,17 @@ hipError_t launch_overlap(const int32_t *comm_ptr, const int32_t *members, int64
                           int32_t *cnt, int32_t *block_sums, hipStream_t st);
 hipError_t launch_counter_sum(const uint64_t *ctr, int64_t n_rec, unsigned long long *tot,
                               hipStream_t st);
+// exclusive scan of n int32 into out[0..n); block_sums: ceil(n/1024)+1 entries,
+// the total lands in block_sums[ceil(n/1024)]
+hipError_t launch_exclusive_scan(const int32_t *in, int64_t n, int32_t *out, int32_t *block_sums,
+                                 hipStream_t st);
+// seed selection: pos/st setup, one selection round (adds the number of
+// undecided candidates at its start to *undecided), and the ordered output
+hipError_t launch_seed_init(const int32_t *row_ptr, const int32_t *perm, int32_t n, int32_t *pos,
+                            uint8_t *st, hipStream_t s);
+hipError_t launch_seed_round(int32_t rule, const int32_t *row_ptr, const int32_t *col, const int32_t *pos,
+                             uint8_t *st, uint8_t *sel, int32_t n, unsigned *undecided, hipStream_t s);
+hipError_t launch_seed_collect(const int32_t *perm, const uint8_t *st, int32_t n, int32_t *flag, int32_t *at,
+                               int32_t *block_sums, int32_t *out, hipStream_t s);
 
 }  // namespace lcd

@@ -1534,6 +1534,96 @@ __global__ void overlap_count_kernel(const int32_t *members, int64_t total, int3
         atomicAdd(&cnt[members[i]], 1);
 }
 
+// ---------------------------------------------------------------------------
+// Seed selection (Sec. 3, initialisation of Algorithm 2) in parallel rounds.
+// Candidate nodes (at least two neighbours) are visited in the order perm;
+// the sequential rule keeps a node that is still a candidate and drops its
+// neighbours (rule 1) or everything within two hops (rule 2).  That set is
+// the first independent set in visiting order of the conflict graph (two
+// candidates conflict within 1 or 2 hops), which rounds of "an undecided
+// candidate joins when it comes first among the undecided candidates it
+// conflicts with" produce exactly (Blelloch, Fineman and Shun, SPAA 2012).
+// st: 0 undecided candidate, 1 seed, 2 not a seed.
+// ---------------------------------------------------------------------------
+
+__global__ void seed_init_kernel(const int32_t *row_ptr, const int32_t *perm, int32_t n, int32_t *pos,
+                                 uint8_t *st) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        pos[perm[i]] = (int32_t)i;
+        st[i] = (row_ptr[i + 1] - row_ptr[i]) >= 2 ? 0 : 2;
+    }
+}
+
+template <int R>
+__global__ void seed_select_kernel(const int32_t *row_ptr, const int32_t *col, const int32_t *pos,
+                                   const uint8_t *st, uint8_t *sel, int32_t n, unsigned *undecided) {
+    unsigned cnt = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        uint8_t ok = 0;
+        if (st[v] == 0) {
+            cnt += 1;
+            ok = 1;
+            const int32_t pv = pos[v];
+            for (int32_t j = row_ptr[v]; j < row_ptr[v + 1] && ok; ++j) {
+                const int32_t u = col[j];
+                if (st[u] == 0 && pos[u] < pv)
+                    ok = 0;
+                if constexpr (R == 2) {
+                    for (int32_t q = row_ptr[u]; q < row_ptr[u + 1] && ok; ++q) {
+                        const int32_t w = col[q];
+                        if (w != v && st[w] == 0 && pos[w] < pv)
+                            ok = 0;
+                    }
+                }
+            }
+        }
+        sel[v] = ok;
+    }
+    if (cnt)
+        atomicAdd(undecided, cnt);
+}
+
+// Selected nodes are pairwise further apart than R hops, so every write
+// below is the same value from whichever thread makes it.
+template <int R>
+__global__ void seed_apply_kernel(const int32_t *row_ptr, const int32_t *col, const uint8_t *sel,
+                                  uint8_t *st, int32_t n) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        if (!sel[v])
+            continue;
+        st[v] = 1;
+        for (int32_t j = row_ptr[v]; j < row_ptr[v + 1]; ++j) {
+            const int32_t u = col[j];
+            if (st[u] == 0)
+                st[u] = 2;
+            if constexpr (R == 2) {
+                for (int32_t q = row_ptr[u]; q < row_ptr[u + 1]; ++q) {
+                    const int32_t w = col[q];
+                    if (w != v && st[w] == 0)
+                        st[w] = 2;
+                }
+            }
+        }
+    }
+}
+
+__global__ void seed_flag_kernel(const int32_t *perm, const uint8_t *st, int32_t n, int32_t *flag) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        flag[i] = st[perm[i]] == 1 ? 1 : 0;
+}
+
+__global__ void seed_scatter_kernel(const int32_t *perm, const int32_t *flag, const int32_t *at, int32_t n,
+                                    int32_t *out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (flag[i])
+            out[at[i]] = perm[i];
+}
+
 // three-phase exclusive scan of n counts into ptr[0..n]
 __global__ void __launch_bounds__(1024) scan_blocks_kernel(const int32_t *cnt, int64_t n,
                                                            int32_t *ptr, int32_t *block_sums) {
@@ -1802,6 +1892,56 @@ hipError_t launch_overlap(const int32_t *comm_ptr, const int32_t *members, int64
         hipLaunchKernelGGL(overlap_sort_kernel, dim3((int)((waves + 3) / 4)), dim3(256), 0, st, node_ptr,
                            n, node_sets);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_exclusive_scan(const int32_t *in, int64_t n, int32_t *out, int32_t *block_sums,
+                                 hipStream_t st) {
+    const int nb = (int)((n + 1023) / 1024);
+    if (nb == 0)
+        return hipSuccess;
+    if (nb > 1024 * 1024)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3(nb), dim3(1024), 0, st, in, n, out, block_sums);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, st, block_sums, nb, block_sums + nb);
+    hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(1024), 0, st, out, n, block_sums);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_init(const int32_t *row_ptr, const int32_t *perm, int32_t n, int32_t *pos,
+                            uint8_t *st, hipStream_t s) {
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(seed_init_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, row_ptr, perm, n, pos, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_round(int32_t rule, const int32_t *row_ptr, const int32_t *col, const int32_t *pos,
+                             uint8_t *st, uint8_t *sel, int32_t n, unsigned *undecided, hipStream_t s) {
+    if (n == 0)
+        return hipSuccess;
+    const dim3 g(grid_for(n, 256)), b(256);
+    if (rule == 1) {
+        hipLaunchKernelGGL(seed_select_kernel<1>, g, b, 0, s, row_ptr, col, pos, st, sel, n, undecided);
+        hipLaunchKernelGGL(seed_apply_kernel<1>, g, b, 0, s, row_ptr, col, sel, st, n);
+    } else if (rule == 2) {
+        hipLaunchKernelGGL(seed_select_kernel<2>, g, b, 0, s, row_ptr, col, pos, st, sel, n, undecided);
+        hipLaunchKernelGGL(seed_apply_kernel<2>, g, b, 0, s, row_ptr, col, sel, st, n);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_collect(const int32_t *perm, const uint8_t *st, int32_t n, int32_t *flag, int32_t *at,
+                               int32_t *block_sums, int32_t *out, hipStream_t s) {
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(seed_flag_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, perm, st, n, flag);
+    hipError_t e = launch_exclusive_scan(flag, n, at, block_sums, s);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(seed_scatter_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, perm, flag, at, n, out);
     return hipGetLastError();
 }
 

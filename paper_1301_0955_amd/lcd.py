@@ -126,6 +126,7 @@ def library() -> ctypes.CDLL:
         "lcd_graph_upload_batch": (st, [ctypes.c_int32, P, P, P, P, P, ctypes.c_int32, P,
                                         ctypes.POINTER(P)]),
         "lcd_graph_batch_info": (st, [P, ctypes.POINTER(ctypes.c_int32), P]),
+        "lcd_seeds": (st, [P, ctypes.c_int32, P, ctypes.c_int32, P, P, ctypes.POINTER(ctypes.c_int32)]),
         "lcd_sweep_batch": (st, [P, P, ctypes.c_int32, P, P, P, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.POINTER(lcd_params), P, ctypes.POINTER(P)]),
         "lcd_sweep": (st, [P, P, ctypes.c_int32, P, P, ctypes.c_int32, ctypes.c_int32,
@@ -471,6 +472,17 @@ def sweep_to_numpy(res: Result) -> dict:
     _, ctr = res.counters(per_record=True)
     return dict(members=members, off=offs, cnt=cnt, K=K, V=V, f=f,
                 ctr=ctr.cpu().numpy().astype(np.uint64), n_sets=ns, n_scales=S)
+
+
+def lcd_seeds(graph: "Graph", perm, rule: int = 1) -> np.ndarray:
+    """Seed selection (rule 1 or 2) on the device, visiting nodes in the order
+    perm; the seeds in order of selection (host array)."""
+    p = np.ascontiguousarray(perm, dtype=np.int32)
+    out = np.zeros(max(p.size, 1), np.int32)
+    k = ctypes.c_int32()
+    _check(library().lcd_seeds(graph._h, int(rule), p.ctypes.data_as(P), LCD_MEM_HOST, _stream(),
+                               out.ctypes.data_as(P), ctypes.byref(k)), "lcd_seeds")
+    return out[:k.value].copy()
 
 
 def lcd_sweep_batch(graph: "Graph", scales, seed_ptr, seed_nodes, seed_graph, params=None, **kw):

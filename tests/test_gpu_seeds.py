@@ -1,0 +1,55 @@
+"""Seed selection on the device (lcd_seeds) equals the oracle's sequential
+rule, seed for seed and in order, for both rules, on graphs from 300 to
+1,000,000 nodes; and rule 1 equals the seeds the workloads use."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1301_0955_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1301_0955_amd import lcd
+    lcd.library()
+    return lcd
+
+
+@pytest.mark.parametrize("which", ["random", "small", "medium"])
+@pytest.mark.parametrize("rule", [1, 2])
+def test_seeds_match_oracle(L, which, rule):
+    if which == "random":
+        g, s = W.random_graph(300, 0.02, False, 7), 7
+    elif which == "small":
+        g, s = W.workload_small()[0], 1
+    else:
+        g, s = W.workload_medium()[0], 1
+    perm = W.seed_permutation(g, s)
+    got = L.lcd_seeds(L.Graph.from_workload(g), perm, rule)
+    ref = oracle.Oracle.from_graph(g).seeds(perm, rule)
+    assert np.array_equal(got, ref)
+    if rule == 1 and which != "random":
+        assert np.array_equal(got, W.seed_rule1(g, s)[1])
+
+
+def test_seeds_large_rule1(L):
+    g, sp, sn, _ = W.workload_large()
+    got = L.lcd_seeds(L.Graph.from_workload(g), W.seed_permutation(g, 1), 1)
+    assert np.array_equal(got, sn)
+
+
+def test_seeds_reject_non_permutation(L):
+    g = W.workload_small()[0]
+    G = L.Graph.from_workload(g)
+    bad = np.arange(g.n, dtype=np.int32)
+    bad[3] = 4
+    with pytest.raises(L.LcdError) as e:
+        L.lcd_seeds(G, bad, 1)
+    assert e.value.status == L.LCD_EINVAL
+    with pytest.raises(L.LcdError):
+        L.lcd_seeds(G, np.arange(g.n), 3)
