@@ -83,6 +83,10 @@ def lib():
         L.lcdo_run_set.argtypes = [P, P, ctypes.c_int32, P, ctypes.c_int32,
                                    ctypes.c_uint32, P, ctypes.c_int64, P, P, P, P,
                                    P, ctypes.POINTER(Trace)]
+        L.lcdo_run_merge.restype = ctypes.c_int
+        L.lcdo_run_merge.argtypes = [P, P, P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_uint32,
+                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int64,
+                                     ctypes.POINTER(ctypes.c_int64), P, P, P, P, P, P, P, P]
         L.lcdo_seeds.restype = ctypes.c_int64
         L.lcdo_seeds.argtypes = [P, P, ctypes.c_int, P]
         L.lcdo_run_sets.restype = ctypes.c_int
@@ -141,6 +145,42 @@ class Oracle:
             self.close()
         except Exception:
             pass
+
+    def run_merge(self, seed_ptr, seed_nodes, scales, k_prune: int = 0, eta=(1, 2),
+                  max_rounds: int = 100000) -> dict:
+        """Algorithm 2 with its check-and-merge phase; records laid out like
+        run_sets(), plus into[R] (-1 live, else the live id merged into) and
+        rounds[S]."""
+        sp = np.ascontiguousarray(seed_ptr, dtype=np.int32)
+        sn = np.ascontiguousarray(seed_nodes, dtype=np.int32)
+        sc = np.ascontiguousarray(scales, dtype=np.float64)
+        ns, S = sp.size - 1, sc.size
+        R = ns * S
+        off = np.zeros(max(R, 1), np.int64)
+        cnt = np.zeros(max(R, 1), np.int32)
+        K = np.zeros(max(R, 1), np.int64)
+        V = np.zeros(max(R, 1), np.int64)
+        f = np.zeros(max(R, 1), np.float64)
+        ctr = np.zeros(max(R, 1) * 4, np.uint64)
+        into = np.zeros(max(R, 1), np.int32)
+        rounds = np.zeros(max(S, 1), np.int32)
+        needed = ctypes.c_int64()
+        cap = max(1024, 4 * self.n)
+        for _ in range(4):
+            members = np.empty(cap, np.int32)
+            rc = lib().lcdo_run_merge(self._ctx, _ptr(sp), _ptr(sn), ns, _ptr(sc), S, k_prune,
+                                      int(eta[0]), int(eta[1]), max_rounds, _ptr(members), cap,
+                                      ctypes.byref(needed), _ptr(off), _ptr(cnt), _ptr(K), _ptr(V),
+                                      _ptr(f), _ptr(ctr), _ptr(into), _ptr(rounds))
+            if rc == -1:
+                cap = needed.value
+                continue
+            if rc != 0:
+                raise RuntimeError("lcdo_run_merge failed (%d)" % rc)
+            return dict(members=members[:needed.value].copy(), off=off[:R], cnt=cnt[:R], K=K[:R], V=V[:R],
+                        f=f[:R], ctr=ctr[:R * 4].reshape(R, 4), into=into[:R], rounds=rounds[:S],
+                        n_sets=ns, n_scales=S)
+        raise RuntimeError("lcdo_run_merge: member buffer did not converge")
 
     def seeds(self, perm, rule: int = 1) -> np.ndarray:
         """Seed selection of Algorithm 2 (rule 1 or 2) visiting nodes in the

@@ -612,3 +612,366 @@ int64_t lcdo_seeds(const lcdo_ctx *g, const int32_t *perm, int rule, int32_t *ou
     free(cand);
     return ns;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Check-and-merge phase (Sec. 3, Algorithm 2; overlap pre-test of          */
+/* Algorithm 3)                                                              */
+/* ------------------------------------------------------------------------ */
+/*
+ * Reading (each point also in the design notes):
+ *   M1 the scale loop of Algorithm 2 runs rounds until a round neither grows
+ *      a community nor merges two;
+ *   M2 memberships M[v] = the live communities holding v, ascending ids,
+ *      rebuilt at the start of a round and again after its growth;
+ *   M3 overlap count of c with i: walk c's members ascending and, for each,
+ *      M[v] ascending; c and i "reach the threshold" when the running count
+ *      x satisfies x * eta_den >= eta_num * min(|c|, |i|) (eta = 1/2 by
+ *      default: at least half of the smaller one); the first such i is c's
+ *      partner;
+ *   M4 pre-test (Algorithm 3): a live community with a partner under the
+ *      round's first M is not grown in that round;
+ *   M5 growth: every other community that needs it grows to its fixpoint at
+ *      the scale (one-scale lcdo_run_set from its members); at the start of
+ *      a scale all live communities need it, later only merged survivors;
+ *   M6 check: for each pre-tested or changed community, ascending, its
+ *      partner under the post-growth M gives the pair (min, max);
+ *   M7 merge: the pairs sorted ascending without repeats; repeatedly take,
+ *      in order, the pairs that share no community, merge each into its
+ *      lower id (union of members; the higher id dies and is renamed to the
+ *      lower one in the remaining pairs), until no pair is left;
+ *   M8 records: a live community reports its members, K, V, f at the scale
+ *      and the counters summed over its growths at that scale; a dead one
+ *      reports no members, K = V = 0, and the live id it was merged into.
+ */
+typedef struct {
+    int32_t ns;
+    int32_t **mem;
+    int32_t *msz, *mcap;
+    uint8_t *alive;
+    int32_t *into;
+    int64_t *node_ptr;   /* memberships, n + 1 */
+    int32_t *node_list;
+    int64_t list_cap;
+    int32_t *cnt, *touched;
+} lcdo_merge;
+
+static int lcdo_mg_memberships(const lcdo_ctx *g, lcdo_merge *m)
+{
+    const int32_t n = g->n;
+    memset(m->node_ptr, 0, sizeof(int64_t) * (size_t)(n + 1));
+    for (int32_t j = 0; j < m->ns; ++j)
+        if (m->alive[j])
+            for (int32_t q = 0; q < m->msz[j]; ++q)
+                m->node_ptr[m->mem[j][q] + 1] += 1;
+    for (int32_t v = 0; v < n; ++v)
+        m->node_ptr[v + 1] += m->node_ptr[v];
+    const int64_t total = m->node_ptr[n];
+    if (total > m->list_cap) {
+        int32_t *p = (int32_t *)realloc(m->node_list, sizeof(int32_t) * (size_t)(total > 0 ? total : 1));
+        if (!p)
+            return -1;
+        m->node_list = p;
+        m->list_cap = total;
+    }
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!fill)
+        return -1;
+    memcpy(fill, m->node_ptr, sizeof(int64_t) * (size_t)n);
+    for (int32_t j = 0; j < m->ns; ++j)       /* ascending ids per node */
+        if (m->alive[j])
+            for (int32_t q = 0; q < m->msz[j]; ++q)
+                m->node_list[fill[m->mem[j][q]]++] = j;
+    free(fill);
+    return 0;
+}
+
+static int32_t lcdo_mg_partner(lcdo_merge *m, int32_t c, int32_t eta_num, int32_t eta_den)
+{
+    int32_t nt = 0, found = -1;
+    for (int32_t q = 0; q < m->msz[c] && found < 0; ++q) {
+        const int32_t v = m->mem[c][q];
+        for (int64_t t = m->node_ptr[v]; t < m->node_ptr[v + 1]; ++t) {
+            const int32_t i = m->node_list[t];
+            if (i == c)
+                continue;
+            if (m->cnt[i]++ == 0)
+                m->touched[nt++] = i;
+            const int64_t small = m->msz[c] < m->msz[i] ? m->msz[c] : m->msz[i];
+            if ((int64_t)m->cnt[i] * eta_den >= (int64_t)eta_num * small) {
+                found = i;
+                break;
+            }
+        }
+    }
+    for (int32_t t = 0; t < nt; ++t)
+        m->cnt[m->touched[t]] = 0;
+    return found;
+}
+
+static int lcdo_cmp_pair(const void *a, const void *b)
+{
+    const int32_t *x = (const int32_t *)a, *y = (const int32_t *)b;
+    if (x[0] != y[0])
+        return (x[0] > y[0]) - (x[0] < y[0]);
+    return (x[1] > y[1]) - (x[1] < y[1]);
+}
+
+/* union of two ascending lists into a (reallocated) */
+static int lcdo_mg_union(lcdo_merge *m, int32_t a, int32_t b)
+{
+    const int32_t na = m->msz[a], nb = m->msz[b];
+    int32_t *u = (int32_t *)malloc(sizeof(int32_t) * (size_t)(na + nb + 1));
+    if (!u)
+        return -1;
+    int32_t i = 0, j = 0, k = 0;
+    while (i < na || j < nb) {
+        if (j >= nb || (i < na && m->mem[a][i] < m->mem[b][j]))
+            u[k++] = m->mem[a][i++];
+        else if (i >= na || m->mem[b][j] < m->mem[a][i])
+            u[k++] = m->mem[b][j++];
+        else {
+            u[k++] = m->mem[a][i++];
+            ++j;
+        }
+    }
+    free(m->mem[a]);
+    m->mem[a] = u;
+    m->msz[a] = k;
+    m->mcap[a] = na + nb + 1;
+    return 0;
+}
+
+/*
+ * Seed sets j = seed_nodes[seed_ptr[j] .. seed_ptr[j+1]), scales as in
+ * lcdo_run_sets.  Record r = j * S + s: members at out_members[out_off[r] ..
+ * out_off[r] + out_cnt[r]), out_K, out_V, out_f, out_ctr (4 per record),
+ * out_into (-1 for a live community, else the live id it merged into).
+ * out_rounds[s]: rounds the scale took.  Returns 0, -1 when members_cap is
+ * too small (*needed set), -2 on allocation failure, -3 when a scale does
+ * not settle within max_rounds rounds.
+ */
+int lcdo_run_merge(lcdo_ctx *g, const int32_t *seed_ptr, const int32_t *seed_nodes, int32_t ns,
+                   const double *scales, int32_t S, uint32_t k_prune, int32_t eta_num,
+                   int32_t eta_den, int32_t max_rounds, int32_t *out_members, int64_t members_cap,
+                   int64_t *needed, int64_t *out_off, int32_t *out_cnt, int64_t *out_K,
+                   int64_t *out_V, double *out_f, uint64_t *out_ctr, int32_t *out_into,
+                   int32_t *out_rounds)
+{
+    const int32_t n = g->n;
+    lcdo_merge m;
+    memset(&m, 0, sizeof(m));
+    m.ns = ns;
+    size_t nn = (size_t)(ns > 0 ? ns : 1);
+    m.mem = (int32_t **)calloc(nn, sizeof(int32_t *));
+    m.msz = (int32_t *)calloc(nn, sizeof(int32_t));
+    m.mcap = (int32_t *)calloc(nn, sizeof(int32_t));
+    m.alive = (uint8_t *)calloc(nn, 1);
+    m.into = (int32_t *)calloc(nn, sizeof(int32_t));
+    m.node_ptr = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    m.cnt = (int32_t *)calloc(nn, sizeof(int32_t));
+    m.touched = (int32_t *)calloc(nn, sizeof(int32_t));
+    int64_t *K = (int64_t *)calloc(nn, sizeof(int64_t));
+    int64_t *V = (int64_t *)calloc(nn, sizeof(int64_t));
+    uint64_t *acc = (uint64_t *)calloc(nn * 4, sizeof(uint64_t));
+    uint8_t *need = (uint8_t *)calloc(nn, 1), *flag = (uint8_t *)calloc(nn, 1), *changed = (uint8_t *)calloc(nn, 1);
+    int32_t *pairs = (int32_t *)malloc(sizeof(int32_t) * 2 * nn);
+    int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *used = (int32_t *)calloc(nn, sizeof(int32_t));
+    int32_t *ren = (int32_t *)malloc(sizeof(int32_t) * 2 * nn);   /* dead id -> survivor, one pass */
+    int status = 0;
+    if (!m.mem || !m.msz || !m.mcap || !m.alive || !m.into || !m.node_ptr || !m.cnt || !m.touched || !K ||
+        !V || !acc || !need || !flag || !changed || !pairs || !tmp || !used || !ren) {
+        status = -2;
+        goto done;
+    }
+    for (int32_t j = 0; j < ns; ++j) {
+        const int32_t c = seed_ptr[j + 1] - seed_ptr[j];
+        m.mem[j] = (int32_t *)malloc(sizeof(int32_t) * (size_t)(c > 0 ? c : 1));
+        if (!m.mem[j]) {
+            status = -2;
+            goto done;
+        }
+        memcpy(m.mem[j], seed_nodes + seed_ptr[j], sizeof(int32_t) * (size_t)c);
+        qsort(m.mem[j], (size_t)c, sizeof(int32_t), lcdo_cmp_i32);
+        m.msz[j] = c;
+        m.mcap[j] = c;
+        m.alive[j] = 1;
+        m.into[j] = -1;
+    }
+    int64_t base = 0;
+    for (int32_t s = 0; s < S; ++s) {
+        const double alpha = scales[s];
+        memset(acc, 0, sizeof(uint64_t) * 4 * nn);
+        for (int32_t j = 0; j < ns; ++j)
+            need[j] = m.alive[j];
+        int32_t rounds = 0;
+        for (;;) {
+            if (++rounds > max_rounds) {
+                status = -3;
+                goto done;
+            }
+            if (lcdo_mg_memberships(g, &m) != 0) {
+                status = -2;
+                goto done;
+            }
+            for (int32_t j = 0; j < ns; ++j)
+                flag[j] = m.alive[j] && lcdo_mg_partner(&m, j, eta_num, eta_den) >= 0;
+            int grew = 0;
+            for (int32_t j = 0; j < ns; ++j) {
+                changed[j] = 0;
+                if (!m.alive[j] || !need[j] || flag[j])
+                    continue;
+                int64_t off2[2];
+                int64_t k1, v1;
+                double f1;
+                uint64_t c4[4];
+                if (lcdo_run_set(g, m.mem[j], m.msz[j], &alpha, 1, k_prune, tmp, n, off2, &k1, &v1, &f1,
+                                 c4, NULL) != 0) {
+                    status = -2;
+                    goto done;
+                }
+                const int32_t sz = (int32_t)(off2[1] - off2[0]);
+                changed[j] = sz != m.msz[j] || memcmp(tmp, m.mem[j], sizeof(int32_t) * (size_t)sz) != 0;
+                if (sz > m.mcap[j]) {
+                    int32_t *p = (int32_t *)realloc(m.mem[j], sizeof(int32_t) * (size_t)sz);
+                    if (!p) {
+                        status = -2;
+                        goto done;
+                    }
+                    m.mem[j] = p;
+                    m.mcap[j] = sz;
+                }
+                memcpy(m.mem[j], tmp, sizeof(int32_t) * (size_t)sz);
+                m.msz[j] = sz;
+                K[j] = k1;
+                V[j] = v1;
+                for (int q = 0; q < 4; ++q)
+                    acc[4 * j + q] += c4[q];
+                need[j] = 0;
+                grew |= changed[j];
+            }
+            if (lcdo_mg_memberships(g, &m) != 0) {
+                status = -2;
+                goto done;
+            }
+            int32_t np = 0;
+            for (int32_t j = 0; j < ns; ++j) {
+                if (!m.alive[j] || !(flag[j] || changed[j]))
+                    continue;
+                const int32_t i = lcdo_mg_partner(&m, j, eta_num, eta_den);
+                if (i >= 0) {
+                    pairs[2 * np] = i < j ? i : j;
+                    pairs[2 * np + 1] = i < j ? j : i;
+                    ++np;
+                }
+            }
+            const int merged = np > 0;
+            while (np > 0) {
+                qsort(pairs, (size_t)np, 2 * sizeof(int32_t), lcdo_cmp_pair);
+                int32_t w = 0;       /* drop repeats */
+                for (int32_t p = 0; p < np; ++p)
+                    if (w == 0 || pairs[2 * p] != pairs[2 * (w - 1)] || pairs[2 * p + 1] != pairs[2 * (w - 1) + 1]) {
+                        pairs[2 * w] = pairs[2 * p];
+                        pairs[2 * w + 1] = pairs[2 * p + 1];
+                        ++w;
+                    }
+                np = w;
+                /* take, in order, the pairs sharing no community */
+                for (int32_t p = 0; p < np; ++p)
+                    used[pairs[2 * p]] = used[pairs[2 * p + 1]] = 0;
+                int32_t rest = 0;
+                int32_t nren = 0;
+                for (int32_t p = 0; p < np; ++p) {
+                    const int32_t a = pairs[2 * p], b = pairs[2 * p + 1];
+                    if (!used[a] && !used[b]) {
+                        used[a] = used[b] = 1;
+                        if (lcdo_mg_union(&m, a, b) != 0) {
+                            status = -2;
+                            goto done;
+                        }
+                        m.alive[b] = 0;
+                        m.into[b] = a;
+                        need[a] = 1;
+                        ren[2 * nren] = b;
+                        ren[2 * nren + 1] = a;
+                        ++nren;
+                    } else {
+                        pairs[2 * rest] = a;
+                        pairs[2 * rest + 1] = b;
+                        ++rest;
+                    }
+                }
+                /* rename the dead ids in the remaining pairs */
+                np = 0;
+                for (int32_t p = 0; p < rest; ++p) {
+                    int32_t a = pairs[2 * p], b = pairs[2 * p + 1];
+                    for (int32_t r = 0; r < nren; ++r) {
+                        if (a == ren[2 * r])
+                            a = ren[2 * r + 1];
+                        if (b == ren[2 * r])
+                            b = ren[2 * r + 1];
+                    }
+                    if (a == b)
+                        continue;
+                    pairs[2 * np] = a < b ? a : b;
+                    pairs[2 * np + 1] = a < b ? b : a;
+                    ++np;
+                }
+            }
+            if (!grew && !merged)
+                break;
+        }
+        out_rounds[s] = rounds;
+        for (int32_t j = 0; j < ns; ++j) {
+            const int64_t r = (int64_t)j * S + s;
+            int32_t to = j;
+            while (!m.alive[to])
+                to = m.into[to];
+            out_into[r] = m.alive[j] ? -1 : to;
+            out_off[r] = base;
+            for (int q = 0; q < 4; ++q)
+                out_ctr[4 * r + q] = acc[4 * j + q];
+            if (m.alive[j]) {
+                out_cnt[r] = m.msz[j];
+                out_K[r] = K[j];
+                out_V[r] = V[j];
+                out_f[r] = K[j] == 0 ? 0.0 : (double)K[j] / pow((double)V[j], alpha);
+                if (base + m.msz[j] <= members_cap)
+                    memcpy(out_members + base, m.mem[j], sizeof(int32_t) * (size_t)m.msz[j]);
+                else
+                    status = -1;
+                base += m.msz[j];
+            } else {
+                out_cnt[r] = 0;
+                out_K[r] = 0;
+                out_V[r] = 0;
+                out_f[r] = 0.0;
+            }
+        }
+    }
+    *needed = base;
+done:
+    if (m.mem)
+        for (int32_t j = 0; j < ns; ++j)
+            free(m.mem[j]);
+    free(m.mem);
+    free(m.msz);
+    free(m.mcap);
+    free(m.alive);
+    free(m.into);
+    free(m.node_ptr);
+    free(m.node_list);
+    free(m.cnt);
+    free(m.touched);
+    free(K);
+    free(V);
+    free(acc);
+    free(need);
+    free(flag);
+    free(changed);
+    free(pairs);
+    free(tmp);
+    free(used);
+    free(ren);
+    return status;
+}

@@ -31,12 +31,19 @@ MUTANTS = {
                                    "cand[u] = (g->row_ptr[u + 1] - g->row_ptr[u]) >= 1;"),
     "seed_rule2_one_hop": ("            if (rule == 2)\n                for (int64_t q",
                            "            if (rule == 3)\n                for (int64_t q"),
+    "merge_survivor_higher_id": ("                        m.alive[b] = 0;\n                        m.into[b] = a;\n                        need[a] = 1;",
+                                 "                        m.alive[b] = 0;\n                        m.into[b] = a;\n                        need[a] = 1;\n                        { int32_t *t_ = m.mem[a]; m.mem[a] = m.mem[b]; m.mem[b] = t_; }"),
+    "merge_threshold_uses_larger": ("const int64_t small = m->msz[c] < m->msz[i] ? m->msz[c] : m->msz[i];",
+                                    "const int64_t small = m->msz[c] > m->msz[i] ? m->msz[c] : m->msz[i];"),
     "rank_uses_d_out": ("lcdo_push(g, lcdo_rank(g->d[u], g->k[u], alpha), u, g->ver[u]);",
                         "lcdo_push(g, lcdo_rank(g->d[u], g->k[u] - g->d[u] + 1, alpha), u, g->ver[u]);"),
 }
 
 PINS = ["tests/test_oracle_bruteforce.py", "tests/test_oracle_replay.py",
-        "tests/test_oracle_limits.py", "tests/test_oracle_audit.py", "tests/test_oracle_seeds.py"]
+        "tests/test_oracle_limits.py", "tests/test_oracle_audit.py"]
+# mutants of the seed selection and of the merge phase are run against the
+# pins of that part only
+PINS_OF = {"seed_": ["tests/test_oracle_seeds.py"], "merge_": ["tests/test_oracle_merge.py"]}
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
@@ -53,6 +60,7 @@ def test_pins_catch_mutant(tmp_path, name):
     # a mutant that makes the growth loop run away is caught by the per-test
     # time limit (the thread method also stops a hang inside the C code)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        "--timeout", "20", "--timeout-method", "thread", *PINS],
+                        "--timeout", "20", "--timeout-method", "thread",
+                        *next((v for k, v in PINS_OF.items() if name.startswith(k)), PINS)],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
     assert r.returncode != 0, "mutant %s survived the pins:\n%s" % (name, r.stdout[-2000:])
