@@ -253,6 +253,40 @@ lcd_status lcd_sweep_batch(const lcd_graph *g, const double *scales, int32_t n_s
                            int32_t n_sets, int32_t mem_kind, const lcd_params *params, void *stream,
                            lcd_result **out);
 
+/*
+ * The multi-scale loop with its check-and-merge phase (Sec. 3, Algorithm 2
+ * with the overlap pre-test of Algorithm 3).  At each scale, rounds until a
+ * round neither grows nor merges:
+ *   - a live community that shares, counted over its members in ascending
+ *     order, at least eta * min(|c|, |i|) nodes with another live
+ *     community i (eta = eta_num / eta_den; the paper's 0.5 is 1 / 2) is
+ *     not grown in that round;
+ *   - every other community that needs it grows to its fixpoint at the
+ *     scale (all at the start of a scale, later only merged ones);
+ *   - each pre-tested or changed community with such a partner forms the
+ *     pair (lower id, higher id); the pairs, ascending, merge in passes of
+ *     pairwise disjoint pairs into their lower ids (union of members; the
+ *     higher id dies and is renamed in the remaining pairs).
+ * The result is read like lcd_sweep's; a community that died reports no
+ * members and K = V = 0 from that scale on, and lcd_result_merged_into()
+ * names the live id it went into.  Seeds, scales, params as in lcd_sweep
+ * (mode and use_graph ignored); every seed set must be non-empty.  Blocking.
+ * The result is freed with lcd_result_free() and cannot be rerun.
+ * Errors: LCD_EINVAL for a null graph or out, eta_num or eta_den < 1, scales
+ * not finite, outside [0, 1000] or not strictly decreasing, an empty seed
+ * set, a seed out of range or repeated within its set; LCD_ENOMEM when device
+ * memory runs out; LCD_EDEVICE for a failed launch or copy, or a scale that
+ * has not settled after 100,000 rounds.
+ */
+lcd_status lcd_sweep_merge(const lcd_graph *g, const double *scales, int32_t n_scales, const int32_t *seed_ptr,
+                           const int32_t *seed_nodes, int32_t n_sets, int32_t eta_num, int32_t eta_den,
+                           int32_t mem_kind, const lcd_params *params, void *stream, lcd_result **out);
+
+/* For each seed set at one scale: -1 if its community is live, else the live
+ * id it was merged into (host memory, int32[n_sets]).  All -1 for results of
+ * lcd_sweep. */
+lcd_status lcd_result_merged_into(const lcd_result *r, int32_t scale_idx, int32_t *into);
+
 /* Sweep shape and the total number of members listed at one scale. */
 lcd_status lcd_result_shape(const lcd_result *r, int32_t *n_sets, int32_t *n_scales);
 lcd_status lcd_result_sizes(const lcd_result *r, int32_t scale_idx, int64_t *total_members);
@@ -305,7 +339,8 @@ lcd_status lcd_result_stats(const lcd_result *r, lcd_sweep_stats *out);
  * device) into the same result, overwriting it; with use_graph the captured
  * hipGraph is replayed (captured again if the member pool or the graph's
  * spill tables were reallocated since).  Sweeps of one graph must not run
- * concurrently: they share its spill-tier tables.  Blocking.
+ * concurrently: they share its spill-tier tables.  Blocking.  LCD_EINVAL for
+ * a result of lcd_sweep_merge().
  */
 lcd_status lcd_result_rerun(lcd_result *r, void *stream);
 

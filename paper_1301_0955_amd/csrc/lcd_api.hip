@@ -3,9 +3,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <iterator>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -229,6 +231,7 @@ struct lcd_result {
     int32_t *work[kMaxTiers - 1] = {nullptr, nullptr, nullptr};
     std::vector<double> scales_h;
     lcd_sweep_stats stats{};
+    int32_t *into = nullptr;          // merge mode: per record, -1 live or the live id merged into
     // use_graph: the captured launch sequence and the buffers it refers to
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -462,6 +465,7 @@ void result_release(lcd_result *r) {
     dev_free(r->scales);
     dev_free(r->seed_ptr);
     dev_free(r->seed_nodes);
+    dev_free(r->into);
     dev_free(r->rec.off);
     dev_free(r->rec.cnt);
     dev_free(r->rec.K);
@@ -973,6 +977,400 @@ lcd_status lcd_sweep_batch(const lcd_graph *g, const double *scales, int32_t n_s
     return lcd_sweep(g, sc.data(), n_scales, sp.data(), sn.data(), n_sets, LCD_MEM_HOST, params, stream, out);
 }
 
+// ---------------------------------------------------------------------------
+// Multi-scale loop with the check-and-merge phase (Sec. 3, Algorithm 2 with
+// the overlap pre-test of Algorithm 3).  Per scale, rounds until a round
+// neither grows nor merges: memberships of the live communities (device
+// readout kernels); overlap partner of every live community (device,
+// partner_kernel) -> those with a partner skip growth; the others that need
+// it grow to their fixpoint at the scale (the sweep kernels, one scale, from
+// their member lists); memberships again and the partners of the pre-tested
+// or changed communities -> pairs; the pairs merge into their lower ids in
+// passes of pairwise disjoint pairs.  The bookkeeping between launches
+// (member lists, unions of merged pairs, pair passes) is host code.
+// ---------------------------------------------------------------------------
+lcd_status lcd_sweep_merge(const lcd_graph *g, const double *scales, int32_t n_scales, const int32_t *seed_ptr,
+                           const int32_t *seed_nodes, int32_t n_sets, int32_t eta_num, int32_t eta_den,
+                           int32_t mem_kind, const lcd_params *params, void *stream, lcd_result **out) {
+    if (!out)
+        return fail(LCD_EINVAL, "out is null");
+    *out = nullptr;
+    if (!g)
+        return fail(LCD_EINVAL, "null graph");
+    if (n_scales < 1 || n_sets < 0)
+        return fail(LCD_EINVAL, "n_scales must be >= 1 and n_sets >= 0");
+    if (eta_num < 1 || eta_den < 1)
+        return fail(LCD_EINVAL, "eta_num and eta_den must be positive");
+    if (mem_kind != LCD_MEM_HOST && mem_kind != LCD_MEM_DEVICE)
+        return fail(LCD_EINVAL, "unknown mem_kind %d", mem_kind);
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t n = g->n, ns = n_sets, S = n_scales;
+    std::vector<double> sc;
+    std::vector<int32_t> sp, sn;
+    CHK(fetch(sc, scales, (size_t)S, mem_kind, st));
+    for (int32_t s = 0; s < S; ++s) {
+        if (!std::isfinite(sc[s]) || sc[s] < 0.0 || sc[s] > 1000.0)
+            return fail(LCD_EINVAL, "scale %d must be finite and in [0, 1000]", s);
+        if (s > 0 && !(sc[s] < sc[s - 1]))
+            return fail(LCD_EINVAL, "scales must be strictly decreasing (finest first)");
+    }
+    CHK(fetch(sp, seed_ptr, (size_t)ns + 1, mem_kind, st));
+    if (sp[0] != 0)
+        return fail(LCD_EINVAL, "seed_ptr[0] must be 0");
+    for (int32_t j = 0; j < ns; ++j)
+        if (sp[j + 1] <= sp[j])
+            return fail(LCD_EINVAL, "seed set %d is empty or seed_ptr decreases", j);
+    CHK(fetch(sn, seed_nodes, (size_t)sp[ns], mem_kind, st));
+    lcd_params prm;
+    lcd_params_default(&prm);
+    if (params)
+        prm = *params;
+    prm.mode = LCD_PERSISTENT;
+    prm.use_graph = 0;
+    // state of every community (host)
+    std::vector<std::vector<int32_t>> lists((size_t)ns);
+    {
+        std::vector<int32_t> stamp((size_t)std::max(n, 1), -1);
+        for (int32_t j = 0; j < ns; ++j) {
+            for (int32_t q = sp[j]; q < sp[j + 1]; ++q) {
+                const int32_t u = sn[q];
+                if (u < 0 || u >= n)
+                    return fail(LCD_EINVAL, "seed node %d of set %d out of range", u, j);
+                if (stamp[u] == j)
+                    return fail(LCD_EINVAL, "seed node %d repeated in set %d", u, j);
+                stamp[u] = j;
+            }
+            lists[j].assign(sn.begin() + sp[j], sn.begin() + sp[j + 1]);
+            std::sort(lists[j].begin(), lists[j].end());
+        }
+    }
+    std::vector<uint8_t> alive((size_t)ns, 1), need((size_t)ns), flag((size_t)ns), changed((size_t)ns);
+    std::vector<int32_t> into((size_t)ns, -1);
+    std::vector<int64_t> K((size_t)ns, 0), V((size_t)ns, 0);
+    std::vector<uint64_t> acc((size_t)ns * 4);
+    const size_t R = (size_t)ns * S;
+    std::vector<int64_t> h_off(R), h_K(R), h_V(R);
+    std::vector<int32_t> h_cnt(R), h_into(R);
+    std::vector<double> h_f(R);
+    std::vector<uint64_t> h_ctr(4 * R);
+    std::vector<int32_t> pool;
+    // device scratch
+    const int nbk = (int)(((int64_t)n + 1 + 1023) / 1024) + 1;
+    int32_t *d_ptr = nullptr, *d_mem = nullptr, *d_node_ptr = nullptr, *d_node_sets = nullptr, *d_cnt = nullptr,
+            *d_bs = nullptr, *d_list = nullptr, *d_partner = nullptr, *d_cnt_all = nullptr;
+    unsigned *d_next = nullptr;
+    int64_t mem_cap = 0;
+    const int32_t slots = (int32_t)std::max<int64_t>(
+        1, std::min<int64_t>(4 * (int64_t)g->dev.cus, ((int64_t)1 << 30) / (4 * (int64_t)std::max(ns, 1))));
+    auto release = [&]() {
+        dev_free(d_ptr);
+        dev_free(d_mem);
+        dev_free(d_node_ptr);
+        dev_free(d_node_sets);
+        dev_free(d_cnt);
+        dev_free(d_bs);
+        dev_free(d_list);
+        dev_free(d_partner);
+        dev_free(d_cnt_all);
+        dev_free(d_next);
+    };
+    lcd_status status = LCD_OK;
+#define MCHK(expr)                         \
+    do {                                   \
+        lcd_status s_ = (expr);            \
+        if (s_ != LCD_OK) {                \
+            release();                     \
+            return s_;                     \
+        }                                  \
+    } while (0)
+#define MHIP(expr)                                                                             \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) {                                                                \
+            release();                                                                         \
+            return fail(LCD_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+        }                                                                                      \
+    } while (0)
+    MCHK(dev_alloc(&d_ptr, (size_t)ns + 1));
+    MCHK(dev_alloc(&d_node_ptr, (size_t)n + 1));
+    MCHK(dev_alloc(&d_cnt, (size_t)n + 1));
+    MCHK(dev_alloc(&d_bs, (size_t)nbk + 1));
+    MCHK(dev_alloc(&d_list, (size_t)std::max(ns, 1)));
+    MCHK(dev_alloc(&d_partner, (size_t)std::max(ns, 1)));
+    MCHK(dev_alloc(&d_cnt_all, (size_t)slots * (size_t)std::max(ns, 1)));
+    MCHK(dev_alloc(&d_next, 1));
+    MHIP(launch_zero_bytes(d_cnt_all, 4 * (int64_t)slots * std::max(ns, 1), st));
+    std::vector<int32_t> h_ptr((size_t)ns + 1), h_list, h_partner;
+    std::vector<int32_t> flat;
+    // upload the live member lists and build the memberships node -> ids
+    auto memberships = [&]() -> lcd_status {
+        h_ptr[0] = 0;
+        for (int32_t j = 0; j < ns; ++j)
+            h_ptr[j + 1] = h_ptr[j] + (alive[j] ? (int32_t)lists[j].size() : 0);
+        const int64_t total = h_ptr[ns];
+        flat.resize((size_t)std::max<int64_t>(total, 1));
+        for (int32_t j = 0; j < ns; ++j)
+            if (alive[j])
+                std::copy(lists[j].begin(), lists[j].end(), flat.begin() + h_ptr[j]);
+        if (total > mem_cap) {
+            dev_free(d_mem);
+            dev_free(d_node_sets);
+            mem_cap = std::max<int64_t>(total, 2 * mem_cap);
+            CHK(dev_alloc(&d_mem, (size_t)mem_cap));
+            CHK(dev_alloc(&d_node_sets, (size_t)mem_cap));
+        }
+        HIPCHK(hipMemcpyAsync(d_ptr, h_ptr.data(), sizeof(int32_t) * ((size_t)ns + 1), hipMemcpyHostToDevice, st));
+        if (total)
+            HIPCHK(hipMemcpyAsync(d_mem, flat.data(), sizeof(int32_t) * (size_t)total, hipMemcpyHostToDevice, st));
+        HIPCHK(launch_overlap(d_ptr, d_mem, total, ns, n, d_node_ptr, d_node_sets, d_cnt, d_bs, st));
+        return LCD_OK;
+    };
+    // partners of the listed communities (host ids in h_list)
+    auto partners = [&]() -> lcd_status {
+        h_partner.assign(h_list.size(), -1);
+        if (h_list.empty()) {
+            // the host lists are rewritten next: the uploads must have landed
+            HIPCHK(hipStreamSynchronize(st));
+            return LCD_OK;
+        }
+        HIPCHK(hipMemcpyAsync(d_list, h_list.data(), sizeof(int32_t) * h_list.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(launch_partner(d_ptr, d_mem, d_node_ptr, d_node_sets, d_list, (int32_t)h_list.size(), ns, eta_num,
+                              eta_den, d_cnt_all, slots, d_next, d_partner, st));
+        HIPCHK(hipMemcpyAsync(h_partner.data(), d_partner, sizeof(int32_t) * h_list.size(), hipMemcpyDeviceToHost,
+                              st));
+        HIPCHK(hipStreamSynchronize(st));
+        return LCD_OK;
+    };
+    const bool trace = std::getenv("LCD_TRACE") != nullptr;
+    for (int32_t s = 0; s < S && status == LCD_OK; ++s) {
+        const double alpha = sc[s];
+        std::fill(acc.begin(), acc.end(), 0);
+        for (int32_t j = 0; j < ns; ++j)
+            need[j] = alive[j];
+        for (int64_t round = 0;; ++round) {
+            if (round > 100000) {
+                release();
+                return fail(LCD_EDEVICE, "scale %d did not settle", s);
+            }
+            // pre-test
+            MCHK(memberships());
+            h_list.clear();
+            for (int32_t j = 0; j < ns; ++j)
+                if (alive[j])
+                    h_list.push_back(j);
+            MCHK(partners());
+            std::fill(flag.begin(), flag.end(), 0);
+            for (size_t t = 0; t < h_list.size(); ++t)
+                flag[h_list[t]] = h_partner[t] >= 0;
+            // growth of the others that need it
+            std::vector<int32_t> grow_ids;
+            for (int32_t j = 0; j < ns; ++j) {
+                changed[j] = 0;
+                if (alive[j] && need[j] && !flag[j])
+                    grow_ids.push_back(j);
+            }
+            bool grew = false;
+            if (!grow_ids.empty()) {
+                std::vector<int32_t> gp(grow_ids.size() + 1, 0), gn;
+                for (size_t t = 0; t < grow_ids.size(); ++t) {
+                    const auto &L = lists[grow_ids[t]];
+                    gn.insert(gn.end(), L.begin(), L.end());
+                    gp[t + 1] = (int32_t)gn.size();
+                }
+                lcd_result *res = nullptr;
+                MCHK(lcd_sweep(g, &alpha, 1, gp.data(), gn.data(), (int32_t)grow_ids.size(), LCD_MEM_HOST, &prm,
+                               stream, &res));
+                // the round's results in bulk: one scale readout and one
+                // counter readout (a few copies, whatever the number of sets)
+                const int32_t ng = (int32_t)grow_ids.size();
+                std::vector<int32_t> rcp((size_t)ng + 1);
+                std::vector<int64_t> rk((size_t)ng), rv((size_t)ng);
+                std::vector<uint64_t> rct(4 * (size_t)ng), tot4(4);
+                int64_t needm = 0;
+                lcd_status s1 = lcd_result_sizes(res, 0, &needm);
+                std::vector<int32_t> rm((size_t)std::max<int64_t>(needm, 1));
+                if (s1 == LCD_OK)
+                    s1 = lcd_result_membership(res, 0, rcp.data(), rm.data(), rk.data(), rv.data(), nullptr,
+                                               LCD_MEM_HOST, stream);
+                if (s1 == LCD_OK)
+                    s1 = lcd_result_counters(res, tot4.data(), rct.data(), LCD_MEM_HOST, stream);
+                lcd_result_free(res);
+                MCHK(s1);
+                std::vector<int64_t> ro((size_t)ng);
+                std::vector<int32_t> rc((size_t)ng);
+                for (int32_t t = 0; t < ng; ++t) {
+                    ro[t] = rcp[t];
+                    rc[t] = rcp[t + 1] - rcp[t];
+                }
+                for (int32_t t = 0; t < ng; ++t) {
+                    const int32_t j = grow_ids[t];
+                    const int32_t *a = rm.data() + ro[t];
+                    const bool same = (size_t)rc[t] == lists[j].size() && std::equal(a, a + rc[t], lists[j].begin());
+                    if (!same) {
+                        lists[j].assign(a, a + rc[t]);
+                        changed[j] = 1;
+                        grew = true;
+                    }
+                    K[j] = rk[t];
+                    V[j] = rv[t];
+                    for (int q = 0; q < 4; ++q)
+                        acc[4 * j + q] += rct[4 * t + q];
+                    need[j] = 0;
+                }
+            }
+            // check
+            MCHK(memberships());
+            h_list.clear();
+            for (int32_t j = 0; j < ns; ++j)
+                if (alive[j] && (flag[j] || changed[j]))
+                    h_list.push_back(j);
+            MCHK(partners());
+            std::vector<std::pair<int32_t, int32_t>> pairs;
+            for (size_t t = 0; t < h_list.size(); ++t)
+                if (h_partner[t] >= 0)
+                    pairs.emplace_back(std::min(h_list[t], h_partner[t]), std::max(h_list[t], h_partner[t]));
+            const bool merged = !pairs.empty();
+            // merge passes of pairwise disjoint pairs, in ascending order
+            std::vector<uint8_t> used((size_t)ns, 0);
+            while (!pairs.empty()) {
+                std::sort(pairs.begin(), pairs.end());
+                pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+                std::vector<std::pair<int32_t, int32_t>> rest, ren;
+                for (auto &p : pairs)
+                    used[p.first] = used[p.second] = 0;
+                for (auto &p : pairs) {
+                    const int32_t a = p.first, b = p.second;
+                    if (!used[a] && !used[b]) {
+                        used[a] = used[b] = 1;
+                        std::vector<int32_t> u;
+                        u.reserve(lists[a].size() + lists[b].size());
+                        std::set_union(lists[a].begin(), lists[a].end(), lists[b].begin(), lists[b].end(),
+                                       std::back_inserter(u));
+                        lists[a].swap(u);
+                        lists[b].clear();
+                        alive[b] = 0;
+                        into[b] = a;
+                        need[a] = 1;
+                        ren.emplace_back(b, a);
+                    } else {
+                        rest.push_back(p);
+                    }
+                }
+                pairs.clear();
+                for (auto p : rest) {
+                    for (auto &r : ren) {
+                        if (p.first == r.first)
+                            p.first = r.second;
+                        if (p.second == r.first)
+                            p.second = r.second;
+                    }
+                    if (p.first != p.second)
+                        pairs.emplace_back(std::min(p.first, p.second), std::max(p.first, p.second));
+                }
+            }
+            if (trace) {
+                int32_t nl = 0, nf = 0;
+                for (int32_t j = 0; j < ns; ++j) {
+                    nl += alive[j];
+                    nf += alive[j] && flag[j];
+                }
+                std::fprintf(stderr, "[lcd merge] scale %d round %lld: live %d, pre-tested %d, grown %zu%s, %s\n",
+                             s, (long long)round, nl, nf, grow_ids.size(), grew ? " (changed)" : "",
+                             merged ? "merged" : "no merge");
+            }
+            if (!grew && !merged)
+                break;
+        }
+        for (int32_t j = 0; j < ns; ++j) {
+            const size_t r = (size_t)j * S + s;
+            int32_t to = j;
+            while (!alive[to])
+                to = into[to];
+            h_into[r] = alive[j] ? -1 : to;
+            h_off[r] = (int64_t)pool.size();
+            for (int q = 0; q < 4; ++q)
+                h_ctr[4 * r + q] = acc[4 * j + q];
+            if (alive[j]) {
+                h_cnt[r] = (int32_t)lists[j].size();
+                h_K[r] = K[j];
+                h_V[r] = V[j];
+                h_f[r] = K[j] == 0 ? 0.0 : (double)K[j] / pow((double)V[j], alpha);
+                pool.insert(pool.end(), lists[j].begin(), lists[j].end());
+            } else {
+                h_cnt[r] = 0;
+                h_K[r] = h_V[r] = 0;
+                h_f[r] = 0.0;
+            }
+        }
+    }
+    release();
+#undef MCHK
+#undef MHIP
+    // the result object: records and member pool on the device
+    lcd_result *r = new (std::nothrow) lcd_result();
+    if (!r)
+        return fail(LCD_ENOMEM, "host allocation failed");
+    r->g = g;
+    r->n_sets = ns;
+    r->S = S;
+    r->prm = prm;
+    r->scales_h = sc;
+    lcd_status s2 = LCD_OK;
+    if ((s2 = dev_alloc(&r->scales, (size_t)S)) != LCD_OK || (s2 = dev_alloc(&r->rec.off, R)) != LCD_OK ||
+        (s2 = dev_alloc(&r->rec.cnt, R)) != LCD_OK || (s2 = dev_alloc(&r->rec.K, R)) != LCD_OK ||
+        (s2 = dev_alloc(&r->rec.V, R)) != LCD_OK || (s2 = dev_alloc(&r->rec.f, R)) != LCD_OK ||
+        (s2 = dev_alloc(&r->rec.ctr, 4 * R)) != LCD_OK || (s2 = dev_alloc(&r->into, R)) != LCD_OK ||
+        (s2 = dev_alloc(&r->pool, std::max<size_t>(pool.size(), 1))) != LCD_OK ||
+        (s2 = dev_alloc(&r->cursor, kCursorWords)) != LCD_OK) {
+        result_release(r);
+        return s2;
+    }
+    r->pool_cap = (int64_t)std::max<size_t>(pool.size(), 1);
+    r->err = (uint32_t *)(r->cursor + 1);
+    hipError_t e = hipMemcpy(r->scales, sc.data(), sizeof(double) * S, hipMemcpyHostToDevice);
+    if (e == hipSuccess && R)
+        e = hipMemcpy(r->rec.off, h_off.data(), sizeof(int64_t) * R, hipMemcpyHostToDevice);
+    if (e == hipSuccess && R)
+        e = hipMemcpy(r->rec.cnt, h_cnt.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice);
+    if (e == hipSuccess && R)
+        e = hipMemcpy(r->rec.K, h_K.data(), sizeof(int64_t) * R, hipMemcpyHostToDevice);
+    if (e == hipSuccess && R)
+        e = hipMemcpy(r->rec.V, h_V.data(), sizeof(int64_t) * R, hipMemcpyHostToDevice);
+    if (e == hipSuccess && R)
+        e = hipMemcpy(r->rec.f, h_f.data(), sizeof(double) * R, hipMemcpyHostToDevice);
+    if (e == hipSuccess && R)
+        e = hipMemcpy(r->rec.ctr, h_ctr.data(), sizeof(uint64_t) * 4 * R, hipMemcpyHostToDevice);
+    if (e == hipSuccess && R)
+        e = hipMemcpy(r->into, h_into.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !pool.empty())
+        e = hipMemcpy(r->pool, pool.data(), sizeof(int32_t) * pool.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        result_release(r);
+        return fail(LCD_EDEVICE, "merge result upload: %s", hipGetErrorString(e));
+    }
+    r->stats.pool_used = (int64_t)pool.size();
+    *out = r;
+    return LCD_OK;
+}
+
+lcd_status lcd_result_merged_into(const lcd_result *r, int32_t scale_idx, int32_t *into) {
+    if (!r || !into)
+        return fail(LCD_EINVAL, "null argument");
+    if (scale_idx < 0 || scale_idx >= r->S)
+        return fail(LCD_EINVAL, "scale index out of range");
+    if (!r->into) {
+        for (int32_t j = 0; j < r->n_sets; ++j)
+            into[j] = -1;
+        return LCD_OK;
+    }
+    std::vector<int32_t> all((size_t)r->n_sets * r->S);
+    if (!all.empty())
+        HIPCHK(hipMemcpy(all.data(), r->into, sizeof(int32_t) * all.size(), hipMemcpyDeviceToHost));
+    for (int32_t j = 0; j < r->n_sets; ++j)
+        into[j] = all[(size_t)j * r->S + scale_idx];
+    return LCD_OK;
+}
+
 lcd_status lcd_tune(lcd_graph *g, const double *scales, int32_t n_scales, const int32_t *seed_ptr,
                     const int32_t *seed_nodes, int32_t n_sets, int32_t mem_kind, const lcd_params *base,
                     void *stream, lcd_tune_report *report) {
@@ -1323,6 +1721,8 @@ lcd_status lcd_result_stats(const lcd_result *r, lcd_sweep_stats *out) {
 lcd_status lcd_result_rerun(lcd_result *r, void *stream) {
     if (!r)
         return fail(LCD_EINVAL, "null result");
+    if (r->into)
+        return fail(LCD_EINVAL, "a result of lcd_sweep_merge cannot be rerun");
     return run_sweep(r, (hipStream_t)stream);
 }
 

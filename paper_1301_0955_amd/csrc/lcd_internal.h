@@ -120,6 +120,12 @@ hipError_t launch_overlap(const int32_t *comm_ptr, const int32_t *members, int64
                           int32_t *cnt, int32_t *block_sums, hipStream_t st);
 hipError_t launch_counter_sum(const uint64_t *ctr, int64_t n_rec, unsigned long long *tot,
                               hipStream_t st);
+// overlap partner of each listed community (check phase); cnt_all holds
+// n_slots zeroed int32[n_comms] arrays and is left zeroed
+hipError_t launch_partner(const int32_t *comm_ptr, const int32_t *members, const int32_t *node_ptr,
+                          const int32_t *node_sets, const int32_t *list, int32_t n_list, int32_t n_comms,
+                          int32_t eta_num, int32_t eta_den, int32_t *cnt_all, int32_t n_slots, unsigned *next,
+                          int32_t *partner, hipStream_t st);
 // exclusive scan of n int32 into out[0..n); block_sums: ceil(n/1024)+1 entries,
 // the total lands in block_sums[ceil(n/1024)]
 hipError_t launch_exclusive_scan(const int32_t *in, int64_t n, int32_t *out, int32_t *block_sums,

@@ -1624,6 +1624,74 @@ __global__ void seed_scatter_kernel(const int32_t *perm, const int32_t *flag, co
             out[at[i]] = perm[i];
 }
 
+// ---------------------------------------------------------------------------
+// Overlap partner of a community (check phase of Algorithm 2, and the
+// overlap pre-test of Algorithm 3).  One wave per listed community c: walk
+// c's members in ascending order and, for each member v, the communities
+// holding v in ascending order, counting per community; the first community
+// i != c whose count x reaches x * den >= num * min(|c|, |i|) is the partner
+// (-1: none).  The order of the walk decides which partner is "first", so
+// lanes take consecutive entries of one member's list and the lowest lane
+// that reaches the threshold wins.  cnt_all: one int32[n_comms] per wave
+// slot, zero on entry and left zero.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) partner_kernel(const int32_t *comm_ptr, const int32_t *members,
+                                                      const int32_t *node_ptr, const int32_t *node_sets,
+                                                      const int32_t *list, int32_t n_list, int32_t n_comms,
+                                                      int32_t eta_num, int32_t eta_den, int32_t *cnt_all,
+                                                      int32_t n_slots, unsigned *next, int32_t *partner) {
+    const int lane = threadIdx.x & 63;
+    const int slot = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (slot >= n_slots)
+        return;
+    int32_t *cnt = cnt_all + (int64_t)slot * n_comms;
+    // item and found are held wave-uniform (scalar registers), and the loop
+    // has no lane-0-only block at its end: a lane-0 block at both ends of the
+    // loop lets the compiler thread them into a second back edge that lanes
+    // 1..63 take alone, with no exit for them while lane 0 waits outside.
+    for (;;) {
+        unsigned item = 0;
+        if (lane == 0)
+            item = atomicAdd(next, 1u);
+        item = (unsigned)__builtin_amdgcn_readfirstlane((int)item);
+        if (item >= (unsigned)n_list)
+            break;
+        const int32_t c = list[item];
+        const int32_t c0 = comm_ptr[c], c1 = comm_ptr[c + 1];
+        const int64_t sc = c1 - c0;
+        int32_t found = -1;
+        for (int32_t q = c0; q < c1 && found < 0; ++q) {
+            const int32_t v = members[q];
+            const int32_t t1 = node_ptr[v + 1];
+            for (int32_t t0 = node_ptr[v]; t0 < t1 && found < 0; t0 += 64) {
+                const int32_t t = t0 + lane;
+                const int32_t i = t < t1 ? node_sets[t] : -1;
+                bool hit = false;
+                if (i >= 0 && i != c) {
+                    const int64_t x = (int64_t)atomicAdd(&cnt[i], 1) + 1;
+                    const int64_t si = comm_ptr[i + 1] - comm_ptr[i];
+                    const int64_t small = sc < si ? sc : si;
+                    hit = x * eta_den >= (int64_t)eta_num * small;
+                }
+                const uint64_t m = __ballot(hit);
+                if (m)
+                    found = __builtin_amdgcn_readlane(i, (int)__builtin_ctzll(m));
+            }
+        }
+        // leave the counts at zero for the next community
+        for (int32_t q = c0; q < c1; ++q) {
+            const int32_t v = members[q];
+            for (int32_t t = node_ptr[v] + lane; t < node_ptr[v + 1]; t += 64) {
+                const int32_t i = node_sets[t];
+                if (i != c)
+                    atomicExch(&cnt[i], 0);
+            }
+        }
+        // every lane stores the same value (no lane-0 branch, see above)
+        partner[item] = found;
+    }
+}
+
 // three-phase exclusive scan of n counts into ptr[0..n]
 __global__ void __launch_bounds__(1024) scan_blocks_kernel(const int32_t *cnt, int64_t n,
                                                            int32_t *ptr, int32_t *block_sums) {
@@ -1942,6 +2010,20 @@ hipError_t launch_seed_collect(const int32_t *perm, const uint8_t *st, int32_t n
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(seed_scatter_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, perm, flag, at, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_partner(const int32_t *comm_ptr, const int32_t *members, const int32_t *node_ptr,
+                          const int32_t *node_sets, const int32_t *list, int32_t n_list, int32_t n_comms,
+                          int32_t eta_num, int32_t eta_den, int32_t *cnt_all, int32_t n_slots, unsigned *next,
+                          int32_t *partner, hipStream_t st) {
+    if (n_list == 0)
+        return hipSuccess;
+    hipError_t e = launch_zero_bytes(next, 4, st);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(partner_kernel, dim3((n_slots + 3) / 4), dim3(256), 0, st, comm_ptr, members, node_ptr,
+                       node_sets, list, n_list, n_comms, eta_num, eta_den, cnt_all, n_slots, next, partner);
     return hipGetLastError();
 }
 

@@ -126,6 +126,9 @@ def library() -> ctypes.CDLL:
         "lcd_graph_upload_batch": (st, [ctypes.c_int32, P, P, P, P, P, ctypes.c_int32, P,
                                         ctypes.POINTER(P)]),
         "lcd_graph_batch_info": (st, [P, ctypes.POINTER(ctypes.c_int32), P]),
+        "lcd_sweep_merge": (st, [P, P, ctypes.c_int32, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_int32, ctypes.POINTER(lcd_params), P, ctypes.POINTER(P)]),
+        "lcd_result_merged_into": (st, [P, ctypes.c_int32, P]),
         "lcd_seeds": (st, [P, ctypes.c_int32, P, ctypes.c_int32, P, P, ctypes.POINTER(ctypes.c_int32)]),
         "lcd_sweep_batch": (st, [P, P, ctypes.c_int32, P, P, P, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.POINTER(lcd_params), P, ctypes.POINTER(P)]),
@@ -472,6 +475,31 @@ def sweep_to_numpy(res: Result) -> dict:
     _, ctr = res.counters(per_record=True)
     return dict(members=members, off=offs, cnt=cnt, K=K, V=V, f=f,
                 ctr=ctr.cpu().numpy().astype(np.uint64), n_sets=ns, n_scales=S)
+
+
+def lcd_sweep_merge(graph: "Graph", scales, seed_ptr, seed_nodes, eta=(1, 2), params=None, **kw):
+    """lcd_sweep_merge: the multi-scale loop with the check-and-merge phase."""
+    lib = library()
+    prm = params if params is not None else make_params(**kw)
+    sc = np.ascontiguousarray(scales, dtype=np.float64)
+    sp = np.ascontiguousarray(seed_ptr, dtype=np.int32)
+    sn = np.ascontiguousarray(seed_nodes, dtype=np.int32)
+    h = P()
+    _check(lib.lcd_sweep_merge(graph._h, sc.ctypes.data_as(P), sc.size, sp.ctypes.data_as(P),
+                               sn.ctypes.data_as(P), sp.size - 1, int(eta[0]), int(eta[1]), LCD_MEM_HOST,
+                               ctypes.byref(prm), _stream(), ctypes.byref(h)), "lcd_sweep_merge")
+    return Result(h, graph.n)
+
+
+def merged_into(res: "Result") -> np.ndarray:
+    """into[R] in record order (set * S + s): -1 live, else the live id."""
+    S, ns = res.n_scales, res.n_sets
+    out = np.zeros((ns, S), np.int32)
+    col = np.zeros(max(ns, 1), np.int32)
+    for s in range(S):
+        _check(library().lcd_result_merged_into(res._h, s, col.ctypes.data_as(P)), "lcd_result_merged_into")
+        out[:, s] = col[:ns]
+    return out.reshape(-1)
 
 
 def lcd_seeds(graph: "Graph", perm, rule: int = 1) -> np.ndarray:
