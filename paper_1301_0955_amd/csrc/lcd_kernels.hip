@@ -1425,16 +1425,19 @@ __device__ __forceinline__ void team_global_entry(const SweepArgs &A) {
     run_team<true, PERSET>(A, t, sh);
 }
 
-// At most 128 VGPRs (four waves per SIMD): a workgroup steps through one
-// community as a chain of dependent scans, reductions and table updates, so
-// more communities in flight per CU is what hides the latency.  The few
-// values this pushes out of registers are kernel-long constants, spilled once
-// and reloaded per community or scale, not per step.
-#define LCD_TEAM_KERNEL __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
-LCD_TEAM_KERNEL sweep_team_lds_kernel(SweepArgs A) { team_lds_entry<false>(A); }
-LCD_TEAM_KERNEL sweep_team_global_kernel(SweepArgs A) { team_global_entry<false>(A); }
-LCD_TEAM_KERNEL query_team_lds_kernel(SweepArgs A) { team_lds_entry<true>(A); }
-LCD_TEAM_KERNEL query_team_global_kernel(SweepArgs A) { team_global_entry<true>(A); }
+// Register bounds: a workgroup steps through one community as a chain of
+// dependent scans, reductions and table updates, so more communities in
+// flight per CU is what hides the latency.  LDS tables of 1,024 entries
+// allow four workgroups per CU, so the LDS kernels take at most 128 VGPRs
+// (four waves per SIMD); the global-table kernels are not LDS-bound and take
+// at most 96 (five).  The values this pushes out of registers are
+// kernel-long constants, spilled once and reloaded per community or scale,
+// not per step.
+#define LCD_TEAM_KERNEL(w) __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(w)))
+LCD_TEAM_KERNEL(4) sweep_team_lds_kernel(SweepArgs A) { team_lds_entry<false>(A); }
+LCD_TEAM_KERNEL(5) sweep_team_global_kernel(SweepArgs A) { team_global_entry<false>(A); }
+LCD_TEAM_KERNEL(4) query_team_lds_kernel(SweepArgs A) { team_lds_entry<true>(A); }
+LCD_TEAM_KERNEL(5) query_team_global_kernel(SweepArgs A) { team_global_entry<true>(A); }
 #undef LCD_TEAM_KERNEL
 
 // ---------------------------------------------------------------------------
