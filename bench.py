@@ -22,6 +22,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# The query server's launch lanes are HIP streams, which HIP spreads over
+# GPU_MAX_HW_QUEUES hardware queues (4 by default); with 8 or more the server
+# runs one stage per tier on six lanes, none sharing a queue.  This has to be
+# set before the HIP runtime starts.
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0) < 12:
+    os.environ["GPU_MAX_HW_QUEUES"] = "12"
+
 METRIC = ("candidate-node gains/s + full multi-scale sweep time; "
           "p50/p99 seed-query latency")
 HBM_PEAK_GBS = 8000.0
@@ -131,6 +138,12 @@ def percentiles(x):
                 p999=round(float(p[3]), 4), mean=round(float(x.mean()), 4), max=round(float(x.max()), 4))
 
 
+# device memory the query server may hold: the global-table tiers buy as
+# many tables as it allows (a table of the whole-graph tier is 32 MiB on the
+# 1M-node graph)
+SERVE_MEM_BUDGET = 16 << 30
+
+
 def serve_bench(lcd, G, g, qps, seconds, warmup_s, oracle_sample, seed=1):
     """Open-loop Poisson stream of (seed set, alpha) queries against the
     query server; latency = completion stamp - scheduled arrival."""
@@ -138,7 +151,7 @@ def serve_bench(lcd, G, g, qps, seconds, warmup_s, oracle_sample, seed=1):
     from paper_1301_0955_amd import workloads as W
     n = int(round(qps * (warmup_s + seconds)))
     t_arr, sets, alphas = W.query_stream(g, n, qps, max_size=256, seed=seed)
-    srv = lcd.Server(G, max_slots=8192)
+    srv = lcd.Server(G, mem_budget=SERVE_MEM_BUDGET, max_slots=8192)
     for i in range(8):                      # first launches of the query kernels
         srv.result(srv.submit(sets[i], alphas[i]))
     st0 = srv.stats()
@@ -183,7 +196,16 @@ def serve_bench(lcd, G, g, qps, seconds, warmup_s, oracle_sample, seed=1):
         max_batch=st["max_batch"], max_lanes_busy=st["max_lanes_busy"], lanes=st["lanes"],
         stage_lanes=st["spill_lanes"], forwarded=st["forwarded"] - st0["forwarded"],
         later_stage_batches=st["spill_batches"] - st0["spill_batches"],
-        requeued=st["requeued"], failed=st["failed"], server_mem_bytes=st["mem_held"])
+        requeued=st["requeued"], failed=st["failed"], server_mem_bytes=st["mem_held"],
+        spill_tables=list(st["spill_tables"]))
+    # latency by the lane that answered (lane k serves stage min(k, stages - 1))
+    by_lane = {}
+    for k in sorted(set(int(res[i]["lane"]) for i in meas)):
+        sel = np.array([(res[i]["t_done_ns"] - sched[i]) * 1e-6 for i in meas if res[i]["lane"] == k])
+        by_lane[str(k)] = dict(queries=int(sel.size), share=round(sel.size / meas.size, 4),
+                               p50=round(float(np.percentile(sel, 50)), 3),
+                               p99=round(float(np.percentile(sel, 99)), 3))
+    out["latency_by_lane_ms"] = by_lane
     # the oracle on a sample of the same queries: per-query CPU latency and parity
     if oracle_sample > 0:
         o = oracle.Oracle.from_graph(g)

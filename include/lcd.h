@@ -385,8 +385,9 @@ typedef struct {
     int64_t pending;          /* waiting for an entry lane now */
     int64_t in_flight;        /* admitted and not finished now */
     int64_t mem_held;         /* device bytes the server holds */
-    int64_t forwarded;        /* queries that outgrew tier 0 and went to a spill lane */
-    int64_t spill_batches;    /* launches of spill lanes */
+    int64_t forwarded;        /* moves of a query to the next stage (it outgrew its
+                                 stage's table); one stage per tier */
+    int64_t spill_batches;    /* launches of lanes of stages after the first */
     int32_t lanes, spill_lanes, max_slots;
     int32_t max_batch;        /* largest batch launched */
     int32_t max_lanes_busy;   /* most lanes with a batch on the device at once */
@@ -398,7 +399,12 @@ typedef struct {
  * Create a server on the current device (the graph's device).
  *   mem_budget  device bytes the server may allocate (0 = 1 GiB); it must
  *               not exceed the free device memory (LCD_ENOMEM) and must
- *               cover four lanes that can each hold any single query
+ *               cover the lanes, each able to hold any single query
+ * Lanes are HIP streams; HIP spreads a process's streams over
+ * GPU_MAX_HW_QUEUES hardware queues (4 unless set before the HIP runtime
+ * starts).  With 8 or more the server runs one stage per table tier on six
+ * lanes (a query moves to the next stage's lane when it outgrows its
+ * stage's table), otherwise tier 0 on one lane and the later tiers on three.
  *   max_slots   queries admitted and unfinished at once (0 = 1024)
  *   params      k_prune, lds_capacity, waves_per_block, watchdog_ms used;
  *               NULL for defaults

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <condition_variable>
 #include <deque>
 #include <mutex>
@@ -82,7 +83,8 @@ void host_free(T *&p) {
 struct Stage {
     int first = 0, last = 0;
 };
-constexpr int kMaxStages = 2;
+constexpr int kMaxStages = kMaxTiers;
+constexpr int kMaxLanes = 8;
 
 struct Lane {
     int id = 0;
@@ -596,18 +598,35 @@ lcd_status lcd_server_create(const lcd_graph *g, int64_t mem_budget, int32_t max
         delete S;
         return s;
     }
-    // stages: tier 0, then all later tiers.  Four lanes: one for stage 0 and
-    // three for the later stage (all four for stage 0 when the plan has one
-    // tier).  Tier-0 batches take milliseconds; a later-stage batch lasts as
-    // long as its slowest query, so that stage gets the lanes and large batches.
+    // Lanes are HIP streams, and HIP spreads a process's streams over a fixed
+    // number of hardware queues (GPU_MAX_HW_QUEUES, 4 unless set before the
+    // runtime starts); lanes that share a queue run their batches in turn,
+    // so a short batch can wait behind a long one.
+    //  * >= 8 queues: one stage per tier (a batch lasts as long as its
+    //    slowest query, so a query that fits a small table never waits for
+    //    one that needs a large table) and six lanes: one per LDS tier,
+    //    three for the 16,384-entry tier (about a third of a query stream
+    //    ends there), one for the whole-graph tier.
+    //  * fewer: tier 0, then all later tiers; four lanes, one for tier 0.
+    int hw_queues = 4;
+    if (const char *e = std::getenv("GPU_MAX_HW_QUEUES"))
+        hw_queues = std::max(1, std::atoi(e));
+    const bool per_tier = hw_queues >= 8 && S->tp.n >= 2;
     S->n_stages = 0;
-    S->stages[S->n_stages++] = Stage{0, 1};
-    if (S->tp.n >= 2)
-        S->stages[S->n_stages++] = Stage{1, S->tp.n};
-    const int n_lanes = 4;
-    int lane_stage[4] = {0, 0, 0, 0};
-    if (S->n_stages == 2)
-        lane_stage[1] = lane_stage[2] = lane_stage[3] = 1;
+    if (per_tier) {
+        for (int k = 0; k < S->tp.n && k < kMaxStages; ++k)
+            S->stages[S->n_stages++] = Stage{k, k + 1};
+    } else {
+        S->stages[S->n_stages++] = Stage{0, 1};
+        if (S->tp.n >= 2)
+            S->stages[S->n_stages++] = Stage{1, S->tp.n};
+    }
+    static const int kPerTierLanes[6] = {0, 1, 2, 2, 2, 3};
+    static const int kTwoStageLanes[4] = {0, 1, 1, 1};
+    const int n_lanes = per_tier ? 6 : 4;
+    int lane_stage[kMaxLanes] = {0};
+    for (int i = 0; i < n_lanes; ++i)
+        lane_stage[i] = std::min(per_tier ? kPerTierLanes[i] : kTwoStageLanes[i], S->n_stages - 1);
     const int32_t max_q = std::max<int32_t>(1, std::min<int32_t>(1024, max_slots));
     const int64_t max_seed = std::max<int64_t>(65536, (int64_t)g->n);
     const int64_t pool_cap = std::max<int64_t>((int64_t)g->n, 1 << 22);

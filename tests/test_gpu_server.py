@@ -58,15 +58,29 @@ def test_server_mix_equals_alone_and_oracle(L, graph):
     heavy = [(W.bfs_prefix(g, r, 256), 0.5) for r in (7, 911, 4242)]
     queries = heavy + list(zip(sets, alphas))
     o = oracle.Oracle.from_graph(g)
-    for cap in (1024, 256):
-        with L.Server(G, max_slots=512, lds_capacity=cap) as srv:
+    # both lane layouts: one stage per tier on six lanes (8 or more hardware
+    # queues), and tier 0 then the rest on four lanes (fewer queues); the
+    # server reads the queue count when it is created
+    import os
+    for queues, cap in (("12", 1024), ("12", 256), ("4", 1024)):
+        old_q = os.environ.get("GPU_MAX_HW_QUEUES")
+        os.environ["GPU_MAX_HW_QUEUES"] = queues
+        try:
+            srv = L.Server(G, max_slots=512, lds_capacity=cap)
+        finally:
+            if old_q is None:
+                del os.environ["GPU_MAX_HW_QUEUES"]
+            else:
+                os.environ["GPU_MAX_HW_QUEUES"] = old_q
+        with srv:
+            assert srv.stats()["lanes"] == (6 if queues == "12" else 4)
             tickets = [srv.submit(s, a) for s, a in queries]
             mix = [srv.result(t, 120_000) for t in tickets]
             st = srv.stats()
-            _say("cap %d: %d queries, %d batches (%d on spill lanes), largest %d, lanes busy at once %d, "
-                 "forwarded %d, requeued %d" % (cap, st["completed"], st["batches"], st["spill_batches"],
-                                                st["max_batch"], st["max_lanes_busy"], st["forwarded"],
-                                                st["requeued"]))
+            _say("queues %s cap %d: %d queries, %d batches (%d after stage 0), largest %d, lanes busy at "
+                 "once %d, forwarded %d, requeued %d"
+                 % (queues, cap, st["completed"], st["batches"], st["spill_batches"], st["max_batch"],
+                    st["max_lanes_busy"], st["forwarded"], st["requeued"]))
             assert st["completed"] == len(queries) and st["failed"] == 0
             assert st["max_lanes_busy"] >= 2        # batches overlapped on the device
             assert st["forwarded"] > 0              # some queries outgrew tier 0
