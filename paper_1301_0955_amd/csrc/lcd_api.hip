@@ -746,10 +746,11 @@ lcd_status lcd_sweep(const lcd_graph *g, const double *scales, int32_t n_scales,
         return fail(LCD_EINVAL, "n_scales must be >= 1");
     if (n_sets < 0)
         return fail(LCD_EINVAL, "n_sets must be >= 0");
+    // the tiers hand a spilled set on as set * n_scales + scale (int32)
+    if ((int64_t)n_sets * n_scales >= ((int64_t)1 << 31))
+        return fail(LCD_EINVAL, "n_sets x n_scales must stay below 2^31");
     if (mem_kind != LCD_MEM_HOST && mem_kind != LCD_MEM_DEVICE)
         return fail(LCD_EINVAL, "unknown mem_kind %d", mem_kind);
-    if ((int64_t)n_sets * n_scales >= ((int64_t)1 << 40))
-        return fail(LCD_EINVAL, "too many records");
     lcd_params prm;
     lcd_params_default(&prm);
     if (params)

@@ -582,7 +582,11 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
         // another wave hit the watchdog: stop taking work
         if (__hip_atomic_load(A.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_TIMEOUT)
             break;
-        const int32_t set = A.tier == 0 ? (int32_t)item : A.work_in[item];
+        // a later tier's item is set * S + s: the set overflowed the tier
+        // before during scale s and resumes there from its scale s - 1 record
+        const uint32_t wi = A.tier == 0 ? item : (uint32_t)A.work_in[item];
+        const int32_t set = A.tier == 0 ? (int32_t)item : (int32_t)(wi / (uint32_t)A.S);
+        const int32_t s0 = A.tier == 0 ? A.s_begin : (int32_t)(wi % (uint32_t)A.S);
 
         if constexpr (!GLOBAL) {
             for (uint32_t i = lane; i <= t.hmask; i += 64)
@@ -613,8 +617,8 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
         const int32_t *init = nullptr;
         int32_t n_init = 0;
         bool bad = false;
-        if (A.resume) {
-            const int64_t r = (int64_t)set * A.S + (A.s_begin - 1);
+        if (s0 > A.s_begin || A.resume) {
+            const int64_t r = (int64_t)set * A.S + (s0 - 1);
             const int64_t off = A.rec.off[r];
             n_init = A.rec.cnt[r];
             if (off < 0 || off + n_init > A.pool_cap)
@@ -647,7 +651,9 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
         st.err = wave_or(st.err);
         int64_t last_off = -1;
         int32_t last_cnt = 0;
-        for (int32_t s = A.s_begin; s < A.s_end && !st.ovf && !bad && !st.err; ++s) {
+        int32_t s_at = s0;   // the scale being grown (where an overflow happened)
+        for (int32_t s = s0; s < A.s_end && !st.ovf && !bad && !st.err; ++s) {
+            s_at = s;
             if constexpr (PERSET)
                 st.alpha = A.alpha_set[set];
             else
@@ -677,7 +683,7 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
             const int64_t r = (int64_t)set * A.S + s;
             const uint64_t G = wave_sum((uint64_t)st.Gl) + st.Gu;
             const uint64_t R = wave_sum((uint64_t)st.Rl);
-            if (s == A.s_begin || moved > 0) {
+            if (s == s0 || moved > 0) {
                 // members, sorted, into the pool
                 int32_t m = 0;
                 for (int32_t base = 0; base < st.count; base += 64) {
@@ -717,7 +723,7 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
         if (st.ovf && lane == 0) {
             if (A.work_out) {
                 const uint32_t pos = atomicAdd(&A.ctl->ovf_count[A.tier], 1u);
-                A.work_out[pos] = set;
+                A.work_out[pos] = set * A.S + s_at;
             } else {
                 atomicOr(A.err, ERR_CAPACITY);
             }
@@ -1237,7 +1243,10 @@ __device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh) {
         const uint32_t item = sh.item;
         if (item >= n_items || sh.abort)
             break;
-        const int32_t set = A.tier == 0 ? (int32_t)item : A.work_in[item];
+        // a later tier's item is set * S + s (see run_wave)
+        const uint32_t wi = A.tier == 0 ? item : (uint32_t)A.work_in[item];
+        const int32_t set = A.tier == 0 ? (int32_t)item : (int32_t)(wi / (uint32_t)A.S);
+        const int32_t s0 = A.tier == 0 ? A.s_begin : (int32_t)(wi % (uint32_t)A.S);
 
         St st;
         st.count = 0;
@@ -1261,8 +1270,8 @@ __device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh) {
         const int32_t *init = nullptr;
         int32_t n_init = 0;
         bool bad = false;
-        if (A.resume) {
-            const int64_t r = (int64_t)set * A.S + (A.s_begin - 1);
+        if (s0 > A.s_begin || A.resume) {
+            const int64_t r = (int64_t)set * A.S + (s0 - 1);
             const int64_t off = A.rec.off[r];
             n_init = A.rec.cnt[r];
             if (off < 0 || off + n_init > A.pool_cap)
@@ -1301,7 +1310,9 @@ __device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh) {
 
         int64_t last_off = -1;
         int32_t last_cnt = 0;
-        for (int32_t s = A.s_begin; s < A.s_end && !st.ovf && !bad && !st.err; ++s) {
+        int32_t s_at = s0;   // the scale being grown (where an overflow happened)
+        for (int32_t s = s0; s < A.s_end && !st.ovf && !bad && !st.err; ++s) {
+            s_at = s;
             if constexpr (PERSET)
                 st.alpha = A.alpha_set[set];
             else
@@ -1331,7 +1342,7 @@ __device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh) {
             const int64_t r = (int64_t)set * A.S + s;
             const uint64_t G = team_sum(sh, id, (uint64_t)st.Gl) + st.Gu;
             const uint64_t R = team_sum(sh, id, (uint64_t)st.Rl);
-            if (s == A.s_begin || moved > 0) {
+            if (s == s0 || moved > 0) {
                 if (id.tid == 0)
                     sh.m = 0;
                 __syncthreads();
@@ -1374,7 +1385,7 @@ __device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh) {
             if (st.ovf) {
                 if (A.work_out) {
                     const uint32_t pos = atomicAdd(&A.ctl->ovf_count[A.tier], 1u);
-                    A.work_out[pos] = set;
+                    A.work_out[pos] = set * A.S + s_at;
                 } else {
                     atomicOr(A.err, ERR_CAPACITY);
                 }
