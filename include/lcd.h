@@ -185,7 +185,8 @@ lcd_status lcd_graph_free(lcd_graph *g);
  *               (finest first: large alpha = small communities)
  *   seed_ptr    int32[n_sets+1] offsets into seed_nodes; set j is
  *               seed_nodes[seed_ptr[j] .. seed_ptr[j+1]) (non-empty, ids in
- *               range, no repeats inside a set).  n_sets may be 0.
+ *               range, no repeats inside a set).  n_sets may be 0;
+ *               n_sets x n_scales must stay below 2^31.
  *   params      NULL for defaults
  * The result holds, for each record r = j * n_scales + s: the sorted member
  * list, K = k_in, V = k_in + k_out, f = K / pow(V, alpha_s) and the work
