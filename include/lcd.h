@@ -218,7 +218,8 @@ typedef struct {
  * lcd_server_create() calls whose params leave every sizing field at 0 use
  * it.  k_prune and watchdog_ms come from base (NULL = defaults).  Results
  * of a sweep never depend on the sizing; only the time does.  Blocking;
- * runs about 2 x 10 sample sweeps.
+ * runs 2 x 14 sample sweeps, then the three fastest sizings once on every
+ * set when that full sweep is expected to take under 5 s.
  */
 lcd_status lcd_tune(lcd_graph *g, const double *scales, int32_t n_scales, const int32_t *seed_ptr,
                     const int32_t *seed_nodes, int32_t n_sets, int32_t mem_kind, const lcd_params *base,

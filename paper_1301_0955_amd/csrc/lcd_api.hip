@@ -1407,7 +1407,8 @@ lcd_status lcd_tune(lcd_graph *g, const double *scales, int32_t n_scales, const 
     // candidate sizings: {tier-0 table, spill mode, workgroup LDS table, waves per community}
     static const int32_t cand[][4] = {
         {256, 0, 1024, 2}, {256, 0, 1024, 4}, {512, 0, 1024, 2}, {512, 0, 1024, 4},
-        {512, 0, 2048, 4}, {1024, 0, 2048, 4}, {256, 2, 0, 8}, {512, 2, 0, 8},
+        {512, 0, 2048, 4}, {1024, 0, 2048, 4}, {256, 0, 768, 2},  {256, 0, 768, 4},
+        {512, 0, 768, 2},  {512, 0, 768, 4},  {256, 2, 0, 8},     {512, 2, 0, 8},
         {512, 1, 0, 0},    {1024, 1, 0, 0},
     };
     const int nc = (int)(sizeof(cand) / sizeof(cand[0]));
@@ -1444,7 +1445,7 @@ lcd_status lcd_tune(lcd_graph *g, const double *scales, int32_t n_scales, const 
     }
     // a sampled timing can rank close candidates differently from the full
     // sweep: when the full sweep is short, re-time the leaders on every set
-    if (stride > 1 && rep.ms[bestc] * stride < 1500.0) {
+    if (stride > 1 && rep.ms[bestc] * stride < 5000.0) {
         std::vector<int> order(rep.n_tried);
         for (int i = 0; i < rep.n_tried; ++i)
             order[i] = i;
