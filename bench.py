@@ -227,6 +227,60 @@ def serve_bench(lcd, G, g, qps, seconds, warmup_s, oracle_sample, seed=1):
     return out
 
 
+def merge_bench(lcd, G, g, sp, sn, sc, with_oracle):
+    """The multi-scale loop with the check-and-merge phase (lcd_sweep_merge):
+    on a 20k-node weighted hierarchy beside the oracle (every record and
+    merged-into id compared), and on the main workload (device only)."""
+    import oracle
+    from paper_1301_0955_amd import workloads as W
+    gm = W.lfr_hierarchical(20_000, 2.5, 15.0, 100, 1.5, 20, 200, mu=0.25, levels=3, weighted=True,
+                            wmax=16, seed=5)
+    msp, msn = W.seed_rule1(gm, 5)
+    msc = W.log_scales(16)
+    GM = lcd.Graph.from_workload(gm)
+    walls = []
+    for _ in range(2):
+        t0 = time.perf_counter()
+        r = lcd.lcd_sweep_merge(GM, msc, msp, msn)
+        walls.append(time.perf_counter() - t0)
+        got = lcd.sweep_to_numpy(r)
+        into = lcd.merged_into(r)
+        r.free()
+    S = msc.size
+    small = dict(workload="20,000-node 3-level weighted LFR-style graph (mean degree 15, max 100, mixing "
+                          "0.25, weights 1..16), rule-1 seeds (%d), 16 scales, eta 1/2" % (msp.size - 1),
+                 seconds_gpu=round(min(walls), 4),
+                 live_finest=int((into[0::S] == -1).sum()), live_coarsest=int((into[S - 1::S] == -1).sum()))
+    if with_oracle:
+        t0 = time.perf_counter()
+        ref = oracle.Oracle.from_graph(gm).run_merge(msp, msn, msc)
+        small["seconds_oracle_1core"] = round(time.perf_counter() - t0, 4)
+        small["rounds"] = int(ref["rounds"].sum())
+        same = np.array_equal(into, ref["into"]) and np.array_equal(got["cnt"], ref["cnt"])
+        same = same and np.array_equal(got["K"], ref["K"]) and np.array_equal(got["V"], ref["V"])
+        same = same and np.array_equal(got["ctr"], np.asarray(ref["ctr"], np.uint64))
+        if same:   # member lists record by record (the two lay records out differently)
+            for rr in range(int(ref["cnt"].size)):
+                c = int(ref["cnt"][rr])
+                a, b = int(got["off"][rr]), int(ref["off"][rr])
+                if c and not np.array_equal(got["members"][a:a + c], ref["members"][b:b + c]):
+                    same = False
+                    break
+        small["identical"] = bool(same)
+    GM.free()
+    t0 = time.perf_counter()
+    r = lcd.lcd_sweep_merge(G, sc, sp, sn)
+    wall = time.perf_counter() - t0
+    into = lcd.merged_into(r)
+    r.free()
+    S = sc.size
+    main = dict(seconds_gpu=round(wall, 4), live_finest=int((into[0::S] == -1).sum()),
+                live_coarsest=int((into[S - 1::S] == -1).sum()))
+    log("merge: lfr-20k %.3f s (oracle %s s), main workload %.3f s"
+        % (small["seconds_gpu"], small.get("seconds_oracle_1core"), main["seconds_gpu"]))
+    return dict(lfr_20k=small, main_workload=main)
+
+
 def sweep_compare(lcd, G, g, sp, sn, sc, steps, prm):
     """Persistent all-scales launch vs the per-scale launch loop on one
     workload (device time of each, identical results required)."""
@@ -288,6 +342,7 @@ def main():
                          "size, to scale HBM byte counters) and exit")
     ap.add_argument("--no-large", action="store_true", help="skip the 1M-node sweep comparison")
     ap.add_argument("--no-serve", action="store_true", help="skip the query-serving run")
+    ap.add_argument("--no-merge", action="store_true", help="skip the check-and-merge runs")
     ap.add_argument("--multigraph", action="store_true",
                     help="also sweep 64 independent graphs (1k-200k nodes) in one batched launch")
     ap.add_argument("--serve-qps", type=float, default=2000.0)
@@ -440,6 +495,8 @@ def main():
         seeds_info["rule%d" % rule] = entry
     log("seed selection: %s" % seeds_info)
 
+    merge = None if args.no_merge else merge_bench(lcd, G, g, sp, sn, sc, not args.no_cpu_baseline)
+
     large = serving = None
     if not (args.no_large and args.no_serve) and args.workload != "large":
         t0 = time.perf_counter()
@@ -521,6 +578,7 @@ def main():
         "per_scale_loop": loop,
         "cpu_baseline": cpu,
         "seed_selection": seeds_info,
+        "merge": merge,
         "large_sweep": large,
         "serving": serving,
         "multigraph": multi,
