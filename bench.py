@@ -124,6 +124,29 @@ def profiled_traffic(kernel: str, tier_caps, workload_name: str):
     return json.loads(m_tr.group(1)).get(kernel)
 
 
+def profiled_utilisation(kernel: str, workload_name: str):
+    """VALU-issue and FP64 fractions of `kernel` from the committed counter
+    summary of this kernel source on this workload; else None."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "sweep_lfr2-100k_utilisation.md")
+    if workload_name != "medium" or not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_sha = re.search(r"kernels_sha256 ([0-9a-f]{64})", text)
+    m_u = re.search(r"^utilisation: (\{.*\})", text, re.M)
+    if not (m_sha and m_u):
+        return None
+    src = os.path.join(ROOT, "paper_1301_0955_amd", "csrc", "lcd_kernels.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m_sha.group(1):
+        return None
+    u = json.loads(m_u.group(1)).get(kernel)
+    if u is None:
+        return None
+    return dict(valu_issue_frac=u["valu_issue_frac"], fp64_frac_upper=u["fp64_frac_upper"],
+                source="profiles/sweep_lfr2-100k_utilisation.md")
+
+
 def W_seed_perm(g):
     from paper_1301_0955_amd import workloads as W
     return W.seed_permutation(g, 1)
@@ -450,6 +473,7 @@ def main():
                     unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 7), traffic=traffic,
                     traffic_GBs=None if traffic is None else round(traffic / (kms * 1e-3) / 1e9, 2),
                     algorithmic_bytes=int(kbytes), kernel_ms=round(kms, 4),
+                    secondary=profiled_utilisation(kname, args.workload),
                     tiers=[dict(kernel=KERNEL_OF_KIND[st0["tier_kind"][k]],
                                 table_entries=st0["tier_capacity"][k], ms=round(ms_tier[k], 3),
                                 sets_finished=st0["tier"][k]["sets_finished"],
