@@ -276,9 +276,10 @@ lcd_status lcd_sweep_batch(const lcd_graph *g, const double *scales, int32_t n_s
  * The result is freed with lcd_result_free() and cannot be rerun.
  * Errors: LCD_EINVAL for a null graph or out, eta_num or eta_den < 1, scales
  * not finite, outside [0, 1000] or not strictly decreasing, an empty seed
- * set, a seed out of range or repeated within its set; LCD_ENOMEM when device
- * memory runs out; LCD_EDEVICE for a failed launch or copy, or a scale that
- * has not settled after 100,000 rounds.
+ * set, a seed out of range or repeated within its set; LCD_ECAPACITY when the
+ * live communities of a round hold 2^31 members or more in all; LCD_ENOMEM
+ * when device memory runs out; LCD_EDEVICE for a failed launch or copy, or a
+ * scale that has not settled after 100,000 rounds.
  */
 lcd_status lcd_sweep_merge(const lcd_graph *g, const double *scales, int32_t n_scales, const int32_t *seed_ptr,
                            const int32_t *seed_nodes, int32_t n_sets, int32_t eta_num, int32_t eta_den,

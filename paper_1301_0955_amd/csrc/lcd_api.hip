@@ -1105,10 +1105,15 @@ lcd_status lcd_sweep_merge(const lcd_graph *g, const double *scales, int32_t n_s
     std::vector<int32_t> flat;
     // upload the live member lists and build the memberships node -> ids
     auto memberships = [&]() -> lcd_status {
+        int64_t total = 0;
+        for (int32_t j = 0; j < ns; ++j)
+            total += alive[j] ? (int64_t)lists[j].size() : 0;
+        if (total > INT32_MAX)
+            return fail(LCD_ECAPACITY, "live communities hold %lld members in all; at most 2^31 - 1",
+                        (long long)total);
         h_ptr[0] = 0;
         for (int32_t j = 0; j < ns; ++j)
             h_ptr[j + 1] = h_ptr[j] + (alive[j] ? (int32_t)lists[j].size() : 0);
-        const int64_t total = h_ptr[ns];
         flat.resize((size_t)std::max<int64_t>(total, 1));
         for (int32_t j = 0; j < ns; ++j)
             if (alive[j])
