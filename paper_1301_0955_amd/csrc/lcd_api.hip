@@ -148,9 +148,12 @@ lcd_status plan_tiers(const DevInfo &dev, int32_t n, const lcd_params &p, TierPl
     if (c2 > have && n > have)
         add_global(TIER_TEAM_GLOBAL, c2, team_waves, resident(TIER_TEAM_GLOBAL, team_waves, 0), 0);
     if (capn > have && n > have) {
+        // the whole-graph tier gets the few largest communities, whose
+        // step-by-step chain is the tier's time: the widest workgroups
+        const int32_t wide = kTeamMaxThreads / 64;
         int64_t slots = ((int64_t)4 << 30) / slab_stride(capn);
-        add_global(TIER_TEAM_GLOBAL, capn, team_waves,
-                   (int32_t)std::max<int64_t>(4, std::min<int64_t>(resident(TIER_TEAM_GLOBAL, team_waves, 0), slots)), 1);
+        add_global(TIER_TEAM_GLOBAL, capn, wide,
+                   (int32_t)std::max<int64_t>(4, std::min<int64_t>(resident(TIER_TEAM_GLOBAL, wide, 0), slots)), 1);
     }
     return LCD_OK;
 }
