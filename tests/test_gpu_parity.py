@@ -71,11 +71,13 @@ def test_small_workload_full(L):
     _say("stats %s" % st)
 
 
-@pytest.mark.parametrize("mode", [1])
-def test_small_workload_per_scale_loop(L, mode):
+@pytest.mark.parametrize("kw", [dict(), dict(lds_capacity=64, team_capacity=128)])
+def test_small_workload_per_scale_loop(L, kw):
+    # one launch group per scale, each resuming from the records of the scale
+    # before; with small tables the spilled sets also resume in later tiers
     g, sp, sn, scales = W.workload_small()
-    got, ref, st = run_both(L, g, sp, sn, scales, mode=mode)
-    compare_results(got, ref, label="per-scale loop")
+    got, ref, st = run_both(L, g, sp, sn, scales, mode=1, **kw)
+    compare_results(got, ref, label="per-scale loop %s" % kw)
     assert st["launches"] >= scales.size
 
 
