@@ -63,6 +63,27 @@ def test_device_log_bitwise(L):
     assert diff.size == 0, (xs[diff[:5]], dev[diff[:5]], ref[diff[:5]])
 
 
+def test_device_log_bitwise_1e8(L):
+    """10^8 integers in ten chunks (uniform on [1, 2^53), log-uniform, and
+    every integer below 10^7): the device log equals the oracle's bit for
+    bit on each."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(11))
+    for c in range(10):
+        if c < 4:
+            xs = rng.integers(1, 2**53, size=10_000_000, dtype=np.int64)
+        elif c < 9:
+            xs = np.exp(rng.uniform(0, np.log(2.0**53 - 2), 10_000_000)).astype(np.int64) + 1
+        else:
+            xs = np.arange(1, 10_000_001, dtype=np.int64)
+        xs = xs[(xs >= 1) & (xs < 2**53)]
+        dev = L.lcd_log_device(torch.from_numpy(xs)).cpu().numpy()
+        ref = oracle.log(xs.astype(np.uint64))
+        diff = np.flatnonzero(dev.view(np.int64) != ref.view(np.int64))
+        assert diff.size == 0, (c, xs[diff[:5]], dev[diff[:5]], ref[diff[:5]])
+        print("log chunk %d: %d values equal" % (c, xs.size), flush=True)
+
+
 def test_small_workload_full(L):
     _say("small workload: 1000 sets x 10 scales")
     g, sp, sn, scales = W.workload_small()
