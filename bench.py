@@ -369,7 +369,7 @@ def main():
     ap.add_argument("--multigraph", action="store_true",
                     help="also sweep 64 independent graphs (1k-200k nodes) in one batched launch")
     ap.add_argument("--serve-qps", type=float, default=2000.0)
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--serve-warmup", type=float, default=2.0)
     ap.add_argument("--serve-oracle", type=int, default=300,
                     help="queries the oracle re-runs for CPU latency and parity")
