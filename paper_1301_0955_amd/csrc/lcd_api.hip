@@ -159,8 +159,10 @@ lcd_status plan_tiers(const DevInfo &dev, int32_t n, const lcd_params &p, TierPl
 }
 
 lcd_status enqueue_tiers(const SweepArgs &a0, const TierPlan &tp, int first, int last, int32_t blocks0,
-                         Slab *slabs, int32_t *const *work, hipStream_t st, hipEvent_t *ev,
-                         int32_t *launches) {
+                         Slab *slabs, int32_t *const *work, int32_t *const *ordered, hipStream_t st,
+                         hipEvent_t *ev, int32_t *launches) {
+    // ordering pays only when a launch spans several scales
+    const bool order = ordered && a0.S >= 2 && a0.S <= 1024 && a0.s_end - a0.s_begin >= 2 && a0.n_sets > 0;
     if (first < 0 || last > tp.n || first > last)
         return fail(LCD_EINVAL, "tier range [%d, %d) outside the plan of %d tiers", first, last, tp.n);
     for (int k = first; k < last; ++k) {
@@ -172,6 +174,11 @@ lcd_status enqueue_tiers(const SweepArgs &a0, const TierPlan &tp, int first, int
         b.kind = T.kind;
         b.in_from = k > 0 ? k - 1 : 0;
         b.work_in = k > 0 ? work[k - 1] : nullptr;
+        if (k > 0 && order && ordered[k - 1]) {
+            HIPCHK(launch_order_spills(work[k - 1], &a0.ctl->ovf_count[k - 1], (uint32_t)a0.n_sets, a0.S,
+                                       ordered[k - 1], st));
+            b.work_in = ordered[k - 1];
+        }
         b.work_out = k + 1 < tp.n ? work[k] : nullptr;
         b.cap = T.cap;
         b.hbits = T.hbits;
@@ -232,6 +239,7 @@ struct lcd_result {
     unsigned long long *cursor = nullptr;
     uint32_t *err = nullptr;
     int32_t *work[kMaxTiers - 1] = {nullptr, nullptr, nullptr};
+    int32_t *ordered[kMaxTiers - 1] = {nullptr, nullptr, nullptr};   // work, by overflow scale
     std::vector<double> scales_h;
     lcd_sweep_stats stats{};
     int32_t *into = nullptr;          // merge mode: per record, -1 live or the live id merged into
@@ -276,7 +284,8 @@ lcd_status run_group(lcd_result *r, const TierPlan &tp, int32_t s_begin, int32_t
     a.err = r->err;
     a.budget_ticks = r->prm.watchdog_ms < 0 ? 0 : g->dev.wall_khz * (int64_t)r->prm.watchdog_ms;
     a.stat = r->cursor + 2;
-    return enqueue_tiers(a, tp, 0, tp.n, tp.t[0].blocks, g->slab, r->work, st, ev, &r->stats.launches);
+    return enqueue_tiers(a, tp, 0, tp.n, tp.t[0].blocks, g->slab, r->work, r->ordered, st, ev,
+                         &r->stats.launches);
 }
 
 void capture_key(const lcd_result *r, int64_t key[8]) {
@@ -479,6 +488,8 @@ void result_release(lcd_result *r) {
     dev_free(r->ctl);
     dev_free(r->cursor);
     for (auto &w : r->work)
+        dev_free(w);
+    for (auto &w : r->ordered)
         dev_free(w);
     delete r;
 }
@@ -820,7 +831,10 @@ lcd_status lcd_sweep(const lcd_graph *g, const double *scales, int32_t n_scales,
         (s = dev_alloc(&r->cursor, kCursorWords)) != LCD_OK ||
         (s = dev_alloc(&r->work[0], (size_t)std::max(n_sets, 1))) != LCD_OK ||
         (s = dev_alloc(&r->work[1], (size_t)std::max(n_sets, 1))) != LCD_OK ||
-        (s = dev_alloc(&r->work[2], (size_t)std::max(n_sets, 1))) != LCD_OK) {
+        (s = dev_alloc(&r->work[2], (size_t)std::max(n_sets, 1))) != LCD_OK ||
+        (s = dev_alloc(&r->ordered[0], (size_t)std::max(n_sets, 1))) != LCD_OK ||
+        (s = dev_alloc(&r->ordered[1], (size_t)std::max(n_sets, 1))) != LCD_OK ||
+        (s = dev_alloc(&r->ordered[2], (size_t)std::max(n_sets, 1))) != LCD_OK) {
         result_release(r);
         return s;
     }

@@ -134,11 +134,14 @@ lcd_status ensure_slab(Slab &sl, int32_t cap, int32_t slots, hipStream_t st);
 
 // Enqueue one launch group on st: tiers first .. last-1 of tp in order, tier
 // k > 0 fed by the overflow queue work[k - 1] (count in ctl->ovf_count[k-1])
-// of the tier before it; tier 0 runs with blocks0 workgroups.  ev (null, or
-// one event per tier plus one) is recorded before each tier and at the end.
+// of the tier before it; tier 0 runs with blocks0 workgroups.  With
+// `ordered` (null, or one buffer per queue) and a launch over several
+// scales, each queue is first copied into ordered[k - 1] by ascending
+// overflow scale and the tier reads that.  ev (null, or one event per tier
+// plus one) is recorded before each tier and at the end.
 lcd_status enqueue_tiers(const SweepArgs &a, const TierPlan &tp, int first, int last, int32_t blocks0,
-                         Slab *slabs, int32_t *const *work, hipStream_t st, hipEvent_t *ev,
-                         int32_t *launches);
+                         Slab *slabs, int32_t *const *work, int32_t *const *ordered, hipStream_t st,
+                         hipEvent_t *ev, int32_t *launches);
 
 }  // namespace lcd
 

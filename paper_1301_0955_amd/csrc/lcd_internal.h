@@ -128,6 +128,10 @@ hipError_t launch_partner(const int32_t *comm_ptr, const int32_t *members, const
                           int32_t *partner, hipStream_t st);
 // exclusive scan of n int32 into out[0..n); block_sums: ceil(n/1024)+1 entries,
 // the total lands in block_sums[ceil(n/1024)]
+// Reorder the overflow list in[0 .. min(*count, n_max)) of items set * S + s
+// into out by ascending s (2 <= S <= 1024).
+hipError_t launch_order_spills(const int32_t *in, const uint32_t *count, uint32_t n_max, int32_t S,
+                               int32_t *out, hipStream_t st);
 hipError_t launch_exclusive_scan(const int32_t *in, int64_t n, int32_t *out, int32_t *block_sums,
                                  hipStream_t st);
 // seed selection: pos/st setup, one selection round (adds the number of

@@ -1713,6 +1713,37 @@ __global__ void __launch_bounds__(256) partner_kernel(const int32_t *comm_ptr, c
     }
 }
 
+// Order one tier's overflow list for the next tier: items set * S + s by
+// ascending s, so that the sets with the most scales left start first (a
+// tier lasts as long as its slowest workgroup).  One workgroup; the order
+// never changes a result.
+__global__ void __launch_bounds__(1024) order_spills_kernel(const int32_t *in, const uint32_t *count,
+                                                            uint32_t n_max, int32_t S, int32_t *out) {
+    __shared__ uint32_t hist[1024];
+    const uint32_t n = min(*count, n_max);
+    const uint32_t tid = threadIdx.x;
+    for (int32_t s = (int32_t)tid; s < S; s += 1024)
+        hist[s] = 0u;
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += 1024)
+        atomicAdd(&hist[(uint32_t)in[i] % (uint32_t)S], 1u);
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int32_t s = 0; s < S; ++s) {
+            const uint32_t c = hist[s];
+            hist[s] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += 1024) {
+        const int32_t w = in[i];
+        const uint32_t pos = atomicAdd(&hist[(uint32_t)w % (uint32_t)S], 1u);
+        out[pos] = w;
+    }
+}
+
 // three-phase exclusive scan of n counts into ptr[0..n]
 __global__ void __launch_bounds__(1024) scan_blocks_kernel(const int32_t *cnt, int64_t n,
                                                            int32_t *ptr, int32_t *block_sums) {
@@ -1981,6 +2012,14 @@ hipError_t launch_overlap(const int32_t *comm_ptr, const int32_t *members, int64
         hipLaunchKernelGGL(overlap_sort_kernel, dim3((int)((waves + 3) / 4)), dim3(256), 0, st, node_ptr,
                            n, node_sets);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_order_spills(const int32_t *in, const uint32_t *count, uint32_t n_max, int32_t S,
+                               int32_t *out, hipStream_t st) {
+    if (S < 2 || S > 1024 || n_max == 0)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(order_spills_kernel, dim3(1), dim3(1024), 0, st, in, count, n_max, S, out);
     return hipGetLastError();
 }
 

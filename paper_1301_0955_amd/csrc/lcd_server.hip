@@ -256,7 +256,7 @@ lcd_status launch_lane(lcd_server *S, Lane &L) {
     const TierSpec &T0 = S->tp.t[0];
     const int32_t blocks0 = std::min<int32_t>(T0.blocks, (nq + T0.waves - 1) / T0.waves);
     int32_t launches = 0;
-    CHK(enqueue_tiers(a, S->tp, G.first, G.last, blocks0, L.slab, L.work, st, nullptr, &launches));
+    CHK(enqueue_tiers(a, S->tp, G.first, G.last, blocks0, L.slab, L.work, nullptr, st, nullptr, &launches));
     HIPCHK(hipMemcpyAsync(L.h_off, L.rec.off, sizeof(int64_t) * nq, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(L.h_cnt, L.rec.cnt, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(L.h_K, L.rec.K, sizeof(int64_t) * nq, hipMemcpyDeviceToHost, st));
