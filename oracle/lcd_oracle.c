@@ -461,11 +461,31 @@ static void lcdo_reset(lcdo_ctx *g)
  * out_K, out_V      K and V per scale; out_f the reported f (R7)
  * out_ctr           per scale: G, R, M, C (4 entries each)
  */
+static int lcdo_run_set_calls(lcdo_ctx *g, const int32_t *seeds, int32_t ns,
+                              const double *scales, int32_t S, uint32_t k_prune,
+                              uint64_t max_calls, int32_t *out_members,
+                              int64_t members_cap, int64_t *out_off, int64_t *out_K,
+                              int64_t *out_V, double *out_f, uint64_t *out_ctr,
+                              lcdo_trace *trace);
+
 int lcdo_run_set(lcdo_ctx *g, const int32_t *seeds, int32_t ns,
                  const double *scales, int32_t S, uint32_t k_prune,
                  int32_t *out_members, int64_t members_cap, int64_t *out_off,
                  int64_t *out_K, int64_t *out_V, double *out_f,
                  uint64_t *out_ctr, lcdo_trace *trace)
+{
+    return lcdo_run_set_calls(g, seeds, ns, scales, S, k_prune, 0, out_members,
+                              members_cap, out_off, out_K, out_V, out_f, out_ctr, trace);
+}
+
+/* The same with at most max_calls growth calls per scale (0 = until a call
+ * changes nothing, R6); the check-and-merge loop makes one call per round. */
+static int lcdo_run_set_calls(lcdo_ctx *g, const int32_t *seeds, int32_t ns,
+                              const double *scales, int32_t S, uint32_t k_prune,
+                              uint64_t max_calls, int32_t *out_members,
+                              int64_t members_cap, int64_t *out_off, int64_t *out_K,
+                              int64_t *out_V, double *out_f, uint64_t *out_ctr,
+                              lcdo_trace *trace)
 {
     lcdo_reset(g);
     g->trace = trace;
@@ -491,6 +511,8 @@ int lcdo_run_set(lcdo_ctx *g, const int32_t *seeds, int32_t ns,
         for (;;) {                   /* R6: grow until nothing changes */
             calls += 1;
             if (lcdo_grow(g, alpha, k_prune) == 0)
+                break;
+            if (max_calls != 0 && calls >= max_calls)
                 break;
         }
         out_ctr[4 * s + 0] = g->G;
@@ -630,9 +652,13 @@ int64_t lcdo_seeds(const lcdo_ctx *g, const int32_t *perm, int rule, int32_t *ou
  *      partner;
  *   M4 pre-test (Algorithm 3): a live community with a partner under the
  *      round's first M is not grown in that round;
- *   M5 growth: every other community that needs it grows to its fixpoint at
- *      the scale (one-scale lcdo_run_set from its members); at the start of
- *      a scale all live communities need it, later only merged survivors;
+ *   M5 growth: every other community that needs it makes one call of the
+ *      growth function at the scale, from its members (Algorithm 2 calls
+ *      growth once per community and round, and repeats the round while
+ *      anything changes); a live community needs a call at the start of a
+ *      scale, after a call that changed it and after a merge it survived
+ *      (a call on an unchanged community changes nothing again: the call
+ *      is a function of the member set);
  *   M6 check: for each pre-tested or changed community, ascending, its
  *      partner under the post-growth M gives the pair (min, max);
  *   M7 merge: the pairs sorted ascending without repeats; repeatedly take,
@@ -825,8 +851,8 @@ int lcdo_run_merge(lcdo_ctx *g, const int32_t *seed_ptr, const int32_t *seed_nod
                 int64_t k1, v1;
                 double f1;
                 uint64_t c4[4];
-                if (lcdo_run_set(g, m.mem[j], m.msz[j], &alpha, 1, k_prune, tmp, n, off2, &k1, &v1, &f1,
-                                 c4, NULL) != 0) {
+                if (lcdo_run_set_calls(g, m.mem[j], m.msz[j], &alpha, 1, k_prune, 1, tmp, n, off2, &k1,
+                                       &v1, &f1, c4, NULL) != 0) {
                     status = -2;
                     goto done;
                 }
@@ -847,7 +873,7 @@ int lcdo_run_merge(lcdo_ctx *g, const int32_t *seed_ptr, const int32_t *seed_nod
                 V[j] = v1;
                 for (int q = 0; q < 4; ++q)
                     acc[4 * j + q] += c4[q];
-                need[j] = 0;
+                need[j] = changed[j];
                 grew |= changed[j];
             }
             if (lcdo_mg_memberships(g, &m) != 0) {

@@ -10,10 +10,17 @@ overlap pre-test of Algorithm 3).
 * on the planted-partition graph the live communities are the planted
   sub-communities (up to a node or two) at the finest scale and exactly the
   planted groups at the coarsest, the two levels the method is meant to find
-  (Sec. 4.1)."""
+  (Sec. 4.1);
+* every record and merged-into id equals a from-scratch Python replay of
+  Algorithm 2's rounds (one growth call per community and round, then check
+  and merge), on random graphs and on a 24-node case where growing each
+  community to its fixpoint inside a round would end with other member
+  sets."""
 import numpy as np
 import pytest
 
+import _replay as RP
+import _replay_merge as RM
 from paper_1301_0955_amd import workloads as W
 
 
@@ -86,3 +93,47 @@ def test_planted_levels(oracle_mod):
         planted = set(range(50 * k, 50 * k + 50))
         assert len(planted & set(c)) / len(planted | set(c)) >= 0.9
     assert live_sets(S - 1) == [list(range(250 * k, 250 * k + 250)) for k in range(4)]
+
+
+def _replay_records(g, sp, sn, sc, eta, calls_per_round=1):
+    sets = [sn[sp[j]:sp[j + 1]] for j in range(sp.size - 1)]
+    return RM.merge_sweep(RP.Graph(g.n, g.row_ptr, g.col, g.w), sets, sc, eta=eta,
+                          calls_per_round=calls_per_round)
+
+
+def _assert_same_as_replay(r, ref, S, ns):
+    for s in range(S):
+        for j in range(ns):
+            rec = j * S + s
+            members, K, V, ctr, into = ref[s][j]
+            assert sorted(_members(r, rec)) == members, (s, j)
+            assert r["cnt"][rec] == len(members), (s, j)
+            assert (int(r["K"][rec]), int(r["V"][rec])) == (K, V), (s, j)
+            assert [int(x) for x in r["ctr"][rec]] == ctr, (s, j)
+            assert int(r["into"][rec]) == into, (s, j)
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("eta", [(1, 2), (2, 3)])
+def test_rounds_match_definition_replay(oracle_mod, seed, eta):
+    for n, p in [(16, 0.25), (24, 0.18)]:
+        g = W.random_graph(n, p, weighted=seed % 2 == 0, seed=seed)
+        sp, sn = W.singleton_seeds(g.n)
+        sc = W.log_scales(5, 0.4, 1.2)
+        r = oracle_mod.Oracle.from_graph(g).run_merge(sp, sn, sc, eta=eta)
+        _assert_same_as_replay(r, _replay_records(g, sp, sn, sc, eta), sc.size, sp.size - 1)
+
+
+def test_one_growth_call_per_round(oracle_mod):
+    # 24-node weighted random graph, every node a seed, 4 scales on
+    # [0.4, 1.2]: one growth call per round (Algorithm 2) and growth to the
+    # fixpoint inside each round end with different member sets
+    g = W.random_graph(24, 0.18, weighted=True, seed=154)
+    sp, sn = W.singleton_seeds(g.n)
+    sc = W.log_scales(4, 0.4, 1.2)
+    one = _replay_records(g, sp, sn, sc, (1, 2))
+    fix = _replay_records(g, sp, sn, sc, (1, 2), calls_per_round=None)
+    assert any(one[s][j][0] != fix[s][j][0] or one[s][j][4] != fix[s][j][4]
+               for s in range(sc.size) for j in range(g.n))
+    r = oracle_mod.Oracle.from_graph(g).run_merge(sp, sn, sc)
+    _assert_same_as_replay(r, one, sc.size, sp.size - 1)

@@ -35,6 +35,8 @@ MUTANTS = {
                                  "                        m.alive[b] = 0;\n                        m.into[b] = a;\n                        need[a] = 1;\n                        { int32_t *t_ = m.mem[a]; m.mem[a] = m.mem[b]; m.mem[b] = t_; }"),
     "merge_threshold_uses_larger": ("const int64_t small = m->msz[c] < m->msz[i] ? m->msz[c] : m->msz[i];",
                                     "const int64_t small = m->msz[c] > m->msz[i] ? m->msz[c] : m->msz[i];"),
+    "merge_growth_to_fixpoint": [("&alpha, 1, k_prune, 1, tmp, n, off2, &k1,", "&alpha, 1, k_prune, 0, tmp, n, off2, &k1,"),
+                                 ("need[j] = changed[j];", "need[j] = 0;")],
     "rank_uses_d_out": ("lcdo_push(g, lcdo_rank(g->d[u], g->k[u], alpha), u, g->ver[u]);",
                         "lcdo_push(g, lcdo_rank(g->d[u], g->k[u] - g->d[u] + 1, alpha), u, g->ver[u]);"),
 }
@@ -48,11 +50,15 @@ PINS_OF = {"seed_": ["tests/test_oracle_seeds.py"], "merge_": ["tests/test_oracl
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_catch_mutant(tmp_path, name):
-    old, new = MUTANTS[name]
+    edits = MUTANTS[name]
+    if isinstance(edits, tuple):
+        edits = [edits]
     src = open(SRC).read()
-    assert src.count(old) == 1, name
+    for old, new in edits:
+        assert src.count(old) == 1, name
+        src = src.replace(old, new)
     mut = tmp_path / "mutant.c"
-    mut.write_text(src.replace(old, new))
+    mut.write_text(src)
     so = tmp_path / "libmutant.so"
     subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
                     str(mut), "-o", str(so), "-lm"], check=True)
