@@ -6,9 +6,13 @@
  * by the growth function of Algorithm 1 (priority-queue additions ranked by
  * 2 d_in / (d_in + d_out)^alpha, then removal passes), repeated until
  * nothing changes at one scale and chained from each scale to the next
- * coarser one (Sec. 2 and the growth half of Algorithm 2).  Seed sets are
- * independent communities; the overlap-merge phase of Algorithm 2 is not
- * part of this library.
+ * coarser one (Sec. 2 and the growth half of Algorithm 2).  In lcd_sweep and
+ * the query server every seed set is an independent community;
+ * lcd_sweep_merge adds the check-and-merge phase of Algorithm 2.
+ * Paper: E. Le Martelot and C. Hankin, "Fast Multi-Scale Community
+ * Detection based on Local Criteria within a Multi-Threaded Algorithm",
+ * arXiv:1301.0955.  Each call below names the passage that defines what it
+ * computes.
  *
  * Exact semantics (shared with the test oracle, written independently):
  *   - k_in counts internal edges from both ends: adding node n raises it by
@@ -95,6 +99,9 @@ typedef struct {
                                 0 = max(1,024, 2 lds_capacity), within one workgroup's LDS */
     int32_t team_waves;      /* waves per community in the workgroup tiers, 1..8;
                                 0 = 4 */
+    int32_t grow_calls;      /* growth calls per (seed set, scale): 0 = until a call
+                                changes nothing (the default); n > 0 stops after
+                                n calls (lcd_sweep_merge makes one per round) */
 } lcd_params;
 
 /* Work of one table tier (0 = one wave per community with an LDS table; the
@@ -134,6 +141,10 @@ void lcd_params_default(lcd_params *p);
 
 /*
  * Upload an undirected graph in symmetric CSR form and keep it resident.
+ * Paper: Sec. 2 (the graph is undirected and weighted: d_in, d_out and the
+ * node degree k in the fitness of Eq. 1 and the queue factor of Algorithm 1
+ * are sums of edge weights); Sec. 3 (complexity: direct access to each
+ * node's neighbours).
  *   n        nodes, 0 <= n < 2^31
  *   nnz      directed entries (twice the undirected edges), < 2^31
  *   row_ptr  int32[n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz
@@ -181,6 +192,12 @@ lcd_status lcd_graph_free(lcd_graph *g);
 
 /*
  * Grow every seed set through every scale.
+ * Paper: Sec. 2, Eq. 1 (fitness) and Eq. 2 (node fitness, the add and
+ * remove tests); Algorithm 1 (one growth call: queue ranked by
+ * 2 d_in / (d_in + d_out)^alpha, additions, then removal passes);
+ * Algorithm 2 (initial communities given as input; for each scale, growth
+ * repeated while it changes something, then the next scale starts from the
+ * result), without its check-and-merge phase.
  *   scales      double[n_scales], finite, >= 0, <= 1000, strictly decreasing
  *               (finest first: large alpha = small communities)
  *   seed_ptr    int32[n_sets+1] offsets into seed_nodes; set j is
@@ -191,7 +208,13 @@ lcd_status lcd_graph_free(lcd_graph *g);
  * The result holds, for each record r = j * n_scales + s: the sorted member
  * list, K = k_in, V = k_in + k_out, f = K / pow(V, alpha_s) and the work
  * counters (criterion evaluations G, rank updates R, moves M, growth calls C).
- * Blocking: returns after the sweep has finished on the stream.
+ * Blocking: the work is queued on stream and the call returns after the
+ * sweep has finished there (the library reads the device's error word and
+ * member-pool fill to grow the pool and run again if it overflowed).
+ * Errors: LCD_EINVAL for an argument outside the rules above;
+ * LCD_ENOMEM when device memory runs out; LCD_ECAPACITY when a set's table
+ * outgrows the largest tier; LCD_EDEVICE for a failed launch or a kernel
+ * error (watchdog, probe failure).  On error *out is NULL.
  */
 lcd_status lcd_sweep(const lcd_graph *g, const double *scales, int32_t n_scales,
                      const int32_t *seed_ptr, const int32_t *seed_nodes, int32_t n_sets,
@@ -263,8 +286,10 @@ lcd_status lcd_sweep_batch(const lcd_graph *g, const double *scales, int32_t n_s
  *     order, at least eta * min(|c|, |i|) nodes with another live
  *     community i (eta = eta_num / eta_den; the paper's 0.5 is 1 / 2) is
  *     not grown in that round;
- *   - every other community that needs it grows to its fixpoint at the
- *     scale (all at the start of a scale, later only merged ones);
+ *   - every other community that needs it makes one call of the growth
+ *     function at the scale (each live one at the start of a scale, then
+ *     those that the last call changed and the survivors of merges); the
+ *     round repeats while a call changed something or a pair merged;
  *   - each pre-tested or changed community with such a partner forms the
  *     pair (lower id, higher id); the pairs, ascending, merge in passes of
  *     pairwise disjoint pairs into their lower ids (union of members; the
@@ -290,12 +315,22 @@ lcd_status lcd_sweep_merge(const lcd_graph *g, const double *scales, int32_t n_s
  * lcd_sweep. */
 lcd_status lcd_result_merged_into(const lcd_result *r, int32_t scale_idx, int32_t *into);
 
-/* Sweep shape and the total number of members listed at one scale. */
+/*
+ * Sweep shape, and the total number of members listed at one scale (the
+ * size the members buffer of lcd_result_membership needs).
+ * Paper: Algorithm 2 stores the community set and its quality for every
+ * scale.  LCD_EINVAL for a null result or a scale index out of range.
+ * Blocking.
+ */
 lcd_status lcd_result_shape(const lcd_result *r, int32_t *n_sets, int32_t *n_scales);
 lcd_status lcd_result_sizes(const lcd_result *r, int32_t scale_idx, int64_t *total_members);
 
 /*
- * Communities at one scale, in caller buffers (all in mem_kind memory):
+ * Communities at one scale, in caller buffers (all in mem_kind memory).
+ * Paper: Algorithm 2 (the community set and its quality stored per scale);
+ * Sec. 3 (community nodes kept sorted); f is Eq. 1 at that scale.
+ * LCD_ECAPACITY when the scale lists 2^31 members or more in all (int32
+ * offsets cannot address them); nothing is written then.
  *   comm_ptr int32[n_sets+1]    offsets into members
  *   members  int32[total]       each community ascending
  *   k_in, vol int64[n_sets], f double[n_sets]   (each may be NULL)
@@ -307,7 +342,9 @@ lcd_status lcd_result_membership(const lcd_result *r, int32_t scale_idx, int32_t
 
 /*
  * Overlap at one scale: for every node, the seed sets whose community holds
- * it (the paper's per-node membership sets).
+ * it.  Paper: Sec. 3 (the per-node membership sets that the check phase of
+ * Algorithm 2 reads).  LCD_ECAPACITY, as for lcd_result_membership, when
+ * the scale lists 2^31 members or more.
  *   node_ptr  int32[n+1], node_sets int32[total members], ascending per node.
  * Blocking.
  */
@@ -317,6 +354,10 @@ lcd_status lcd_result_overlap(const lcd_result *r, int32_t scale_idx, int32_t *n
 /*
  * Work counters: totals[4] = sums of G, R, M, C over all records (host
  * memory); per_record (n_sets * n_scales * 4, in mem_kind memory) may be NULL.
+ * Paper: the counts are those of a sequential run of Algorithm 1 and the
+ * scale loop of Algorithm 2: G = queue pops plus members visited by the
+ * removal passes (one evaluation of Eq. 2 each), R = queue (re)insertions
+ * with a fresh rank, M = nodes added or removed, C = growth calls.
  * Blocking.
  */
 lcd_status lcd_result_counters(const lcd_result *r, uint64_t *totals, uint64_t *per_record,

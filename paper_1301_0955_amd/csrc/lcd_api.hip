@@ -275,6 +275,7 @@ lcd_status run_group(lcd_result *r, const TierPlan &tp, int32_t s_begin, int32_t
     a.seed_nodes = r->seed_nodes;
     a.n_sets = r->n_sets;
     a.k_prune = r->prm.k_prune;
+    a.max_calls = r->prm.grow_calls > 0 ? (uint32_t)r->prm.grow_calls : 0u;
     a.resume = s_begin > 0 ? 1 : 0;
     a.rec = r->rec;
     a.pool = r->pool;
@@ -773,6 +774,8 @@ lcd_status lcd_sweep(const lcd_graph *g, const double *scales, int32_t n_scales,
         return fail(LCD_EINVAL, "unknown mode %d", prm.mode);
     if (prm.watchdog_ms == 0)
         prm.watchdog_ms = 20000;
+    if (prm.grow_calls < 0)
+        return fail(LCD_EINVAL, "grow_calls must be >= 0");
     apply_tuned(g, prm);
     hipStream_t st = (hipStream_t)stream;
     std::vector<double> sc;
@@ -1001,8 +1004,8 @@ lcd_status lcd_sweep_batch(const lcd_graph *g, const double *scales, int32_t n_s
 // neither grows nor merges: memberships of the live communities (device
 // readout kernels); overlap partner of every live community (device,
 // partner_kernel) -> those with a partner skip growth; the others that need
-// it grow to their fixpoint at the scale (the sweep kernels, one scale, from
-// their member lists); memberships again and the partners of the pre-tested
+// it make one growth call at the scale (the sweep kernels, one scale, one
+// call, from their member lists); memberships again and the partners of the pre-tested
 // or changed communities -> pairs; the pairs merge into their lower ids in
 // passes of pairwise disjoint pairs.  The bookkeeping between launches
 // (member lists, unions of merged pairs, pair passes) is host code.
@@ -1045,6 +1048,7 @@ lcd_status lcd_sweep_merge(const lcd_graph *g, const double *scales, int32_t n_s
         prm = *params;
     prm.mode = LCD_PERSISTENT;
     prm.use_graph = 0;
+    prm.grow_calls = 1;   // one growth call per community and round
     // state of every community (host)
     std::vector<std::vector<int32_t>> lists((size_t)ns);
     {
@@ -1238,7 +1242,7 @@ lcd_status lcd_sweep_merge(const lcd_graph *g, const double *scales, int32_t n_s
                     V[j] = rv[t];
                     for (int q = 0; q < 4; ++q)
                         acc[4 * j + q] += rct[4 * t + q];
-                    need[j] = 0;
+                    need[j] = changed[j];   // a call that changed it calls for another
                 }
             }
             // check
@@ -1509,6 +1513,41 @@ lcd_status lcd_result_shape(const lcd_result *r, int32_t *n_sets, int32_t *n_sca
     return LCD_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Offsets of one scale's member lists into cp (device, n_sets + 1 entries)
+// and their exact total.  The int32 offsets wrap when the total passes
+// 2^31 - 1, so callers that use them must check the total first.
+lcd_status scale_offsets(const lcd_result *r, int32_t scale_idx, int32_t *cp, hipStream_t st,
+                         int64_t *total) {
+    long long *d_tot = nullptr;
+    CHK(dev_alloc(&d_tot, 1));
+    long long tot = 0;
+    hipError_t e = launch_scale_scan(r->rec, r->S, scale_idx, r->n_sets, cp, d_tot, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&tot, d_tot, sizeof(long long), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    dev_free(d_tot);
+    if (e != hipSuccess)
+        return fail(LCD_EDEVICE, "scale offsets: %s", hipGetErrorString(e));
+    *total = (int64_t)tot;
+    return LCD_OK;
+}
+
+lcd_status check_int32_total(int64_t total, int32_t scale_idx) {
+    if (total > (int64_t)INT32_MAX)
+        return fail(LCD_ECAPACITY, "scale %d lists %lld members; int32 offsets address at most 2^31 - 1",
+                    scale_idx, (long long)total);
+    return LCD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 lcd_status lcd_result_sizes(const lcd_result *r, int32_t scale_idx, int64_t *total_members) {
     if (!r || !total_members)
         return fail(LCD_EINVAL, "null argument");
@@ -1516,13 +1555,10 @@ lcd_status lcd_result_sizes(const lcd_result *r, int32_t scale_idx, int64_t *tot
         return fail(LCD_EINVAL, "scale index %d out of range", scale_idx);
     int32_t *cp = nullptr;
     CHK(dev_alloc(&cp, (size_t)r->n_sets + 1));
-    hipError_t e = launch_scale_scan(r->rec, r->S, scale_idx, r->n_sets, cp, nullptr);
-    int32_t tot = 0;
-    if (e == hipSuccess)
-        e = hipMemcpy(&tot, cp + r->n_sets, sizeof(int32_t), hipMemcpyDeviceToHost);
+    int64_t tot = 0;
+    const lcd_status s = scale_offsets(r, scale_idx, cp, nullptr, &tot);
     dev_free(cp);
-    if (e != hipSuccess)
-        return fail(LCD_EDEVICE, "sizes: %s", hipGetErrorString(e));
+    CHK(s);
     *total_members = tot;
     return LCD_OK;
 }
@@ -1547,14 +1583,17 @@ lcd_status lcd_result_membership(const lcd_result *r, int32_t scale_idx, int32_t
         CHK(dev_alloc(&tmp_cp, ns + 1));
         cp = tmp_cp;
     }
-    HIPCHK(launch_scale_scan(r->rec, r->S, scale_idx, r->n_sets, cp, st));
-    int32_t tot = 0;
-    HIPCHK(hipMemcpyAsync(&tot, cp + ns, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    int64_t tot = 0;
+    lcd_status s = scale_offsets(r, scale_idx, cp, st, &tot);
+    if (s == LCD_OK)
+        s = check_int32_total(tot, scale_idx);
+    if (s != LCD_OK) {
+        dev_free(tmp_cp);
+        return s;
+    }
     int32_t *m = members;
     int64_t *kk = k_in, *vv = vol;
     double *ff = f;
-    lcd_status s = LCD_OK;
     if (host) {
         if (members && (s = dev_alloc(&tmp_m, (size_t)tot)) != LCD_OK)
             goto done;
@@ -1613,20 +1652,13 @@ lcd_status lcd_result_overlap(const lcd_result *r, int32_t scale_idx, int32_t *n
     const size_t ns = (size_t)r->n_sets;
     int32_t *cp = nullptr, *mem = nullptr, *cnt = nullptr, *bs = nullptr, *np = nullptr, *nsets = nullptr;
     lcd_status s = LCD_OK;
-    int32_t tot = 0;
+    int64_t tot = 0;
     const int nb = (int)(((int64_t)n + 1 + 1023) / 1024);
     hipError_t e;
     if ((s = dev_alloc(&cp, ns + 1)) != LCD_OK)
         goto done;
-    e = launch_scale_scan(r->rec, r->S, scale_idx, r->n_sets, cp, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(&tot, cp + ns, sizeof(int32_t), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(st);
-    if (e != hipSuccess) {
-        s = fail(LCD_EDEVICE, "overlap: %s", hipGetErrorString(e));
+    if ((s = scale_offsets(r, scale_idx, cp, st, &tot)) != LCD_OK || (s = check_int32_total(tot, scale_idx)) != LCD_OK)
         goto done;
-    }
     if ((s = dev_alloc(&mem, (size_t)tot)) != LCD_OK || (s = dev_alloc(&cnt, (size_t)n + 1)) != LCD_OK ||
         (s = dev_alloc(&bs, (size_t)nb + 1)) != LCD_OK)
         goto done;

@@ -53,6 +53,7 @@ struct SweepArgs {
     const int32_t *seed_nodes;
     int32_t n_sets;
     uint32_t k_prune;
+    uint32_t max_calls;       // growth calls per (set, scale); 0 = until one changes nothing
     int32_t resume;           // 1: start from the records of scale s_begin - 1
     Records rec;
     int32_t *pool;
@@ -107,8 +108,9 @@ hipError_t launch_sweep(const SweepArgs &a, int32_t blocks, int32_t waves_per_bl
 // given waves per workgroup and dynamic LDS bytes.
 hipError_t tier_blocks_per_cu(int32_t kind, int32_t waves, size_t lds_bytes, int32_t *out);
 // readout
+// comm_ptr[0..n_sets] (int32, wraps past 2^31 - 1) and the exact total in *total
 hipError_t launch_scale_scan(const Records &rec, int32_t S, int32_t s, int32_t n_sets,
-                             int32_t *comm_ptr, hipStream_t st);
+                             int32_t *comm_ptr, long long *total, hipStream_t st);
 hipError_t launch_scale_gather(const Records &rec, const int32_t *pool, const double *scales,
                                int32_t S, int32_t s, int32_t n_sets, const int32_t *comm_ptr,
                                int32_t *members, int64_t *k_in, int64_t *vol, double *f,

@@ -572,15 +572,45 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
     c.logtab = A.g.logtab;
     c.logtab_last = A.g.logtab_n - 1;
     const uint32_t n_items = A.tier == 0 ? (uint32_t)A.n_sets : A.ctl->ovf_count[A.in_from];
+    // What one item leaves for the device-wide counters is published by
+    // lane 0 at the top of the next iteration, in the same lane-0 block that
+    // takes the next item.  The item loop so has exactly one lane-0 block,
+    // and its exits test wave-uniform (scalar) values: a lane-0 block at
+    // both ends of such a loop lets the compiler thread them into a second
+    // back edge that lanes 1..63 take without lane 0.
+    bool pend = false;          // an item's epilogue is waiting
+    uint32_t pend_push = 0;     // overflow item to push (valid if pend_ovf)
+    bool pend_ovf = false;
+    uint32_t pend_err = 0;
+    uint64_t pend_stat[5] = {0, 0, 0, 0, 0};
     for (;;) {
         uint32_t item = 0;
-        if (lane == 0)
+        if (lane == 0) {
+            if (pend) {
+                if (pend_ovf) {
+                    if (A.work_out) {
+                        const uint32_t pos = atomicAdd(&A.ctl->ovf_count[A.tier], 1u);
+                        A.work_out[pos] = (int32_t)pend_push;
+                    } else {
+                        atomicOr(A.err, ERR_CAPACITY);
+                    }
+                }
+                if (pend_err)
+                    atomicOr(A.err, pend_err);
+                if (!pend_ovf) {
+                    unsigned long long *sx = A.stat + 5 * A.tier;
+                    for (int q = 0; q < 5; ++q)
+                        atomicAdd(&sx[q], (unsigned long long)pend_stat[q]);
+                }
+            }
             item = atomicAdd(&A.ctl->work_next[A.tier], 1u);
-        item = __shfl(item, 0);
-        if (item >= n_items)
-            break;
+        }
+        pend = false;
+        item = (uint32_t)__builtin_amdgcn_readfirstlane((int)item);
         // another wave hit the watchdog: stop taking work
-        if (__hip_atomic_load(A.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_TIMEOUT)
+        const uint32_t abort = (uint32_t)__builtin_amdgcn_readfirstlane(
+            (int)(__hip_atomic_load(A.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_TIMEOUT));
+        if (item >= n_items || abort)
             break;
         // a later tier's item is set * S + s: the set overflowed the tier
         // before during scale s and resumes there from its scale s - 1 record
@@ -671,6 +701,8 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
                 moved += mv;
                 if (st.ovf || st.err || mv == 0)
                     break;
+                if (A.max_calls != 0 && calls >= (uint64_t)A.max_calls)
+                    break;
                 if ((int64_t)calls > st.move_limit) {
                     st.err |= ERR_LIMIT;
                     break;
@@ -720,27 +752,15 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
                 A.rec.ctr[4 * r + 3] = calls;
             }
         }
-        if (st.ovf && lane == 0) {
-            if (A.work_out) {
-                const uint32_t pos = atomicAdd(&A.ctl->ovf_count[A.tier], 1u);
-                A.work_out[pos] = set * A.S + s_at;
-            } else {
-                atomicOr(A.err, ERR_CAPACITY);
-            }
-        }
-        if (st.err) {
-            const uint32_t e = st.err;
-            if (lane == 0)
-                atomicOr(A.err, e);
-        }
-        if (!st.ovf && lane == 0) {
-            unsigned long long *sx = A.stat + 5 * A.tier;
-            atomicAdd(&sx[0], (unsigned long long)st.rows);
-            atomicAdd(&sx[1], (unsigned long long)st.row_len);
-            atomicAdd(&sx[2], (unsigned long long)st.inserted);
-            atomicAdd(&sx[3], (unsigned long long)st.written);
-            atomicAdd(&sx[4], 1ull);
-        }
+        pend = true;
+        pend_ovf = st.ovf;
+        pend_push = (uint32_t)(set * A.S + s_at);
+        pend_err = st.err;
+        pend_stat[0] = st.rows;
+        pend_stat[1] = st.row_len;
+        pend_stat[2] = st.inserted;
+        pend_stat[3] = st.written;
+        pend_stat[4] = 1;
         if constexpr (GLOBAL) {
             // leave the slab's hash empty for the next community
             wsync<GLOBAL>();
@@ -1330,6 +1350,8 @@ __device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh) {
                 moved += mv;
                 if (st.ovf || st.err || mv == 0)
                     break;
+                if (A.max_calls != 0 && calls >= (uint64_t)A.max_calls)
+                    break;
                 if ((int64_t)calls > st.move_limit) {
                     st.err |= ERR_LIMIT;
                     break;
@@ -1494,9 +1516,12 @@ __global__ void fill_i32_kernel(int32_t *p, int32_t v, int64_t n) {
 // Readout
 // ---------------------------------------------------------------------------
 
-// exclusive scan of the member counts of one scale (single workgroup)
+// exclusive scan of the member counts of one scale (single workgroup); the
+// exact int64 total goes to *total, so the host can refuse a scale whose
+// int32 offsets would wrap before it sizes or gathers anything
 __global__ void __launch_bounds__(1024) scale_scan_kernel(const int32_t *cnt, int32_t S, int32_t s,
-                                                          int32_t n_sets, int32_t *comm_ptr) {
+                                                          int32_t n_sets, int32_t *comm_ptr,
+                                                          long long *total) {
     __shared__ int64_t part[1024];
     const int tid = threadIdx.x;
     const int64_t per = ((int64_t)n_sets + 1023) / 1024;
@@ -1518,8 +1543,10 @@ __global__ void __launch_bounds__(1024) scale_scan_kernel(const int32_t *cnt, in
         comm_ptr[j] = (int32_t)run;
         run += cnt[j * S + s];
     }
-    if (tid == 1023)
+    if (tid == 1023) {
         comm_ptr[n_sets] = (int32_t)part[1023];
+        *total = (long long)part[1023];
+    }
 }
 
 __global__ void __launch_bounds__(256) scale_gather_kernel(Records rec, const int32_t *pool,
@@ -1966,8 +1993,8 @@ hipError_t tier_blocks_per_cu(int32_t kind, int32_t waves, size_t lds_bytes, int
 }
 
 hipError_t launch_scale_scan(const Records &rec, int32_t S, int32_t s, int32_t n_sets,
-                             int32_t *comm_ptr, hipStream_t st) {
-    hipLaunchKernelGGL(scale_scan_kernel, dim3(1), dim3(1024), 0, st, rec.cnt, S, s, n_sets, comm_ptr);
+                             int32_t *comm_ptr, long long *total, hipStream_t st) {
+    hipLaunchKernelGGL(scale_scan_kernel, dim3(1), dim3(1024), 0, st, rec.cnt, S, s, n_sets, comm_ptr, total);
     return hipGetLastError();
 }
 

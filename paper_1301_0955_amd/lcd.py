@@ -37,7 +37,7 @@ class lcd_params(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("pool_hint", ctypes.c_int64), ("watchdog_ms", ctypes.c_int32),
                 ("spill_mode", ctypes.c_int32), ("team_capacity", ctypes.c_int32),
-                ("team_waves", ctypes.c_int32)]
+                ("team_waves", ctypes.c_int32), ("grow_calls", ctypes.c_int32)]
 
 
 class lcd_tier_stats(ctypes.Structure):
@@ -412,7 +412,7 @@ class Result:
 def make_params(k_prune: int = 0, mode: int = LCD_PERSISTENT, lds_capacity: int = 0,
                 waves_per_block: int = 0, blocks_per_cu: int = 0, use_graph: int = 0,
                 pool_hint: int = 0, watchdog_ms: int = 0, spill_mode: int = 0,
-                team_capacity: int = 0, team_waves: int = 0) -> lcd_params:
+                team_capacity: int = 0, team_waves: int = 0, grow_calls: int = 0) -> lcd_params:
     p = lcd_params()
     library().lcd_params_default(ctypes.byref(p))
     p.k_prune = k_prune
@@ -427,6 +427,7 @@ def make_params(k_prune: int = 0, mode: int = LCD_PERSISTENT, lds_capacity: int 
     p.spill_mode = spill_mode
     p.team_capacity = team_capacity
     p.team_waves = team_waves
+    p.grow_calls = grow_calls
     return p
 
 
