@@ -93,6 +93,8 @@ def lib():
         L.lcdo_run_sets.argtypes = [P, P, P, ctypes.c_int32, P, ctypes.c_int32,
                                     ctypes.c_uint32, P, ctypes.c_int64, P, P, P, P,
                                     P, P, P]
+        L.lcdo_nmi.restype = ctypes.c_double
+        L.lcdo_nmi.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_int32, P, P]
         _lib = L
     return _lib
 
@@ -116,6 +118,49 @@ def improves(Kp: int, Vp: int, K: int, V: int, alpha: float):
 
 def rank(d: int, k: int, alpha: float) -> float:
     return lib().lcdo_rank(d, k, alpha)
+
+
+def _cover_csr(cover):
+    """A cover as (int64 offsets, int32 members): a list of node-id arrays,
+    or an (offsets, members) pair already in that form."""
+    if isinstance(cover, tuple):
+        ptr, mem = cover
+        return (np.ascontiguousarray(ptr, dtype=np.int64), np.ascontiguousarray(mem, dtype=np.int32))
+    sizes = [len(c) for c in cover]
+    ptr = np.zeros(len(cover) + 1, np.int64)
+    np.cumsum(sizes, out=ptr[1:])
+    mem = (np.concatenate([np.asarray(c, np.int32) for c in cover]) if cover and ptr[-1] > 0
+           else np.zeros(1, np.int32))
+    return ptr, np.ascontiguousarray(mem, dtype=np.int32)
+
+
+def nmi(n: int, cover_x, cover_y) -> float:
+    """Normalised mutual information of two covers of n nodes (the
+    overlapping-community definition the paper uses in Sec. 4; readings N1-N4
+    in lcd_oracle.c).  A cover is a list of node-id arrays (each without
+    repeats) or an (offsets, members) pair."""
+    px, mx = _cover_csr(cover_x)
+    py, my = _cover_csr(cover_y)
+    v = lib().lcdo_nmi(int(n), px.size - 1, _ptr(px), _ptr(mx), py.size - 1, _ptr(py), _ptr(my))
+    if v < -1.0:
+        raise MemoryError("lcdo_nmi")
+    return v
+
+
+def nmi_successive(n: int, covers, p: int) -> np.ndarray:
+    """Sec. 4's NMI averaged over p successive scales: for every window of
+    p consecutive covers starting at scale s, the mean of the NMI of its
+    p - 1 consecutive pairs (reading N5); len(covers) - p + 1 values."""
+    if p < 2 or p > len(covers):
+        raise ValueError("p must be in [2, number of scales]")
+    pair = [nmi(n, covers[t], covers[t + 1]) for t in range(len(covers) - 1)]
+    out = []
+    for s in range(len(covers) - p + 1):
+        acc = 0.0
+        for t in range(s, s + p - 1):
+            acc += pair[t]
+        out.append(acc / (p - 1))
+    return np.array(out, dtype=np.float64)
 
 
 class Oracle:

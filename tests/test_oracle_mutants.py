@@ -37,6 +37,10 @@ MUTANTS = {
                                     "const int64_t small = m->msz[c] > m->msz[i] ? m->msz[c] : m->msz[i];"),
     "merge_growth_to_fixpoint": [("&alpha, 1, k_prune, 1, tmp, n, off2, &k1,", "&alpha, 1, k_prune, 0, tmp, n, off2, &k1,"),
                                  ("need[j] = changed[j];", "need[j] = 0;")],
+    "nmi_admission_reversed": ("if (!(ha + he > hb + hc))", "if (!(ha + he < hb + hc))"),
+    "nmi_max_instead_of_min": ("if (!found || cond < best) {", "if (!found || cond > best) {"),
+    "nmi_unnormalised": ("sum += best / hx;", "sum += best;"),
+    "nmi_joint_drops_a_cell": ("const double hxy = ((ha + hb) + hc) + he;", "const double hxy = (ha + hb) + hc;"),
     "rank_uses_d_out": ("lcdo_push(g, lcdo_rank(g->d[u], g->k[u], alpha), u, g->ver[u]);",
                         "lcdo_push(g, lcdo_rank(g->d[u], g->k[u] - g->d[u] + 1, alpha), u, g->ver[u]);"),
 }
@@ -45,7 +49,8 @@ PINS = ["tests/test_oracle_bruteforce.py", "tests/test_oracle_replay.py",
         "tests/test_oracle_limits.py", "tests/test_oracle_audit.py"]
 # mutants of the seed selection and of the merge phase are run against the
 # pins of that part only
-PINS_OF = {"seed_": ["tests/test_oracle_seeds.py"], "merge_": ["tests/test_oracle_merge.py"]}
+PINS_OF = {"seed_": ["tests/test_oracle_seeds.py"], "merge_": ["tests/test_oracle_merge.py"],
+           "nmi_": ["tests/test_oracle_nmi.py"]}
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
