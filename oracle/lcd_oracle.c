@@ -1025,8 +1025,11 @@ done:
  *      the order written below;
  *   N2 a cover is taken as listed: every community counts, a repeated one
  *      each time it is listed;
- *   N3 a community with H(X_k) = 0 (empty, or every node) adds 0 to its mean;
- *   N4 with an empty cover the NMI is 1 if both are empty, else 0.
+ *   N3 an empty community is no community: it is skipped on both sides (it
+ *      adds no term and does not count in the mean); a community of every
+ *      node (H(X_k) = 0) adds 0 to its mean;
+ *   N4 a cover without a non-empty community: the NMI is 1 if both are so,
+ *      else 0.
  */
 static double lcdo_h(int64_t c, int64_t n)
 {
@@ -1064,8 +1067,12 @@ static double lcdo_nmi_half(int32_t n, int32_t kx, const int64_t *px, const int3
         for (int64_t q = py[l]; q < py[l + 1]; ++q)
             node_sets[fill[my[q]]++] = l;
     double sum = 0.0;
+    int32_t counted = 0;
     for (int32_t k = 0; k < kx; ++k) {
         const int64_t sx = px[k + 1] - px[k];
+        if (sx == 0)
+            continue;
+        counted += 1;
         for (int64_t q = px[k]; q < px[k + 1]; ++q) {
             const int32_t v = mx[q];
             for (int64_t t = node_ptr[v]; t < node_ptr[v + 1]; ++t)
@@ -1076,6 +1083,8 @@ static double lcdo_nmi_half(int32_t n, int32_t kx, const int64_t *px, const int3
         int found = 0;
         for (int32_t l = 0; l < ky; ++l) {
             const int64_t sy = py[l + 1] - py[l];
+            if (sy == 0)
+                continue;
             const int64_t a = cnt[l];
             const int64_t b = sx - a, c = sy - a, e = n - a - b - c;
             const double ha = lcdo_h(a, n), hb = lcdo_h(b, n), hc = lcdo_h(c, n), he = lcdo_h(e, n);
@@ -1097,7 +1106,15 @@ static double lcdo_nmi_half(int32_t n, int32_t kx, const int64_t *px, const int3
     free(cnt);
     free(node_sets);
     free(fill);
-    return kx > 0 ? sum / (double)kx : 0.0;
+    return counted > 0 ? sum / (double)counted : 0.0;
+}
+
+static int32_t lcdo_nonempty(int32_t k, const int64_t *p)
+{
+    int32_t c = 0;
+    for (int32_t j = 0; j < k; ++j)
+        c += p[j + 1] > p[j];
+    return c;
 }
 
 /* NMI of covers X and Y of n nodes (N1-N4 above); returns -2 on allocation
@@ -1105,8 +1122,9 @@ static double lcdo_nmi_half(int32_t n, int32_t kx, const int64_t *px, const int3
 double lcdo_nmi(int32_t n, int32_t kx, const int64_t *px, const int32_t *mx, int32_t ky, const int64_t *py,
                 const int32_t *my)
 {
-    if (kx == 0 || ky == 0)
-        return (kx == 0 && ky == 0) ? 1.0 : 0.0;
+    const int32_t ex = lcdo_nonempty(kx, px), ey = lcdo_nonempty(ky, py);
+    if (ex == 0 || ey == 0)
+        return (ex == 0 && ey == 0) ? 1.0 : 0.0;
     const double hxy = lcdo_nmi_half(n, kx, px, mx, ky, py, my);
     const double hyx = lcdo_nmi_half(n, ky, py, my, kx, px, mx);
     if (hxy < 0.0 || hyx < 0.0)

@@ -141,6 +141,18 @@ def test_matches_brute_force(oracle_mod, seed):
 def test_empty_covers(oracle_mod):
     assert oracle_mod.nmi(10, [], []) == 1.0
     assert oracle_mod.nmi(10, [np.array([1, 2], np.int32)], []) == 0.0
+    empty = np.zeros(0, np.int32)
+    assert oracle_mod.nmi(10, [empty], [empty, empty]) == 1.0
+
+
+def test_empty_communities_are_skipped(oracle_mod):
+    rng = np.random.default_rng(11)
+    n = 50
+    X = _random_cover(rng, n, 4)
+    Y = _random_cover(rng, n, 3)
+    empty = np.zeros(0, np.int32)
+    v = oracle_mod.nmi(n, X, Y)
+    assert oracle_mod.nmi(n, X[:2] + [empty] + X[2:], [empty] + Y + [empty]) == v
 
 
 def test_successive_average(oracle_mod):
