@@ -1,11 +1,17 @@
 #!/usr/bin/env python3
 """Benchmark of the multi-scale local community sweep on one MI355X.
 
-One step = one lcd_sweep() call: every seed set of the workload grown
-through every scale (queue-emulated additions, removal passes, fixpoint per
-scale, chained scales), with sorted member lists, K, V, f and the work
-counters written for every (seed set, scale).  Inputs (graph, seeds,
-scales) are resident on the device before the timed region.
+One step = one sweep (lcd_result_rerun of an lcd_sweep result): every seed
+set of the workload grown through every scale (queue-emulated additions,
+removal passes, fixpoint per scale, chained scales), with sorted member
+lists, K, V, f and the work counters written for every (seed set, scale).
+Inputs (graph, seeds, scales) are resident on the device before the timed
+region.
+
+The headline workload is the 10M-node graph of the largest configuration
+with one GPU's share of its rule-1 seed sets (every --xl-stride-th set in
+selection order: the sweep shards over seed sets with no exchange, so a
+share at the full graph shape is what one GPU of a multi-GPU run does).
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -32,7 +38,8 @@ if int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0) < 12:
 METRIC = ("candidate-node gains/s + full multi-scale sweep time; "
           "p50/p99 seed-query latency")
 HBM_PEAK_GBS = 8000.0
-RECORD_BYTES = 8 + 4 + 8 + 8 + 8 + 32   # off, cnt, K, V, f, four counters
+SUMMARY_BYTES = 24        # per (set, scale): K, V, f (the survey's algorithmic output unit)
+XL_STRIDE = 64            # default seed share of the 10M-node workload
 KERNEL_OF_KIND = {0: "sweep_lds_kernel", 1: "sweep_global_kernel", 2: "sweep_team_lds_kernel",
                   3: "sweep_team_global_kernel"}
 
@@ -54,51 +61,109 @@ def workload(name: str):
         g, sp, sn, sc = W.workload_large()
         desc = ("lfr3-1M: 1,000,000-node 3-level LFR-style graph (mean degree 15, max 200, mixing 0.25, "
                 "weights 1..16), rule-1 seeds, 64 scales on [0.5,1]")
+    elif name.startswith("xl"):
+        stride = int(name[2:] or XL_STRIDE)
+        g, sp_all, sn_all, sc = W.workload_xl()
+        sp, sn, _ = W.subsample_sets(sp_all, sn_all, stride)
+        m = g.meta
+        desc = ("lfr3-10M: 10,000,000-node 3-level power-law graph (degree exponent 2.2, mean 20, max 5,000; "
+                "achieved mean %.1f, max %d, %d directed entries; communities 20..5,000 nodes; mixing 0.3 "
+                "(achieved %.3f); weights 1..16), every %dth of its %d rule-1 seed sets (%d sets: one GPU's "
+                "share), 32 scales on [0.5,1]"
+                % (m["achieved_mean_deg"], m["achieved_max_deg"], g.nnz, m["achieved_mu_comm"], stride,
+                   sp_all.size - 1, sp.size - 1))
     else:
         raise SystemExit("unknown workload %s" % name)
     return g, sp, sn, sc, desc
 
 
-def algorithmic_bytes(t: dict, weighted: bool, seed_nodes: int, n_records: int) -> int:
-    """HBM bytes the method itself must move for the work one tier finished:
-    per gathered CSR row its two offsets and its entries (id, plus weight),
-    one degree read per table entry created, the seed ids, and the output
-    (member ids and one record per (set, scale))."""
+def gather_bytes(t: dict, weighted: bool) -> int:
+    """Algorithmic input bytes of one tier (the survey's measurement rules):
+    per CSR row that a move or a seed-set member gathers, its two offsets and
+    its entries (id, plus weight); one degree read per table entry created
+    for a committed scale.  Rows that a set resumed from a record gathers
+    again, and work of a scale that overflowed and was redone in the next
+    tier, are not counted."""
     wb = 1 if weighted else 0
-    return (8 * t["rows_gathered"] + (4 + wb) * t["row_entries"] + 4 * t["entries_created"]
-            + 4 * seed_nodes + 4 * t["members_written"] + RECORD_BYTES * n_records)
+    rows = t["move_rows"] + t["seed_rows"]
+    ents = t["move_row_entries"] + t["seed_row_entries"]
+    return 8 * rows + (4 + wb) * ents + 4 * t["entries_committed"]
 
 
-def cpu_baseline(g, sp, sn, sc, stride, got_res):
-    """The oracle on every stride-th seed set, single thread, on this host."""
+def output_bytes(moves: int, seed_nodes: int, n_records: int) -> int:
+    """Algorithmic output: 4 B per member change between consecutive scales
+    (at most the seed set plus one per move) and a 24-byte summary (K, V, f)
+    per (set, scale)."""
+    return 4 * (moves + seed_nodes) + SUMMARY_BYTES * n_records
+
+
+_CPU_JOB = None   # (graph, seed_ptr, seed_nodes, scales) inherited by forked oracle workers
+
+
+def _oracle_chunk(ids):
+    """Oracle run of the seed sets `ids` (a worker of the CPU baseline)."""
     import oracle
-    from paper_1301_0955_amd import workloads as W
-    sp2, sn2, ids = W.subsample_sets(sp, sn, stride)
+    g, sp, sn, sc = _CPU_JOB
+    sizes = sp[ids + 1] - sp[ids]
+    ptr = np.zeros(ids.size + 1, np.int32)
+    np.cumsum(sizes, out=ptr[1:])
+    nodes = np.concatenate([sn[sp[i]:sp[i + 1]] for i in ids]) if ids.size else np.zeros(0, np.int32)
     o = oracle.Oracle.from_graph(g)
     t0 = time.perf_counter()
-    ref = o.run_sets(sp2, sn2, sc)
+    ref = o.run_sets(ptr, nodes, sc)
     dt = time.perf_counter() - t0
-    G = int(ref["ctr"][:, 0].sum())
-    parity = None
-    if got_res is not None:
-        S = sc.size
+    return ids, ref, dt
+
+
+class CpuBaseline:
+    """The oracle on a bounded sample of the benchmarked seed sets, sharded
+    over the host cores as independent processes (seed sets are independent
+    in the sweep).  The worker pool is forked before the process touches the
+    GPU; the runs start after the GPU's timed steps."""
+
+    def __init__(self, g, sp, sn, sc, n_sample: int, cores: int):
+        global _CPU_JOB
+        import multiprocessing as mp
+        ns = sp.size - 1
+        self.ids = np.unique(np.linspace(0, max(ns - 1, 0), min(n_sample, ns)).astype(np.int64))
+        self.cores = max(1, min(cores, self.ids.size))
+        self.ns, self.S = ns, sc.size
+        _CPU_JOB = (g, sp, sn, sc)
+        self.pool = mp.get_context("fork").Pool(self.cores)
+
+    def run(self, got_sets):
+        """got_sets(ids) -> the GPU's records of those sets (lcd sets_to_numpy
+        layout).  Returns the cpu_baseline object of the bench line."""
+        chunks = [self.ids[k::self.cores] for k in range(self.cores)]
+        t0 = time.perf_counter()
+        outs = self.pool.map(_oracle_chunk, chunks)
+        wall = time.perf_counter() - t0
+        self.pool.close()
+        self.pool.join()
+        G = sum(int(ref["ctr"][:, 0].sum()) for _, ref, _ in outs)
+        busy = sum(dt for _, _, dt in outs)
         ok = True
-        for j, q in enumerate(ids.tolist()):
-            for s in range(S):
-                r, rq = j * S + s, q * S + s
-                a = got_res["members"][got_res["off"][rq]:got_res["off"][rq] + got_res["cnt"][rq]]
-                b = ref["members"][ref["off"][r]:ref["off"][r] + ref["cnt"][r]]
-                if (not np.array_equal(a, b) or got_res["K"][rq] != ref["K"][r]
-                        or not np.array_equal(got_res["ctr"][rq], ref["ctr"][r])):
-                    ok = False
-                    break
-            if not ok:
-                break
-        parity = "bit-exact" if ok else "MISMATCH"
-    return dict(value=G / dt, unit="gains/s", cores=1, kind="oracle",
-                sample="every %dth seed set (%d of %d), all %d scales; %.1f s, %d gains"
-                       % (stride, ids.size, sp.size - 1, sc.size, dt, G),
-                seconds=dt, parity_on_sample=parity)
+        S = self.S
+        for ids, ref, _ in outs:
+            got = got_sets(ids.astype(np.int32))
+            for q in range(ids.size):
+                for s in range(S):
+                    r = q * S + s
+                    a = got["members"][got["off"][r]:got["off"][r] + got["cnt"][r]]
+                    b = ref["members"][ref["off"][r]:ref["off"][r] + ref["cnt"][r]]
+                    fa, fb = float(got["f"][r]), float(ref["f"][r])
+                    if (not np.array_equal(a, b) or got["K"][r] != ref["K"][r] or got["V"][r] != ref["V"][r]
+                            or abs(fa - fb) > 1e-12 * abs(fb)
+                            or not np.array_equal(np.asarray(got["ctr"][r], np.uint64),
+                                                  np.asarray(ref["ctr"][r], np.uint64))):
+                        ok = False
+        return dict(value=G / wall, unit="gains/s", cores=self.cores, kind="oracle",
+                    sample="%d of the %d benchmarked seed sets (evenly spaced), all %d scales, sharded over %d "
+                           "processes: %.1f s wall, %.1f core-s, %d gains"
+                           % (self.ids.size, self.ns, S, self.cores, wall, busy, G),
+                    seconds=round(wall, 3), core_seconds=round(busy, 3), gains=G,
+                    single_core_gains_per_s=G / busy if busy > 0 else None,
+                    parity_on_sample=("bit-exact members, K, V, counters; f within 1e-12" if ok else "MISMATCH"))
 
 
 def profiled_traffic(kernel: str, tier_caps, workload_name: str):
@@ -346,32 +411,88 @@ def sweep_compare(lcd, G, g, sp, sn, sc, steps, prm):
                 persistent_speedup=round(lst["ms_total"] / ms, 3), identical_results=bool(same))
 
 
+CPU_SETS_PER_CORE = {"small": 100, "medium": 300, "large": 40, "xl": 12}
+
+
+def medium_compare(lcd, steps):
+    """The 100k-node workload: autotuned persistent sweep vs the per-scale
+    launch loop (device time of each; identical counters and records)."""
+    from paper_1301_0955_amd import workloads as W
+    g, sp, sn, sc = W.workload_medium()
+    G = lcd.Graph.from_workload(g)
+    out = sweep_compare(lcd, G, g, sp, sn, sc, steps, {})
+    out["workload"] = ("lfr2-100k: 100,000-node 2-level LFR-style graph (degree exp 2.5, mean 20, max 100; "
+                       "community sizes exp 1.5 on [20,200]; mixing 0.3; unweighted), rule-1 seeds (%d), "
+                       "32 scales on [0.5,1]" % (sp.size - 1))
+    G.free()
+    return out
+
+
+def nmi_bench(lcd):
+    """Sec. 4's multi-scale relevance analysis on the device: the NMI of
+    successive community sets (averaged over 3 and 5 scales) and with the
+    planted levels, for the check-and-merge run of the planted-partition
+    graph, against the oracle's NMI of the oracle's own run."""
+    import oracle
+    from paper_1301_0955_amd import workloads as W
+    g, sp, sn, sc = W.workload_small()
+    G = lcd.Graph.from_workload(g)
+    res = lcd.lcd_sweep_merge(G, sc, sp, sn)
+    t0 = time.perf_counter()
+    w3 = res.nmi_successive(3)
+    w5 = res.nmi_successive(5)
+    subs = [np.arange(50 * k, 50 * k + 50, dtype=np.int32) for k in range(20)]
+    groups = [np.arange(250 * k, 250 * k + 250, dtype=np.int32) for k in range(4)]
+    vs_sub = [res.nmi_cover(s, subs) for s in range(sc.size)]
+    vs_grp = [res.nmi_cover(s, groups) for s in range(sc.size)]
+    dt = time.perf_counter() - t0
+    res.free()
+    G.free()
+    ref = oracle.Oracle.from_graph(g).run_merge(sp, sn, sc)
+    S = sc.size
+    covers = [[ref["members"][ref["off"][j * S + s]:ref["off"][j * S + s] + ref["cnt"][j * S + s]]
+               for j in range(sp.size - 1) if ref["cnt"][j * S + s] > 0] for s in range(S)]
+    err = max(float(np.max(np.abs(w3 - oracle.nmi_successive(g.n, covers, 3)))),
+              float(np.max(np.abs(w5 - oracle.nmi_successive(g.n, covers, 5)))),
+              max(abs(vs_sub[s] - oracle.nmi(g.n, covers[s], subs)) for s in range(S)),
+              max(abs(vs_grp[s] - oracle.nmi(g.n, covers[s], groups)) for s in range(S)))
+    return dict(workload="planted-partition-1k with the check-and-merge phase, 10 scales",
+                nmi_successive_3=[round(x, 6) for x in w3.tolist()],
+                nmi_successive_5=[round(x, 6) for x in w5.tolist()],
+                nmi_vs_planted_sub=[round(x, 6) for x in vs_sub], nmi_vs_planted_groups=[round(x, 6) for x in vs_grp],
+                seconds_device_calls=round(dt, 4), max_abs_diff_vs_oracle=err)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="medium", choices=["small", "medium", "large"])
+    ap.add_argument("--workload", default="xl",
+                    help="small | medium | large | xl[STRIDE] (the 10M-node graph with every STRIDE-th seed set, "
+                         "default %d)" % XL_STRIDE)
     ap.add_argument("--lds-capacity", type=int, default=0)
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
-    ap.add_argument("--cpu-stride", type=int, default=0,
-                    help="oracle sample stride (0 = sized for ~15 s)")
+    ap.add_argument("--cpu-sets", type=int, default=0, help="oracle sample size (0 = sized per workload)")
+    ap.add_argument("--cpu-cores", type=int, default=0, help="oracle processes (0 = min(16, host cores))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-loop-compare", action="store_true")
+    ap.add_argument("--tune", action="store_true", help="autotune the headline workload (default: xl not tuned)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (static sizing)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 4 times (a plain copy kernel of known "
                          "size, to scale HBM byte counters) and exit")
     ap.add_argument("--no-large", action="store_true", help="skip the 1M-node sweep comparison")
+    ap.add_argument("--no-medium", action="store_true", help="skip the 100k-node sweep comparison")
     ap.add_argument("--no-serve", action="store_true", help="skip the query-serving run")
     ap.add_argument("--no-merge", action="store_true", help="skip the check-and-merge runs")
-    ap.add_argument("--multigraph", action="store_true",
-                    help="also sweep 64 independent graphs (1k-200k nodes) in one batched launch")
+    ap.add_argument("--no-nmi", action="store_true", help="skip the NMI analysis leg")
+    ap.add_argument("--no-multigraph", action="store_true", help="skip the 64-graph batched sweep")
     ap.add_argument("--serve-qps", type=float, default=2000.0)
-    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--serve-warmup", type=float, default=2.0)
-    ap.add_argument("--serve-oracle", type=int, default=300,
+    ap.add_argument("--serve-oracle", type=int, default=1000,
                     help="queries the oracle re-runs for CPU latency and parity")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -380,12 +501,9 @@ def main():
               "(asked for --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(2)
-    torch.cuda.set_device(0)
     if args.calibrate_copy:
+        import torch
+        torch.cuda.set_device(0)
         n = args.calibrate_copy << 18            # int32 elements
         src = torch.ones(n, dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)
@@ -395,20 +513,40 @@ def main():
         torch.cuda.synchronize()
         log("copied %d MiB x 4" % args.calibrate_copy)
         return
+
+    # inputs (host), and the oracle's worker processes, before anything
+    # touches the GPU
+    t0 = time.perf_counter()
+    g, sp, sn, sc, desc = workload(args.workload)
+    wl_key = "xl" if args.workload.startswith("xl") else args.workload
+    g_n, g_nnz = int(g.n), int(g.nnz)
+    log("workload %s ready in %.1f s: n=%d nnz=%d sets=%d scales=%d"
+        % (args.workload, time.perf_counter() - t0, g.n, g.nnz, sp.size - 1, sc.size))
+    cpu_job = None
+    if not args.no_cpu_baseline:
+        cores = args.cpu_cores or min(16, os.cpu_count() or 1)
+        n_sample = args.cpu_sets or CPU_SETS_PER_CORE[wl_key] * cores
+        cpu_job = CpuBaseline(g, sp, sn, sc, n_sample, cores)
+        log("cpu baseline: %d oracle processes forked for %d seed sets" % (cpu_job.cores, cpu_job.ids.size))
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
     from paper_1301_0955_amd import lcd
 
     t0 = time.perf_counter()
-    g, sp, sn, sc, desc = workload(args.workload)
-    log("workload %s ready in %.1f s: n=%d nnz=%d sets=%d scales=%d"
-        % (args.workload, time.perf_counter() - t0, g.n, g.nnz, sp.size - 1, sc.size))
     G = lcd.Graph.from_workload(g)
+    log("graph uploaded in %.1f s" % (time.perf_counter() - t0))
     d_sc = torch.as_tensor(sc, dtype=torch.float64, device="cuda")
     d_sp = torch.as_tensor(sp, dtype=torch.int32, device="cuda")
     d_sn = torch.as_tensor(sn, dtype=torch.int32, device="cuda")
     prm = dict(lds_capacity=args.lds_capacity, waves_per_block=args.waves_per_block,
                blocks_per_cu=args.blocks_per_cu)
     tuned = None
-    if not any(prm.values()) and not args.no_tune:
+    do_tune = not any(prm.values()) and not args.no_tune and (wl_key != "xl" or args.tune)
+    if do_tune:
         t0 = time.perf_counter()
         tuned = lcd.lcd_tune(G, sc, sp, sn)
         log("autotuned in %.1f s: %s (sample of every %d-th set)"
@@ -416,8 +554,11 @@ def main():
     torch.cuda.synchronize()
 
     # one result object; every step re-runs the whole sweep into it (inputs
-    # and outputs stay on the device; the first call allocates)
+    # and outputs stay on the device; the first call allocates and sizes the
+    # member pool)
+    t0 = time.perf_counter()
     res = lcd.lcd_sweep(G, d_sc, d_sp, d_sn, **prm)
+    log("first call %.1f s (reruns for pool growth: %d)" % (time.perf_counter() - t0, res.stats()["reruns"]))
     for i in range(args.warmup):
         st = res.rerun().stats()
         log("warmup %d: device %.2f ms, tiers %s ms, spilled %d, reruns %d"
@@ -428,31 +569,24 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         stats.append(res.rerun().stats())
+        log("step %d: device %.2f ms" % (i, stats[-1]["ms_total"]))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = 1e3 * wall / max(args.steps, 1)
     totals = res.counters()
     log("timed %d steps: %.2f ms/step wall" % (args.steps, ms_step))
-    got = lcd.sweep_to_numpy(res)
-    res.free()
 
-    # the same sweep captured in a hipGraph and replayed
+    # the same sweep captured in a hipGraph and replayed (two replays)
     rg = lcd.lcd_sweep(G, d_sc, d_sp, d_sn, use_graph=1, **prm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(2):
         rg.rerun()
     torch.cuda.synchronize()
-    graph_ms = 1e3 * (time.perf_counter() - t0) / max(args.steps, 1)
+    graph_ms = 1e3 * (time.perf_counter() - t0) / 2
     graph_same = bool(np.array_equal(rg.counters(), totals))
     rg.free()
-    # a fresh call each step (allocation, seed upload, launch, statistics)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(2):
-        lcd.lcd_sweep(G, d_sc, d_sp, d_sn, **prm).free()
-    fresh_ms = 1e3 * (time.perf_counter() - t0) / 2
-    log("hipGraph replay %.2f ms/step, fresh call %.2f ms" % (graph_ms, fresh_ms))
+    log("hipGraph replay %.2f ms/step" % graph_ms)
 
     gains = totals[0]
     ms_dev = float(np.mean([s["ms_total"] for s in stats]))
@@ -463,31 +597,44 @@ def main():
     ms_tier = [float(np.mean([s["ms_tier"][k] for s in stats])) for k in range(nt)]
     k_dom = int(np.argmax(ms_tier))
     t_dom = st0["tier"][k_dom]
-    kbytes = algorithmic_bytes(t_dom, weighted, int(sn.size) if k_dom == 0 else 0,
-                               t_dom["sets_finished"] * S)
+    kbytes = gather_bytes(t_dom, weighted)
     kname = KERNEL_OF_KIND[st0["tier_kind"][k_dom]]
     kms = ms_tier[k_dom]
     achieved = kbytes / (kms * 1e-3) / 1e9
-    traffic = profiled_traffic(kname, st0["tier_capacity"][:nt], args.workload)
+    n_rec = (sp.size - 1) * S
+    all_bytes = (sum(gather_bytes(st0["tier"][k], weighted) for k in range(nt))
+                 + output_bytes(int(totals[2]), int(sn.size), n_rec))
+    scanned = [int(st0["tier"][k]["entries_scanned"]) for k in range(nt)]
+    traffic = profiled_traffic(kname, st0["tier_capacity"][:nt], wl_key)
     roofline = dict(bound="hbm", kernel=kname, tier=k_dom, achieved=round(achieved, 3), peak=HBM_PEAK_GBS,
                     unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 7), traffic=traffic,
                     traffic_GBs=None if traffic is None else round(traffic / (kms * 1e-3) / 1e9, 2),
                     algorithmic_bytes=int(kbytes), kernel_ms=round(kms, 4),
-                    secondary=profiled_utilisation(kname, args.workload),
+                    bytes_rule="per CSR row gathered by a move or a seed member: 8 B offsets + (4 + 1 if "
+                               "weighted) B per entry; 4 B per table entry created; rows regathered by resumed "
+                               "sets and work of overflowed scales excluded; the kernel's own output not "
+                               "attributed (it is in all_tiers)",
+                    all_tiers=dict(algorithmic_bytes=int(all_bytes), ms=round(ms_dev, 4),
+                                   achieved=round(all_bytes / (ms_dev * 1e-3) / 1e9, 3),
+                                   frac=round(all_bytes / (ms_dev * 1e-3) / 1e9 / HBM_PEAK_GBS, 7),
+                                   output_rule="4 B per member change between scales (at most seeds + moves) "
+                                               "+ 24 B (K, V, f) per (set, scale)"),
+                    scanned_entries=scanned, scanned_over_gains=round(sum(scanned) / max(gains, 1), 3),
+                    secondary=profiled_utilisation(kname, wl_key),
                     tiers=[dict(kernel=KERNEL_OF_KIND[st0["tier_kind"][k]],
                                 table_entries=st0["tier_capacity"][k], ms=round(ms_tier[k], 3),
                                 sets_finished=st0["tier"][k]["sets_finished"],
-                                algorithmic_bytes=int(algorithmic_bytes(
-                                    st0["tier"][k], weighted, int(sn.size) if k == 0 else 0,
-                                    st0["tier"][k]["sets_finished"] * S)))
+                                entries_scanned=scanned[k],
+                                algorithmic_bytes=int(gather_bytes(st0["tier"][k], weighted)))
                            for k in range(nt)])
 
     loop = None
-    if not args.no_loop_compare:
+    if not args.no_loop_compare and wl_key != "xl":
         r = lcd.lcd_sweep(G, d_sc, d_sp, d_sn, mode=lcd.LCD_PER_SCALE_LOOP, **prm)
         lst = r.stats()
         same = lcd.sweep_to_numpy(r)
         r.free()
+        got = lcd.sweep_to_numpy(res)
         identical = (np.array_equal(same["K"], got["K"]) and np.array_equal(same["ctr"], got["ctr"])
                      and np.array_equal(same["cnt"], got["cnt"]))
         loop = dict(device_ms=round(lst["ms_total"], 3), launches=lst["launches"],
@@ -496,33 +643,51 @@ def main():
         log("per-scale loop: %.2f ms device (%d launches)" % (lst["ms_total"], lst["launches"]))
 
     cpu = None
-    if not args.no_cpu_baseline:
-        stride = args.cpu_stride or {"small": 1, "medium": 16, "large": 1024}[args.workload]
-        log("cpu baseline: oracle on every %dth seed set" % stride)
-        cpu = cpu_baseline(g, sp, sn, sc, stride, got)
-        log("cpu baseline: %s" % cpu["sample"])
+    if cpu_job is not None:
+        log("cpu baseline: oracle on %d seed sets over %d processes" % (cpu_job.ids.size, cpu_job.cores))
+        cpu = cpu_job.run(lambda ids: res.sets_to_numpy(ids))
+        log("cpu baseline: %s; parity %s" % (cpu["sample"], cpu["parity_on_sample"]))
+    res.free()
 
     # seed selection (initialisation of Algorithm 2) on the device vs the oracle
     seeds_info = {}
-    perm = W_seed_perm(g)
-    for rule in (1, 2):
-        t0 = time.perf_counter()
-        dev = lcd.lcd_seeds(G, perm, rule)
-        t_dev = time.perf_counter() - t0
-        entry = dict(seeds=int(dev.size), ms_device_call=round(t_dev * 1e3, 3))
-        if not args.no_cpu_baseline:
-            import oracle
+    if wl_key != "xl":
+        perm = W_seed_perm(g)
+        for rule in (1, 2):
             t0 = time.perf_counter()
-            ref = oracle.Oracle.from_graph(g).seeds(perm, rule)
-            entry["ms_oracle_1core"] = round((time.perf_counter() - t0) * 1e3, 3)
-            entry["identical"] = bool(np.array_equal(dev, ref))
-        seeds_info["rule%d" % rule] = entry
-    log("seed selection: %s" % seeds_info)
+            dev = lcd.lcd_seeds(G, perm, rule)
+            t_dev = time.perf_counter() - t0
+            entry = dict(seeds=int(dev.size), ms_device_call=round(t_dev * 1e3, 3))
+            if not args.no_cpu_baseline:
+                import oracle
+                t0 = time.perf_counter()
+                ref = oracle.Oracle.from_graph(g).seeds(perm, rule)
+                entry["ms_oracle_1core"] = round((time.perf_counter() - t0) * 1e3, 3)
+                entry["identical"] = bool(np.array_equal(dev, ref))
+            seeds_info["rule%d" % rule] = entry
+        log("seed selection: %s" % seeds_info)
+    G.free()
+    del g
 
-    merge = None if args.no_merge else merge_bench(lcd, G, g, sp, sn, sc, not args.no_cpu_baseline)
+    medium = None if (args.no_medium or wl_key == "medium") else medium_compare(lcd, 2)
+    if medium:
+        log("lfr2-100k sweep: %.1f ms device, per-scale loop %.1f ms"
+            % (medium["sweep_ms_device"], medium["per_scale_loop_ms_device"]))
+
+    merge = None
+    if not args.no_merge:
+        from paper_1301_0955_amd import workloads as W
+        gm, spm, snm, scm = W.workload_medium()
+        GM = lcd.Graph.from_workload(gm)
+        merge = merge_bench(lcd, GM, gm, spm, snm, scm, not args.no_cpu_baseline)
+        GM.free()
+    nmi = None if args.no_nmi else nmi_bench(lcd)
+    if nmi:
+        log("nmi: successive(3) %s; device vs oracle max diff %.2e" % (nmi["nmi_successive_3"],
+                                                                      nmi["max_abs_diff_vs_oracle"]))
 
     large = serving = None
-    if not (args.no_large and args.no_serve) and args.workload != "large":
+    if not (args.no_large and args.no_serve) and wl_key != "large":
         t0 = time.perf_counter()
         from paper_1301_0955_amd import workloads as W
         gl, spl, snl, scl = W.workload_large()
@@ -545,7 +710,7 @@ def main():
         GL.free()
 
     multi = None
-    if args.multigraph:
+    if not args.no_multigraph:
         from paper_1301_0955_amd import workloads as W
         t0 = time.perf_counter()
         gs, msp, msn, msg, msc = W.workload_multigraph()
@@ -556,7 +721,7 @@ def main():
         tot = r.counters()
         r.free()
         walls = []
-        for _ in range(3):
+        for _ in range(2):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             r = lcd.lcd_sweep_batch(GB, msc, msp, msn, msg)
@@ -585,28 +750,33 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "n": g.n, "nnz": g.nnz, "seed_sets": int(sp.size - 1),
-                   "scales": int(S), "graph_sha256": g.sha256()[:16],
-                   "lds_capacity": st0["lds_capacity"], "waves_per_block": st0["waves_per_block"],
-                   "grid_blocks": st0["grid_blocks"], "tiers": nt,
-                   "tuned": tuned["best"] if tuned else None},
+        "config": None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    out["config"] = {"workload": desc, "n": g_n, "nnz": g_nnz, "seed_sets": int(sp.size - 1), "scales": int(S),
+                     "lds_capacity": st0["lds_capacity"], "waves_per_block": st0["waves_per_block"],
+                     "grid_blocks": st0["grid_blocks"], "tiers": nt,
+                     "tier_capacity": st0["tier_capacity"][:nt],
+                     "tuned": tuned["best"] if tuned else None}
+    out.update({
+        "sweep_ms_device": round(ms_dev, 4),
         "hipgraph_ms_per_step": round(graph_ms, 4),
         "hipgraph_identical_counters": graph_same,
-        "fresh_call_ms": round(fresh_ms, 3),
-        "sweep_ms_device": round(ms_dev, 4),
         "gains_per_step": int(gains),
         "counters": {"G": totals[0], "R": totals[1], "M": totals[2], "C": totals[3]},
         "gains_per_s_device": gains / (ms_dev * 1e-3),
         "spilled_sets": st0["n_spilled"],
-        "roofline": roofline,
+        "pool_entries": st0["pool_used"],
         "per_scale_loop": loop,
-        "cpu_baseline": cpu,
         "seed_selection": seeds_info,
-        "merge": merge,
+        "medium_sweep": medium,
         "large_sweep": large,
+        "merge": merge,
+        "nmi": nmi,
         "serving": serving,
         "multigraph": multi,
-    }
+    })
     print(json.dumps(out), flush=True)
 
 

@@ -102,6 +102,11 @@ typedef struct {
     int32_t grow_calls;      /* growth calls per (seed set, scale): 0 = until a call
                                 changes nothing (the default); n > 0 stops after
                                 n calls (lcd_sweep_merge makes one per round) */
+    int32_t queue_min_entries; /* workgroup tiers on global tables: a growth call whose
+                                table holds at least this many entries keeps its queue
+                                bucketed by rank (a step looks at the queue's head, not
+                                the whole table); 0 = default (8,192); results never
+                                depend on it */
 } lcd_params;
 
 /* Work of one table tier (0 = one wave per community with an LDS table; the
@@ -113,6 +118,18 @@ typedef struct {
     int64_t entries_created;  /* table entries created (one degree read each) */
     int64_t members_written;  /* member ids written to the output pool */
     int64_t sets_finished;    /* seed sets completed in this tier */
+    int64_t entries_scanned;  /* table entries the tier's growth scans visited (the
+                                 sequential algorithm's own visits are the counter G) */
+    /* Algorithmic work, over every set the tier ran (finished or passed on),
+     * for the scales whose records the tier wrote: a scale whose table
+     * overflowed is redone by the next tier and counted there. */
+    int64_t move_rows;        /* CSR rows gathered by additions and removals */
+    int64_t move_row_entries; /* ... their total length */
+    int64_t seed_rows;        /* rows of the seed-set members, in a set's first tier
+                                 (a set resumed from a record gathers again: overhead) */
+    int64_t seed_row_entries; /* ... their total length */
+    int64_t entries_committed;/* table entries created for those scales (one degree read
+                                 each; entries rebuilt when a set resumes excluded) */
 } lcd_tier_stats;
 
 /* Timing and bookkeeping of one sweep (filled by lcd_result_stats). */
@@ -377,6 +394,42 @@ lcd_status lcd_result_sets(const lcd_result *r, const int32_t *set_ids, int32_t 
                            uint64_t *ctr);
 
 lcd_status lcd_result_stats(const lcd_result *r, lcd_sweep_stats *out);
+
+/* ------------------------------------------------------------------------
+ * Multi-scale relevance analysis.  Paper: Sec. 4 compares the community sets
+ * of successive scales, and with the planted ones, by the normalised mutual
+ * information for overlapping communities of Lancichinetti, Fortunato and
+ * Kertesz (2009), averaged over p successive scales (p = 3 and 5 there).
+ * The paper cites the definition without printing it; restated: each
+ * community is a binary variable over the n nodes; H(X_k | Y_l) counts only
+ * when h(a) + h(e) > h(b) + h(c) for the intersection counts a, b, c, e;
+ * H(X_k | Y) is the least counting one (H(X_k) if none); NMI = 1 - (mean_k
+ * H(X_k|Y)/H(X_k) + mean_l H(Y_l|X)/H(Y_l)) / 2.  Entropies are in nats,
+ * h(c) = (c / n)(L(n) - L(c)) with the integer log L of the decisions, so
+ * the admission test decides the same way in every implementation of this
+ * specification.  Empty communities are skipped; a cover without a
+ * non-empty community gives 1 against another such cover, else 0.  Cost
+ * O(kx * ky + intersections).  All blocking; *out in host memory.
+ * ------------------------------------------------------------------------ */
+
+/* Two covers of n nodes as device CSR arrays: community j of X is
+ * mem_x[ptr_x[j] .. ptr_x[j+1]), strictly ascending ids in [0, n).
+ * LCD_EINVAL for a malformed cover. */
+lcd_status lcd_cover_nmi(int32_t n, int32_t kx, const int32_t *ptr_x, const int32_t *mem_x, int32_t ky,
+                         const int32_t *ptr_y, const int32_t *mem_y, double *out, void *stream);
+
+/* The community sets of scales s1 and s2 of a result (one community per
+ * record, empty records skipped). */
+lcd_status lcd_result_nmi(const lcd_result *r, int32_t s1, int32_t s2, double *out, void *stream);
+
+/* The NMI averaged over p successive scales: out[s] (s = 0 .. n_scales - p)
+ * is the mean of NMI(scale t, scale t + 1) for t = s .. s + p - 2. */
+lcd_status lcd_result_nmi_successive(const lcd_result *r, int32_t p, double *out, void *stream);
+
+/* One scale's community set against a given cover of the graph's nodes
+ * (device CSR as in lcd_cover_nmi), e.g. the planted communities. */
+lcd_status lcd_result_nmi_cover(const lcd_result *r, int32_t scale_idx, int32_t k, const int32_t *ptr,
+                                const int32_t *mem, double *out, void *stream);
 
 /*
  * Run the same sweep again (same graph, scales and seed sets, still on the

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "lcd.h"
@@ -59,7 +60,7 @@ lcd_status device_info(DevInfo &d) {
 
 lcd_status ensure_slab(Slab &sl, int32_t cap, int32_t slots, hipStream_t st) {
     const int32_t hbits = next_pow2_bits(2 * (int64_t)cap);
-    const int64_t stride = (table_bytes(cap, hbits) + 255) / 256 * 256;
+    const int64_t stride = slab_stride(cap);
     if (sl.buf && sl.cap == cap && sl.slots == slots && !sl.dirty)
         return LCD_OK;
     if (!(sl.buf && sl.cap == cap && sl.slots == slots)) {
@@ -144,7 +145,11 @@ lcd_status plan_tiers(const DevInfo &dev, int32_t n, const lcd_params &p, TierPl
                                 resident(TIER_TEAM_LDS, team_waves, (size_t)table_bytes(cl, hb)), 0, -1};
         have = cl;
     }
-    const int32_t c2 = std::min<int32_t>(16384, capn);
+    // graphs of millions of nodes grow communities of thousands of members
+    // whose tables hold tens of thousands of entries: there the first global
+    // tier takes 131,072 entries, so that such sets run one per resident
+    // workgroup instead of waiting for the few whole-graph tables
+    const int32_t c2 = std::min<int32_t>(n >= (4 << 20) ? 131072 : 16384, capn);
     if (c2 > have && n > have)
         add_global(TIER_TEAM_GLOBAL, c2, team_waves, resident(TIER_TEAM_GLOBAL, team_waves, 0), 0);
     if (capn > have && n > have) {
@@ -276,6 +281,7 @@ lcd_status run_group(lcd_result *r, const TierPlan &tp, int32_t s_begin, int32_t
     a.n_sets = r->n_sets;
     a.k_prune = r->prm.k_prune;
     a.max_calls = r->prm.grow_calls > 0 ? (uint32_t)r->prm.grow_calls : 0u;
+    a.queue_min = queue_min_of(r->prm);
     a.resume = s_begin > 0 ? 1 : 0;
     a.rec = r->rec;
     a.pool = r->pool;
@@ -445,11 +451,18 @@ lcd_status run_sweep(lcd_result *r, hipStream_t st) {
         r->stats.n_spilled_big = spb;
         r->stats.pool_used = (int64_t)cur[0];
         for (int t = 0; t < kMaxTiers; ++t) {
-            r->stats.tier[t].rows_gathered = (int64_t)cur[2 + 5 * t];
-            r->stats.tier[t].row_entries = (int64_t)cur[3 + 5 * t];
-            r->stats.tier[t].entries_created = (int64_t)cur[4 + 5 * t];
-            r->stats.tier[t].members_written = (int64_t)cur[5 + 5 * t];
-            r->stats.tier[t].sets_finished = (int64_t)cur[6 + 5 * t];
+            const unsigned long long *x = cur + 2 + kStatWords * t;
+            r->stats.tier[t].rows_gathered = (int64_t)x[0];
+            r->stats.tier[t].row_entries = (int64_t)x[1];
+            r->stats.tier[t].entries_created = (int64_t)x[2];
+            r->stats.tier[t].members_written = (int64_t)x[3];
+            r->stats.tier[t].sets_finished = (int64_t)x[4];
+            r->stats.tier[t].entries_scanned = (int64_t)x[5];
+            r->stats.tier[t].move_rows = (int64_t)x[6];
+            r->stats.tier[t].move_row_entries = (int64_t)x[7];
+            r->stats.tier[t].seed_rows = (int64_t)x[8];
+            r->stats.tier[t].seed_row_entries = (int64_t)x[9];
+            r->stats.tier[t].entries_committed = (int64_t)x[10];
         }
         if ((int64_t)cur[0] <= r->pool_cap)
             break;
@@ -542,35 +555,80 @@ lcd_status build_graph(int32_t n, int64_t nnz, const std::vector<int32_t> &rp,
     // --- validation ---
     if (rp[0] != 0 || rp[n] != nnz)
         return fail(LCD_EINVAL, "row_ptr must start at 0 and end at nnz");
-    int64_t maxk = 0, vol = 0;
-    for (int32_t u = 0; u < n; ++u) {
-        const int32_t b = rp[u], e = rp[u + 1];
-        if (e < b)
+    for (int32_t u = 0; u < n; ++u)
+        if (rp[u + 1] < rp[u])
             return fail(LCD_EINVAL, "row_ptr decreases at node %d", u);
-        int64_t k = 0;
-        for (int32_t j = b; j < e; ++j) {
-            const int32_t v = cl[j];
-            if (v < 0 || v >= n)
-                return fail(LCD_EINVAL, "neighbour id %d of node %d out of range", v, u);
-            if (v == u)
-                return fail(LCD_EINVAL, "self-loop at node %d", u);
-            if (j > b && cl[j - 1] >= v)
-                return fail(LCD_EINVAL, "row %d is not strictly ascending", u);
-            const int wt = w ? (int)ww[j] : 1;
-            if (wt < 1)
-                return fail(LCD_EINVAL, "zero weight on edge %d-%d", u, v);
-            // symmetry: u must appear in row v with the same weight
-            const int32_t *rb = cl.data() + rp[v];
-            const int32_t *re = cl.data() + rp[v + 1];
-            const int32_t *it = std::lower_bound(rb, re, u);
-            if (it == re || *it != u)
-                return fail(LCD_EINVAL, "edge %d-%d has no reverse entry", u, v);
-            if (w && ww[it - cl.data()] != ww[j])
-                return fail(LCD_EINVAL, "edge %d-%d has unequal weights", u, v);
-            k += wt;
+    // rows are checked in parallel blocks; the first failing row of the
+    // lowest block is reported
+    struct RowCheck {
+        int32_t row = -1;
+        int code = 0;
+        int32_t v = 0;
+        int64_t maxk = 0, vol = 0;
+    };
+    auto check_rows = [&](int32_t u0, int32_t u1, RowCheck &rc) {
+        for (int32_t u = u0; u < u1; ++u) {
+            const int32_t b = rp[u], e = rp[u + 1];
+            int64_t k = 0;
+            for (int32_t j = b; j < e; ++j) {
+                const int32_t v = cl[j];
+                int code = 0;
+                if (v < 0 || v >= n)
+                    code = 1;
+                else if (v == u)
+                    code = 2;
+                else if (j > b && cl[j - 1] >= v)
+                    code = 3;
+                else if ((w ? (int)ww[j] : 1) < 1)
+                    code = 4;
+                else {
+                    // symmetry: u must appear in row v with the same weight
+                    const int32_t *rb = cl.data() + rp[v];
+                    const int32_t *re = cl.data() + rp[v + 1];
+                    const int32_t *it = std::lower_bound(rb, re, u);
+                    if (it == re || *it != u)
+                        code = 5;
+                    else if (w && ww[it - cl.data()] != ww[j])
+                        code = 6;
+                }
+                if (code) {
+                    rc.row = u;
+                    rc.code = code;
+                    rc.v = v;
+                    return;
+                }
+                k += w ? (int)ww[j] : 1;
+            }
+            rc.maxk = std::max(rc.maxk, k);
+            rc.vol += k;
         }
-        maxk = std::max(maxk, k);
-        vol += k;
+    };
+    const int32_t nthr = (int32_t)std::max<int64_t>(1, std::min<int64_t>(16, (int64_t)n / 65536));
+    std::vector<RowCheck> rcs((size_t)nthr);
+    {
+        std::vector<std::thread> th;
+        for (int32_t t = 0; t < nthr; ++t) {
+            const int32_t u0 = (int32_t)((int64_t)n * t / nthr), u1 = (int32_t)((int64_t)n * (t + 1) / nthr);
+            th.emplace_back(check_rows, u0, u1, std::ref(rcs[(size_t)t]));
+        }
+        for (auto &x : th)
+            x.join();
+    }
+    int64_t maxk = 0, vol = 0;
+    for (const RowCheck &rc : rcs) {
+        if (rc.code) {
+            const int32_t u = rc.row, v = rc.v;
+            switch (rc.code) {
+            case 1: return fail(LCD_EINVAL, "neighbour id %d of node %d out of range", v, u);
+            case 2: return fail(LCD_EINVAL, "self-loop at node %d", u);
+            case 3: return fail(LCD_EINVAL, "row %d is not strictly ascending", u);
+            case 4: return fail(LCD_EINVAL, "zero weight on edge %d-%d", u, v);
+            case 5: return fail(LCD_EINVAL, "edge %d-%d has no reverse entry", u, v);
+            default: return fail(LCD_EINVAL, "edge %d-%d has unequal weights", u, v);
+            }
+        }
+        maxk = std::max(maxk, rc.maxk);
+        vol += rc.vol;
     }
     if (maxk >= ((int64_t)1 << 27))
         return fail(LCD_EINVAL, "weighted degree %lld exceeds 2^27", (long long)maxk);
@@ -1765,6 +1823,253 @@ lcd_status lcd_result_sets(const lcd_result *r, const int32_t *set_ids, int32_t 
         return fail(LCD_ECAPACITY, "members buffer holds %lld entries, %lld needed",
                     (long long)members_cap, (long long)pos);
     return LCD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// NMI of two well-formed covers given as device CSR arrays (int32 offsets,
+// tx and ty members); the value goes to the device double d_out.
+lcd_status cover_nmi_dev(int32_t n, int32_t cus, int32_t kx, const int32_t *px, const int32_t *mx, int64_t tx,
+                         int32_t ky, const int32_t *py, const int32_t *my, int64_t ty, double *d_out, hipStream_t st) {
+    double *h = nullptr, *term = nullptr, *res = nullptr;
+    int32_t *np_x = nullptr, *ns_x = nullptr, *np_y = nullptr, *ns_y = nullptr, *cnt = nullptr, *bs = nullptr,
+            *cnt_all = nullptr;
+    unsigned *next = nullptr;
+    const int32_t kmax = std::max(std::max(kx, ky), 1);
+    const int nb = (int)(((int64_t)n + 1 + 1023) / 1024) + 1;
+    const int32_t slots = (int32_t)std::max<int64_t>(
+        1, std::min<int64_t>(4 * (int64_t)cus, ((int64_t)1 << 30) / (4 * (int64_t)kmax)));
+    auto release = [&]() {
+        dev_free(h);
+        dev_free(term);
+        dev_free(res);
+        dev_free(np_x);
+        dev_free(ns_x);
+        dev_free(np_y);
+        dev_free(ns_y);
+        dev_free(cnt);
+        dev_free(bs);
+        dev_free(cnt_all);
+        dev_free(next);
+    };
+    lcd_status s;
+    if ((s = dev_alloc(&h, (size_t)n + 1)) != LCD_OK || (s = dev_alloc(&term, (size_t)kmax)) != LCD_OK ||
+        (s = dev_alloc(&res, 4)) != LCD_OK || (s = dev_alloc(&np_x, (size_t)n + 1)) != LCD_OK ||
+        (s = dev_alloc(&ns_x, (size_t)std::max<int64_t>(tx, 1))) != LCD_OK ||
+        (s = dev_alloc(&np_y, (size_t)n + 1)) != LCD_OK ||
+        (s = dev_alloc(&ns_y, (size_t)std::max<int64_t>(ty, 1))) != LCD_OK ||
+        (s = dev_alloc(&cnt, (size_t)n + 1)) != LCD_OK || (s = dev_alloc(&bs, (size_t)nb + 1)) != LCD_OK ||
+        (s = dev_alloc(&cnt_all, (size_t)slots * (size_t)kmax)) != LCD_OK || (s = dev_alloc(&next, 1)) != LCD_OK) {
+        release();
+        return s;
+    }
+    hipError_t e = launch_nmi_htab(h, n, st);
+    if (e == hipSuccess)
+        e = launch_overlap(py, my, ty, ky, n, np_y, ns_y, cnt, bs, st);
+    if (e == hipSuccess)
+        e = launch_overlap(px, mx, tx, kx, n, np_x, ns_x, cnt, bs, st);
+    if (e == hipSuccess)
+        e = launch_zero_bytes(cnt_all, 4 * (int64_t)slots * kmax, st);
+    if (e == hipSuccess)
+        e = launch_nmi_half(px, mx, kx, py, ky, np_y, ns_y, h, n, cnt_all, slots, next, term, res, st);
+    if (e == hipSuccess)
+        e = launch_nmi_half(py, my, ky, px, kx, np_x, ns_x, h, n, cnt_all, slots, next, term, res + 2, st);
+    if (e == hipSuccess)
+        e = launch_nmi_final(res, res + 2, d_out, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    release();
+    if (e != hipSuccess)
+        return fail(LCD_EDEVICE, "nmi: %s", hipGetErrorString(e));
+    return LCD_OK;
+}
+
+// One scale of a result as a device cover (offsets and members, owned by
+// the caller of this helper).
+lcd_status scale_cover(const lcd_result *r, int32_t s, hipStream_t st, int32_t **ptr, int32_t **mem, int64_t *tot) {
+    *ptr = nullptr;
+    *mem = nullptr;
+    CHK(dev_alloc(ptr, (size_t)r->n_sets + 1));
+    lcd_status x = scale_offsets(r, s, *ptr, st, tot);
+    if (x == LCD_OK)
+        x = check_int32_total(*tot, s);
+    if (x == LCD_OK)
+        x = dev_alloc(mem, (size_t)std::max<int64_t>(*tot, 1));
+    if (x == LCD_OK) {
+        const hipError_t e = launch_scale_gather(r->rec, r->pool, r->scales, r->S, s, r->n_sets, *ptr, *mem,
+                                                 nullptr, nullptr, nullptr, st);
+        if (e != hipSuccess)
+            x = fail(LCD_EDEVICE, "scale cover: %s", hipGetErrorString(e));
+    }
+    if (x != LCD_OK) {
+        dev_free(*ptr);
+        dev_free(*mem);
+    }
+    return x;
+}
+
+}  // namespace
+
+extern "C" {
+
+lcd_status lcd_cover_nmi(int32_t n, int32_t kx, const int32_t *ptr_x, const int32_t *mem_x, int32_t ky,
+                         const int32_t *ptr_y, const int32_t *mem_y, double *out, void *stream) {
+    if (!out || n < 1 || kx < 0 || ky < 0 || !ptr_x || !ptr_y)
+        return fail(LCD_EINVAL, "bad arguments (n >= 1, counts >= 0, offsets and out not null)");
+    hipStream_t st = (hipStream_t)stream;
+    int32_t tt[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(&tt[0], ptr_x + kx, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&tt[1], ptr_y + ky, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if ((tt[0] > 0 && !mem_x) || (tt[1] > 0 && !mem_y))
+        return fail(LCD_EINVAL, "null members array");
+    DevInfo d;
+    CHK(device_info(d));
+    uint32_t *bad = nullptr;
+    double *dv = nullptr;
+    CHK(dev_alloc(&bad, 2));
+    uint32_t hb[2] = {0, 0};
+    hipError_t e = launch_cover_check(ptr_x, mem_x, kx, tt[0], n, bad, st);
+    if (e == hipSuccess)
+        e = launch_cover_check(ptr_y, mem_y, ky, tt[1], n, bad + 1, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hb, bad, sizeof(hb), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    dev_free(bad);
+    if (e != hipSuccess)
+        return fail(LCD_EDEVICE, "cover check: %s", hipGetErrorString(e));
+    if (hb[0] || hb[1])
+        return fail(LCD_EINVAL, "a cover is malformed (offsets from 0 to the total, ascending ids in [0, n))");
+    CHK(dev_alloc(&dv, 1));
+    lcd_status s = cover_nmi_dev(n, d.cus, kx, ptr_x, mem_x, tt[0], ky, ptr_y, mem_y, tt[1], dv, st);
+    if (s == LCD_OK) {
+        e = hipMemcpyAsync(out, dv, sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess)
+            s = fail(LCD_EDEVICE, "nmi readout: %s", hipGetErrorString(e));
+    }
+    dev_free(dv);
+    return s;
+}
+
+lcd_status lcd_result_nmi(const lcd_result *r, int32_t s1, int32_t s2, double *out, void *stream) {
+    if (!r || !out)
+        return fail(LCD_EINVAL, "null argument");
+    if (s1 < 0 || s1 >= r->S || s2 < 0 || s2 >= r->S)
+        return fail(LCD_EINVAL, "scale index out of range");
+    hipStream_t st = (hipStream_t)stream;
+    int32_t *p1 = nullptr, *m1 = nullptr, *p2 = nullptr, *m2 = nullptr;
+    double *dv = nullptr;
+    int64_t t1 = 0, t2 = 0;
+    CHK(scale_cover(r, s1, st, &p1, &m1, &t1));
+    lcd_status s = scale_cover(r, s2, st, &p2, &m2, &t2);
+    if (s == LCD_OK)
+        s = dev_alloc(&dv, 1);
+    if (s == LCD_OK)
+        s = cover_nmi_dev(r->g->n, r->g->dev.cus, r->n_sets, p1, m1, t1, r->n_sets, p2, m2, t2, dv, st);
+    if (s == LCD_OK) {
+        hipError_t e = hipMemcpyAsync(out, dv, sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess)
+            s = fail(LCD_EDEVICE, "nmi readout: %s", hipGetErrorString(e));
+    }
+    dev_free(p1);
+    dev_free(m1);
+    dev_free(p2);
+    dev_free(m2);
+    dev_free(dv);
+    return s;
+}
+
+lcd_status lcd_result_nmi_successive(const lcd_result *r, int32_t p, double *out, void *stream) {
+    if (!r || !out)
+        return fail(LCD_EINVAL, "null argument");
+    if (p < 2 || p > r->S)
+        return fail(LCD_EINVAL, "p must be in [2, n_scales]");
+    hipStream_t st = (hipStream_t)stream;
+    double *pair = nullptr, *win = nullptr;
+    CHK(dev_alloc(&pair, (size_t)r->S));
+    lcd_status s = dev_alloc(&win, (size_t)r->S);
+    int32_t *pa = nullptr, *ma = nullptr;
+    int64_t ta = 0;
+    if (s == LCD_OK)
+        s = scale_cover(r, 0, st, &pa, &ma, &ta);
+    for (int32_t t = 0; t + 1 < r->S && s == LCD_OK; ++t) {
+        int32_t *pb = nullptr, *mb = nullptr;
+        int64_t tb = 0;
+        s = scale_cover(r, t + 1, st, &pb, &mb, &tb);
+        if (s == LCD_OK)
+            s = cover_nmi_dev(r->g->n, r->g->dev.cus, r->n_sets, pa, ma, ta, r->n_sets, pb, mb, tb, pair + t, st);
+        dev_free(pa);
+        dev_free(ma);
+        pa = pb;
+        ma = mb;
+        ta = tb;
+    }
+    if (s == LCD_OK) {
+        hipError_t e = launch_nmi_windows(pair, r->S, p, win, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(out, win, sizeof(double) * (size_t)(r->S - p + 1), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess)
+            s = fail(LCD_EDEVICE, "nmi windows: %s", hipGetErrorString(e));
+    }
+    dev_free(pa);
+    dev_free(ma);
+    dev_free(pair);
+    dev_free(win);
+    return s;
+}
+
+lcd_status lcd_result_nmi_cover(const lcd_result *r, int32_t scale_idx, int32_t k, const int32_t *ptr,
+                                const int32_t *mem, double *out, void *stream) {
+    if (!r || !out || !ptr || k < 0)
+        return fail(LCD_EINVAL, "bad arguments");
+    if (scale_idx < 0 || scale_idx >= r->S)
+        return fail(LCD_EINVAL, "scale index out of range");
+    hipStream_t st = (hipStream_t)stream;
+    int32_t tk = 0;
+    HIPCHK(hipMemcpyAsync(&tk, ptr + k, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (tk > 0 && !mem)
+        return fail(LCD_EINVAL, "null members array");
+    uint32_t *bad = nullptr;
+    CHK(dev_alloc(&bad, 1));
+    uint32_t hb = 0;
+    hipError_t e = launch_cover_check(ptr, mem, k, tk, r->g->n, bad, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&hb, bad, sizeof(hb), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    dev_free(bad);
+    if (e != hipSuccess)
+        return fail(LCD_EDEVICE, "cover check: %s", hipGetErrorString(e));
+    if (hb)
+        return fail(LCD_EINVAL, "the cover is malformed (offsets from 0 to the total, ascending ids in [0, n))");
+    int32_t *p1 = nullptr, *m1 = nullptr;
+    double *dv = nullptr;
+    int64_t t1 = 0;
+    CHK(scale_cover(r, scale_idx, st, &p1, &m1, &t1));
+    lcd_status s = dev_alloc(&dv, 1);
+    if (s == LCD_OK)
+        s = cover_nmi_dev(r->g->n, r->g->dev.cus, r->n_sets, p1, m1, t1, k, ptr, mem, tk, dv, st);
+    if (s == LCD_OK) {
+        e = hipMemcpyAsync(out, dv, sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess)
+            s = fail(LCD_EDEVICE, "nmi readout: %s", hipGetErrorString(e));
+    }
+    dev_free(p1);
+    dev_free(m1);
+    dev_free(dv);
+    return s;
 }
 
 lcd_status lcd_result_stats(const lcd_result *r, lcd_sweep_stats *out) {

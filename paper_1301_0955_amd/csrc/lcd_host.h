@@ -98,8 +98,13 @@ struct Slab {
     bool dirty = false;
 };
 
-// pool cursor, error word, then 5 statistics per tier
-constexpr int kCursorWords = 2 + 5 * kMaxTiers;
+// pool cursor, error word, then kStatWords statistics per tier
+constexpr int kCursorWords = 2 + kStatWords * kMaxTiers;
+
+// The table size from which a growth call keeps its queue bucketed by rank.
+inline int32_t queue_min_of(const lcd_params &p) {
+    return p.queue_min_entries > 0 ? p.queue_min_entries : 8192;
+}
 
 // One tier of the launch chain.
 struct TierSpec {
@@ -118,7 +123,7 @@ struct TierPlan {
 };
 
 inline int64_t slab_stride(int32_t cap) {
-    return (table_bytes(cap, next_pow2_bits(2 * (int64_t)cap)) + 255) / 256 * 256;
+    return (global_table_bytes(cap, next_pow2_bits(2 * (int64_t)cap)) + 255) / 256 * 256;
 }
 
 // The tier chain for a graph of n nodes: tier 0 one wave per community with

@@ -54,6 +54,8 @@ struct SweepArgs {
     int32_t n_sets;
     uint32_t k_prune;
     uint32_t max_calls;       // growth calls per (set, scale); 0 = until one changes nothing
+    int32_t queue_min;        // workgroup tiers on global tables: a growth call that starts
+                              // with at least this many table entries uses the bucketed queue
     int32_t resume;           // 1: start from the records of scale s_begin - 1
     Records rec;
     int32_t *pool;
@@ -61,8 +63,13 @@ struct SweepArgs {
     Counters *ctl;
     unsigned long long *pool_cursor;   // entries claimed in the pool (may pass pool_cap)
     uint32_t *err;                     // ERR_* bits
-    unsigned long long *stat;          // per tier: rows gathered, their length, entries
-                                       // created, pool entries written, sets finished
+    unsigned long long *stat;          // per tier (kStatWords each), over the sets the tier
+                                       // finished: rows gathered, their length, entries
+                                       // created, pool entries written, sets finished, table
+                                       // entries scanned; over every set the tier ran, for
+                                       // the scales whose records it wrote: rows gathered by
+                                       // moves, their length, seed-set rows, their length,
+                                       // entries created after the set's start
     int32_t tier;             // 0 = LDS; 1, 2 = global-memory tiers
     int32_t in_from;          // tier > 0: the tier whose pushes this one consumes
     const int32_t *work_in;   // tier > 0: set ids pushed by that tier
@@ -86,14 +93,24 @@ enum : int32_t {
     TIER_TEAM_GLOBAL = 3      // one workgroup per community, table in global memory
 };
 constexpr int kMaxTiers = 4;
+constexpr int kStatWords = 11;  // statistics words per tier
 constexpr int kTeamMaxThreads = 512;
 
 // Bytes per table entry (dense arrays + scratch) and per hash slot.
 constexpr int kEntryBytes = 4 /*node*/ + 4 /*d|flags*/ + 4 /*k*/ + 8 /*rank*/ + 4 /*scratch*/;
 constexpr int kSlotBytes = 4;
 
-__host__ __device__ inline int64_t table_bytes(int32_t cap, int32_t hbits) {
+__host__ __device__ constexpr int64_t table_bytes(int32_t cap, int32_t hbits) {
     return (int64_t)cap * kEntryBytes + ((int64_t)1 << hbits) * kSlotBytes;
+}
+
+// Tables in global memory also hold the workgroup kernel's rank-bucketed
+// queue and fresh list (one int32 entry index per table entry each), after
+// the hash slots.
+constexpr int kQueueBytes = 4 /*bucketed queue*/ + 4 /*fresh list*/;
+
+__host__ __device__ constexpr int64_t global_table_bytes(int32_t cap, int32_t hbits) {
+    return table_bytes(cap, hbits) + (int64_t)cap * kQueueBytes;
 }
 
 hipError_t launch_degrees(const int32_t *row_ptr, const uint8_t *w, int32_t *kdeg, int32_t n,
@@ -122,6 +139,21 @@ hipError_t launch_overlap(const int32_t *comm_ptr, const int32_t *members, int64
                           int32_t *cnt, int32_t *block_sums, hipStream_t st);
 hipError_t launch_counter_sum(const uint64_t *ctr, int64_t n_rec, unsigned long long *tot,
                               hipStream_t st);
+// NMI of two covers: h[c] for c = 0..n; one half H(X|Y)_norm into res[0]
+// (with the number of non-empty X communities in res[1]; term has kx
+// entries, cnt_all n_slots zeroed int32[ky] rows, left zeroed); the NMI
+// from both halves into *out.
+hipError_t launch_nmi_htab(double *h, int32_t n, hipStream_t st);
+hipError_t launch_nmi_half(const int32_t *px, const int32_t *mx, int32_t kx, const int32_t *py, int32_t ky,
+                           const int32_t *node_ptr, const int32_t *node_sets, const double *h, int32_t n,
+                           int32_t *cnt_all, int32_t n_slots, unsigned *next, double *term, double *res,
+                           hipStream_t st);
+hipError_t launch_nmi_final(const double *hx, const double *hy, double *out, hipStream_t st);
+// *bad = 1 unless the cover (CSR with total members) is well formed over n nodes
+hipError_t launch_cover_check(const int32_t *ptr, const int32_t *mem, int32_t k, int64_t total, int32_t n,
+                              uint32_t *bad, hipStream_t st);
+// out[s] = mean of pair[s .. s + p - 2] for s = 0 .. S - p
+hipError_t launch_nmi_windows(const double *pair, int32_t S, int32_t p, double *out, hipStream_t st);
 // overlap partner of each listed community (check phase); cnt_all holds
 // n_slots zeroed int32[n_comms] arrays and is left zeroed
 hipError_t launch_partner(const int32_t *comm_ptr, const int32_t *members, const int32_t *node_ptr,

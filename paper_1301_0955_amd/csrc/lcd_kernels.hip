@@ -104,6 +104,8 @@ struct Tab {
     int32_t *kv;
     int32_t *scr;
     int32_t *hs;
+    int32_t *sq;      // global tables: rank-bucketed queue (entry indices)
+    int32_t *fr;      // global tables: fresh list (entry indices)
     uint32_t hmask;
     int hbits;
     int cap;
@@ -117,9 +119,20 @@ __device__ __forceinline__ Tab carve(char *base, int cap, int hbits) {
     t.kv = (int32_t *)(base + (size_t)cap * 16);
     t.scr = (int32_t *)(base + (size_t)cap * 20);
     t.hs = (int32_t *)(base + (size_t)cap * 24);
+    t.sq = nullptr;
+    t.fr = nullptr;
     t.hbits = hbits;
     t.hmask = (1u << hbits) - 1;
     t.cap = cap;
+    return t;
+}
+
+// A table in global memory, with the queue arrays after its hash slots.
+__device__ __forceinline__ Tab carve_global(char *base, int cap, int hbits) {
+    Tab t = carve(base, cap, hbits);
+    char *q = base + table_bytes(cap, hbits);
+    t.sq = (int32_t *)q;
+    t.fr = (int32_t *)(q + (size_t)cap * 4);
     return t;
 }
 
@@ -161,6 +174,15 @@ struct St {
     uint64_t row_len;   // ... and their total length
     uint64_t inserted;  // table entries created (one degree read each)
     uint64_t written;   // member ids written to the pool
+    uint64_t scanned;   // table entries visited by the growth scans
+    // algorithmic work, committed when a scale's record is written (work of
+    // a scale that overflows is redone in the next tier and not counted)
+    uint64_t mrows, mrow_len;       // rows gathered by moves, running totals
+    uint64_t c_mrows, c_mrow_len;   // ... at the last record written
+    uint64_t ins_mark, c_ins;       // entries created: not counted before ins_mark;
+                                    // committed count at the last record written
+    uint64_t srows, srow_len;       // seed-set rows of a set in its first tier
+    bool emitted;                   // a record was written in this tier
 };
 
 // Watchdog: a seed set that runs past its budget stops with ERR_TIMEOUT, so
@@ -252,6 +274,10 @@ __device__ void row_update(const Tab &t, St &st, const Ctx &c, int32_t n, int la
     const int32_t end = c.row_ptr[n + 1];
     st.rows += 1;
     st.row_len += (uint64_t)(end - beg);
+    if constexpr (MODE != ROW_INIT) {
+        st.mrows += 1;
+        st.mrow_len += (uint64_t)(end - beg);
+    }
     for (int32_t base = beg; base < end; base += 64) {
         const int32_t j = base + lane;
         const bool act = j < end;
@@ -396,6 +422,7 @@ __device__ int64_t grow(const Tab &t, St &st, const Ctx &c, uint32_t k_prune, in
         double br = -__builtin_huge_val();
         int32_t bu = INT32_MAX;
         int32_t bi = -1;
+        st.scanned += (uint64_t)st.count;
         for (int32_t i = lane; i < st.count; i += 64) {
             uint32_t v = t.dv[i];
             double r;
@@ -473,6 +500,7 @@ __device__ int64_t grow(const Tab &t, St &st, const Ctx &c, uint32_t k_prune, in
         for (;;) {
             int32_t cu = INT32_MAX;
             int32_t ci = -1;
+            st.scanned += (uint64_t)st.count;
             for (int32_t i = lane; i < st.count; i += 64) {
                 const uint32_t v = t.dv[i];
                 if (!(v & kMember))
@@ -582,7 +610,7 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
     uint32_t pend_push = 0;     // overflow item to push (valid if pend_ovf)
     bool pend_ovf = false;
     uint32_t pend_err = 0;
-    uint64_t pend_stat[5] = {0, 0, 0, 0, 0};
+    uint64_t pend_stat[kStatWords] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (;;) {
         uint32_t item = 0;
         if (lane == 0) {
@@ -597,11 +625,10 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
                 }
                 if (pend_err)
                     atomicOr(A.err, pend_err);
-                if (!pend_ovf) {
-                    unsigned long long *sx = A.stat + 5 * A.tier;
-                    for (int q = 0; q < 5; ++q)
+                unsigned long long *sx = A.stat + kStatWords * A.tier;
+                for (int q = 0; q < kStatWords; ++q)
+                    if (q >= 6 || !pend_ovf)
                         atomicAdd(&sx[q], (unsigned long long)pend_stat[q]);
-                }
             }
             item = atomicAdd(&A.ctl->work_next[A.tier], 1u);
         }
@@ -640,7 +667,10 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
         st.move_limit = 8 * (int64_t)A.g.n + 65536;
         st.t0 = wall_clock64();
         st.budget = (uint64_t)A.budget_ticks;
-        st.rows = st.row_len = st.inserted = st.written = 0;
+        st.rows = st.row_len = st.inserted = st.written = st.scanned = 0;
+        st.mrows = st.mrow_len = st.c_mrows = st.c_mrow_len = st.ins_mark = st.c_ins = 0;
+        st.srows = st.srow_len = 0;
+        st.emitted = false;
 
         // initial community: the seed set, or the members recorded at the
         // previous scale when resuming
@@ -679,6 +709,14 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
         }
 
         st.err = wave_or(st.err);
+        // a seed set's initial gathers are part of the method; a set resumed
+        // from an earlier tier's record gathers its members again (overhead)
+        if (!(s0 > A.s_begin || A.resume)) {
+            st.srows = st.rows;
+            st.srow_len = st.row_len;
+        } else {
+            st.ins_mark = st.inserted;
+        }
         int64_t last_off = -1;
         int32_t last_cnt = 0;
         int32_t s_at = s0;   // the scale being grown (where an overflow happened)
@@ -751,6 +789,10 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
                 A.rec.ctr[4 * r + 2] = st.M;
                 A.rec.ctr[4 * r + 3] = calls;
             }
+            st.c_mrows = st.mrows;
+            st.c_mrow_len = st.mrow_len;
+            st.c_ins = st.inserted - st.ins_mark;
+            st.emitted = true;
         }
         pend = true;
         pend_ovf = st.ovf;
@@ -761,6 +803,12 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
         pend_stat[2] = st.inserted;
         pend_stat[3] = st.written;
         pend_stat[4] = 1;
+        pend_stat[5] = st.scanned;
+        pend_stat[6] = st.c_mrows;
+        pend_stat[7] = st.c_mrow_len;
+        pend_stat[8] = st.emitted ? st.srows : 0;
+        pend_stat[9] = st.emitted ? st.srow_len : 0;
+        pend_stat[10] = st.c_ins;
         if constexpr (GLOBAL) {
             // leave the slab's hash empty for the next community
             wsync<GLOBAL>();
@@ -794,7 +842,7 @@ __global__ void __launch_bounds__(256) sweep_global_kernel(SweepArgs A) {
     const int slot = blockIdx.x * (blockDim.x >> 6) + wave;
     if (slot >= A.n_slots)
         return;
-    Tab t = carve(A.gtab + (int64_t)slot * A.gtab_stride, A.cap, A.hbits);
+    Tab t = carve_global(A.gtab + (int64_t)slot * A.gtab_stride, A.cap, A.hbits);
     run_wave<true, false>(A, t, lane);
 }
 
@@ -814,7 +862,7 @@ __global__ void __launch_bounds__(256) query_global_kernel(SweepArgs A) {
     const int slot = blockIdx.x * (blockDim.x >> 6) + wave;
     if (slot >= A.n_slots)
         return;
-    Tab t = carve(A.gtab + (int64_t)slot * A.gtab_stride, A.cap, A.hbits);
+    Tab t = carve_global(A.gtab + (int64_t)slot * A.gtab_stride, A.cap, A.hbits);
     run_wave<true, true>(A, t, lane);
 }
 
@@ -829,6 +877,8 @@ __global__ void __launch_bounds__(256) query_global_kernel(SweepArgs A) {
 // ---------------------------------------------------------------------------
 
 constexpr int kTeamMaxWaves = 8;
+// Rank buckets of the queue of a workgroup on a global-memory table.
+constexpr int kBuckets = 256;
 
 struct TeamSh {
     double r[kTeamMaxWaves];
@@ -843,6 +893,13 @@ struct TeamSh {
     uint32_t ovf;
     uint32_t stop;
     uint32_t abort;
+    // rank-bucketed queue (global tables)
+    int32_t flen;                       // fresh-list appends (may pass the capacity)
+    int32_t bstart[kBuckets + 1];       // queue positions of each bucket
+    uint32_t fill[kBuckets];            // bucket counts, then fill cursors
+    double r2[2 * kTeamMaxWaves];       // more reduction slots
+    int32_t u2[2 * kTeamMaxWaves];
+    int32_t i2[2 * kTeamMaxWaves];
 };
 
 struct TeamId {
@@ -919,12 +976,19 @@ __device__ int32_t team_ensure(const Tab &t, TeamSh &sh, St &st, const Ctx &c, b
     return idx;
 }
 
+// bqm: the table's queue is the rank-bucketed one of team_grow_bq (global
+// tables only); otherwise pops are applied lazily as in team_grow.
 template <bool GLOBAL, int MODE>
-__device__ void team_row(const Tab &t, TeamSh &sh, St &st, const Ctx &c, const TeamId &id, int32_t n) {
+__device__ void team_row(const Tab &t, TeamSh &sh, St &st, const Ctx &c, const TeamId &id, int32_t n,
+                         bool bqm = false) {
     const int32_t beg = c.row_ptr[n];
     const int32_t end = c.row_ptr[n + 1];
     st.rows += 1;
     st.row_len += (uint64_t)(end - beg);
+    if constexpr (MODE != ROW_INIT) {
+        st.mrows += 1;
+        st.mrow_len += (uint64_t)(end - beg);
+    }
     for (int32_t base = beg; base < end; base += id.nt) {
         const int32_t j = base + id.tid;
         const bool act = j < end;
@@ -955,6 +1019,21 @@ __device__ void team_row(const Tab &t, TeamSh &sh, St &st, const Ctx &c, const T
                 d += wt;
                 if (v & kMember) {
                     t.dv[idx] = (v & ~kDMask) | (uint32_t)d;
+                } else if (GLOBAL && bqm) {
+                    // bucketed queue: popped entries are marked, and an entry
+                    // whose rank changes moves to the fresh list (its queue
+                    // slot is stale while kFresh is set)
+                    if (!(v & kLive))
+                        st.Gl += 1;
+                    const int32_t k = t.kv[idx];
+                    t.rk[idx] = rank_of(c, d, k, st.alpha);
+                    st.Rl += 1;
+                    if (!(v & kFresh)) {
+                        const int32_t pos = atomicAdd(&sh.flen, 1);
+                        if (pos < t.cap)
+                            t.fr[pos] = idx;
+                    }
+                    t.dv[idx] = (uint32_t)d | kLive | kFresh;
                 } else {
                     const bool queued = (v & kLive) && !before(t.rk[idx], u, st.pr, st.pu);
                     if (!queued)
@@ -1037,6 +1116,7 @@ __device__ int64_t team_grow(const Tab &t, TeamSh &sh, St &st, const Ctx &c, con
         double br = -__builtin_huge_val();
         int32_t bu = INT32_MAX;
         int32_t bi = -1;
+        st.scanned += (uint64_t)st.count;
         for (int32_t base = id.tid; base < st.count; base += kScanAhead * id.nt) {
             uint32_t vv[kScanAhead];
             double rr[kScanAhead];
@@ -1132,6 +1212,7 @@ __device__ int64_t team_grow(const Tab &t, TeamSh &sh, St &st, const Ctx &c, con
         for (;;) {
             int32_t cu = INT32_MAX;
             int32_t ci = -1;
+            st.scanned += (uint64_t)st.count;
             for (int32_t base = id.tid; base < st.count; base += kScanAhead * id.nt) {
                 uint32_t vv[kScanAhead];
                 int32_t nn[kScanAhead], kk[kScanAhead];
@@ -1171,6 +1252,514 @@ __device__ int64_t team_grow(const Tab &t, TeamSh &sh, St &st, const Ctx &c, con
                 t.dv[ci] = v & ~kMember;
             st.K -= 2 * (int64_t)d;
             st.V -= k;
+            st.nmem -= 1;
+            st.M += 1;
+            moves += 1;
+            set_logs(st);
+            team_row<GLOBAL, ROW_REMOVE>(t, sh, st, c, id, cu);
+            removed = true;
+            cursor = cu;
+            if ((int64_t)st.M > st.move_limit) {
+                st.err |= ERR_LIMIT;
+                return moves;
+            }
+            if ((st.M & 15) == 0 && team_over_budget(sh, id, st))
+                return moves;
+        }
+        if (!removed)
+            break;
+    }
+    return moves;
+}
+
+// ---------------------------------------------------------------------------
+// Growth on a global-memory table with a rank-bucketed queue.
+//
+// A table of thousands of entries makes a full scan per addition the cost
+// that dominates (a community adding A nodes scans its table A times).  For
+// global tables the queue is therefore kept ordered enough that a step only
+// looks at its head:
+//   * the queue: every queued entry's index, counting-sorted into kBuckets
+//     rank buckets (bucket(r) is monotone non-increasing in r, so every
+//     entry of a later bucket ranks strictly below every entry of an earlier
+//     one); positions before q.cp hold only popped entries;
+//   * the fresh list: entries re-ranked by an addition since the queue was
+//     built (flag kFresh; their queue slot is stale);
+//   * a step takes the best improving fresh entry and walks the queue from
+//     q.cp in windows of whole buckets (the best improving entry of a window
+//     is the first improving entry of the queue, if it ranks above the fresh
+//     candidate; a window with no improving entry ranked above the fresh
+//     candidate is popped whole), so it pops exactly the entries the
+//     sequential queue pops;
+//   * the queue is rebuilt (three table passes) when the fresh list grows
+//     past max(512, entries / 16).
+// Removal passes walk a list of the members instead of the whole table.
+// Same decisions, counters and results as team_grow.
+// ---------------------------------------------------------------------------
+struct BQ {
+    double rtop;     // rank of bucket 0's upper end
+    double scale;    // buckets per unit of rank
+    int32_t ns;      // entries in the bucketed queue
+    int32_t cp;      // queue positions before cp hold only popped entries
+};
+
+__device__ __forceinline__ int32_t bucket_of(double r, const BQ &q) {
+    const double x = (q.rtop - r) * q.scale;
+    if (!(x > 0.0))
+        return 0;
+    if (x >= (double)(kBuckets - 1))
+        return kBuckets - 1;
+    return (int32_t)x;
+}
+
+// true when (r, u) pops after (pr, pu)
+__device__ __forceinline__ bool pops_after(double r, int32_t u, double pr, int32_t pu) {
+    return before(pr, pu, r, u);
+}
+
+// largest b in [lo, hi] with bstart[b] <= pos (bstart non-decreasing, bstart[lo] <= pos)
+__device__ __forceinline__ int32_t bucket_at(const TeamSh &sh, int32_t lo, int32_t hi, int32_t pos) {
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (sh.bstart[mid] <= pos)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Team argmax of (r, u, i) plus the team minimum and maximum of lo and hi.
+__device__ __forceinline__ void team_max_range(TeamSh &sh, const TeamId &id, double &r, int32_t &u, int32_t &i,
+                                               double &lo, double &hi) {
+    wave_argmax(r, u, i);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, off));
+        hi = fmax(hi, __shfl_xor(hi, off));
+    }
+    if (id.lane == 0) {
+        sh.r[id.wid] = r;
+        sh.u[id.wid] = u;
+        sh.i[id.wid] = i;
+        sh.r2[id.wid] = lo;
+        sh.r2[kTeamMaxWaves + id.wid] = hi;
+    }
+    __syncthreads();
+    r = sh.r[0];
+    u = sh.u[0];
+    i = sh.i[0];
+    lo = sh.r2[0];
+    hi = sh.r2[kTeamMaxWaves];
+    for (int w = 1; w < id.nw; ++w) {
+        if (before(sh.r[w], sh.u[w], r, u)) {
+            r = sh.r[w];
+            u = sh.u[w];
+            i = sh.i[w];
+        }
+        lo = fmin(lo, sh.r2[w]);
+        hi = fmax(hi, sh.r2[kTeamMaxWaves + w]);
+    }
+    __syncthreads();
+}
+
+// Team reduction of one queue window: the best improving fresh entry (f),
+// the best improving window entry (w) and the window entry that pops last
+// (m; mi < 0: none).
+__device__ __forceinline__ void team_window(TeamSh &sh, const TeamId &id, double &fr, int32_t &fu, int32_t &fi,
+                                            double &wr, int32_t &wu, int32_t &wi, double &mr, int32_t &mi,
+                                            int32_t &mu) {
+    wave_argmax(fr, fu, fi);
+    wave_argmax(wr, wu, wi);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double r2 = __shfl_xor(mr, off);
+        const int32_t u2 = __shfl_xor(mu, off);
+        const int32_t i2 = __shfl_xor(mi, off);
+        if (i2 >= 0 && (mi < 0 || pops_after(r2, u2, mr, mu))) {
+            mr = r2;
+            mu = u2;
+            mi = i2;
+        }
+    }
+    if (id.lane == 0) {
+        sh.r[id.wid] = fr;
+        sh.u[id.wid] = fu;
+        sh.i[id.wid] = fi;
+        sh.r2[id.wid] = wr;
+        sh.u2[id.wid] = wu;
+        sh.i2[id.wid] = wi;
+        sh.r2[kTeamMaxWaves + id.wid] = mr;
+        sh.u2[kTeamMaxWaves + id.wid] = mu;
+        sh.i2[kTeamMaxWaves + id.wid] = mi;
+    }
+    __syncthreads();
+    fr = sh.r[0];
+    fu = sh.u[0];
+    fi = sh.i[0];
+    wr = sh.r2[0];
+    wu = sh.u2[0];
+    wi = sh.i2[0];
+    mr = sh.r2[kTeamMaxWaves];
+    mu = sh.u2[kTeamMaxWaves];
+    mi = sh.i2[kTeamMaxWaves];
+    for (int w = 1; w < id.nw; ++w) {
+        if (before(sh.r[w], sh.u[w], fr, fu)) {
+            fr = sh.r[w];
+            fu = sh.u[w];
+            fi = sh.i[w];
+        }
+        if (before(sh.r2[w], sh.u2[w], wr, wu)) {
+            wr = sh.r2[w];
+            wu = sh.u2[w];
+            wi = sh.i2[w];
+        }
+        const int32_t i2 = sh.i2[kTeamMaxWaves + w];
+        const double r2 = sh.r2[kTeamMaxWaves + w];
+        const int32_t u2 = sh.u2[kTeamMaxWaves + w];
+        if (i2 >= 0 && (mi < 0 || pops_after(r2, u2, mr, mu))) {
+            mr = r2;
+            mu = u2;
+            mi = i2;
+        }
+    }
+    __syncthreads();
+}
+
+// Counting-sort the queued entries into rank buckets, ranks in [rbot, rtop].
+// With pop_above, entries that pop before (pr, pu) are popped instead; entry
+// `skip` (the addition in progress) is left out.  Clears every kFresh flag
+// and empties the fresh list.
+__device__ void bq_build(const Tab &t, TeamSh &sh, St &st, const TeamId &id, BQ &q, double rtop,
+                         double rbot, bool pop_above, double pr, int32_t pu, int32_t skip) {
+    q.rtop = rtop;
+    q.scale = rtop > rbot ? (double)kBuckets / (rtop - rbot) : 0.0;
+    st.scanned += 2 * (uint64_t)st.count;
+    for (int32_t b = id.tid; b < kBuckets; b += id.nt)
+        sh.fill[b] = 0u;
+    if (id.tid == 0)
+        sh.flen = 0;
+    __syncthreads();
+    for (int32_t i = id.tid; i < st.count; i += id.nt) {
+        const uint32_t v = t.dv[i];
+        if (!(v & kLive) || (v & kMember) || i == skip)
+            continue;
+        const double r = t.rk[i];
+        if (pop_above && before(r, t.node[i], pr, pu)) {
+            t.dv[i] = v & ~(kLive | kFresh);
+            continue;
+        }
+        if (v & kFresh)
+            t.dv[i] = v & ~kFresh;
+        atomicAdd(&sh.fill[bucket_of(r, q)], 1u);
+    }
+    __syncthreads();
+    // exclusive prefix of the bucket counts (wave 0: four buckets per lane)
+    if (id.wid == 0) {
+        const int32_t b0 = 4 * id.lane;
+        uint32_t c4[4];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            c4[j] = sh.fill[b0 + j];
+            sum += c4[j];
+        }
+        uint32_t incl = sum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t x = __shfl_up(incl, off);
+            if (id.lane >= off)
+                incl += x;
+        }
+        uint32_t run = incl - sum;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            sh.bstart[b0 + j] = (int32_t)run;
+            sh.fill[b0 + j] = run;
+            run += c4[j];
+        }
+        if (id.lane == 63)
+            sh.bstart[kBuckets] = (int32_t)incl;
+    }
+    __syncthreads();
+    for (int32_t i = id.tid; i < st.count; i += id.nt) {
+        const uint32_t v = t.dv[i];
+        if (!(v & kLive) || (v & kMember) || i == skip)
+            continue;
+        const uint32_t pos = atomicAdd(&sh.fill[bucket_of(t.rk[i], q)], 1u);
+        t.sq[pos] = i;
+    }
+    __syncthreads();
+    q.ns = sh.bstart[kBuckets];
+    q.cp = 0;
+}
+
+// Rebuild the queue from every queued entry (fresh ones included).
+__device__ void bq_rebuild(const Tab &t, TeamSh &sh, St &st, const TeamId &id, BQ &q) {
+    double lo = __builtin_huge_val(), hi = -__builtin_huge_val();
+    st.scanned += (uint64_t)st.count;
+    for (int32_t i = id.tid; i < st.count; i += id.nt) {
+        const uint32_t v = t.dv[i];
+        if ((v & kLive) && !(v & kMember)) {
+            const double r = t.rk[i];
+            lo = fmin(lo, r);
+            hi = fmax(hi, r);
+        }
+    }
+    double r = -__builtin_huge_val();
+    int32_t u = INT32_MAX, i = -1;
+    team_max_range(sh, id, r, u, i, lo, hi);
+    bq_build(t, sh, st, id, q, hi, lo, false, 0.0, 0, -1);
+}
+
+// The next addition: the entry the sequential queue would add next (the
+// first improving entry in rank order), popping every queued entry ranked
+// above it.  Returns its index, or -1 when no queued entry improves (all of
+// them are popped then); er, eu, ev, ek get its rank, id, d|flags, degree.
+__device__ int32_t bq_step(const Tab &t, TeamSh &sh, St &st, const TeamId &id, BQ &q, double &er, int32_t &eu,
+                           uint32_t &ev, int32_t &ek) {
+    const int32_t flen = min(sh.flen, t.cap);
+    st.scanned += (uint64_t)flen;
+    double fr = -__builtin_huge_val();
+    int32_t fu = INT32_MAX, fi = -1;
+    for (int32_t j = id.tid; j < flen; j += id.nt) {
+        const int32_t i = t.fr[j];
+        const uint32_t v = t.dv[i];
+        if ((v & (kLive | kFresh | kMember)) != (kLive | kFresh))
+            continue;
+        const double r = t.rk[i];
+        const int32_t u = t.node[i];
+        if (before(r, u, fr, fu) && improves_add(st, (int32_t)(v & kDMask), t.kv[i])) {
+            fr = r;
+            fu = u;
+            fi = i;
+        }
+    }
+    int32_t cp = q.cp;
+    int32_t win = id.nt;
+    bool first = true;
+    int32_t e = -1;
+    bool from_q = false;
+    for (;;) {
+        // the window: whole buckets from cp, at most win entries unless its
+        // first bucket alone holds more
+        int32_t end = cp;
+        if (cp < q.ns) {
+            const int32_t b0 = bucket_at(sh, 0, kBuckets - 1, cp);
+            int32_t b1 = bucket_at(sh, b0, kBuckets, cp + win);
+            if (b1 <= b0)
+                b1 = b0 + 1;
+            end = sh.bstart[b1];
+        }
+        double wr = -__builtin_huge_val(), mr = 0.0;
+        int32_t wu = INT32_MAX, wi = -1, mu = 0, mi = -1;
+        st.scanned += (uint64_t)(end - cp);
+        for (int32_t j = cp + id.tid; j < end; j += id.nt) {
+            const int32_t i = t.sq[j];
+            const uint32_t v = t.dv[i];
+            if ((v & (kLive | kFresh | kMember)) != kLive)
+                continue;
+            const double r = t.rk[i];
+            const int32_t u = t.node[i];
+            if (mi < 0 || pops_after(r, u, mr, mu)) {
+                mr = r;
+                mu = u;
+                mi = i;
+            }
+            if (before(r, u, wr, wu) && improves_add(st, (int32_t)(v & kDMask), t.kv[i])) {
+                wr = r;
+                wu = u;
+                wi = i;
+            }
+        }
+        if (!first) {
+            fr = -__builtin_huge_val();
+            fu = INT32_MAX;
+            fi = -1;
+        }
+        team_window(sh, id, fr, fu, fi, wr, wu, wi, mr, mi, mu);
+        if (first) {
+            // the fresh candidate, kept for later windows
+            er = fr;
+            eu = fu;
+            e = fi;
+            first = false;
+        }
+        const bool has_f = e >= 0 && !from_q;
+        const bool last = end >= q.ns;
+        bool decided = false;
+        if (wi >= 0 && (!has_f || before(wr, wu, er, eu))) {
+            e = wi;
+            er = wr;
+            eu = wu;
+            from_q = true;
+            decided = true;
+        } else if (has_f && ((mi >= 0 && before(er, eu, mr, mu)) || last)) {
+            decided = true;
+        } else if (last) {
+            e = -1;
+            decided = true;
+        }
+        // pops in the window: entries ranked above the addition, or all
+        for (int32_t j = cp + id.tid; j < end; j += id.nt) {
+            const int32_t i = t.sq[j];
+            const uint32_t v = t.dv[i];
+            if ((v & (kLive | kFresh | kMember)) != kLive || i == e)
+                continue;
+            if (!decided || e < 0 || before(t.rk[i], t.node[i], er, eu))
+                t.dv[i] = v & ~kLive;
+        }
+        if (decided)
+            break;
+        cp = end;
+        win *= 2;
+        __syncthreads();
+    }
+    // pops in the fresh list
+    for (int32_t j = id.tid; j < flen; j += id.nt) {
+        const int32_t i = t.fr[j];
+        const uint32_t v = t.dv[i];
+        if ((v & (kLive | kFresh | kMember)) != (kLive | kFresh) || i == e)
+            continue;
+        if (e < 0 || before(t.rk[i], t.node[i], er, eu))
+            t.dv[i] = v & ~(kLive | kFresh);
+    }
+    // buckets before the addition's hold only popped entries now
+    q.cp = (e >= 0 && from_q) ? sh.bstart[bucket_of(er, q)] : cp;
+    if (e >= 0) {
+        ev = t.dv[e];
+        ek = t.kv[e];
+    }
+    __syncthreads();
+    return e;
+}
+
+template <bool GLOBAL>
+__device__ int64_t team_grow_bq(const Tab &t, TeamSh &sh, St &st, const Ctx &c, const TeamId &id,
+                                uint32_t k_prune) {
+    int64_t moves = 0;
+    // the queue is built from every non-member with a link into c; its best
+    // improving entry is the first addition
+    double br = -__builtin_huge_val(), lo = __builtin_huge_val(), hi = -__builtin_huge_val();
+    int32_t bu = INT32_MAX, bi = -1;
+    st.scanned += (uint64_t)st.count;
+    for (int32_t base = id.tid; base < st.count; base += kScanAhead * id.nt) {
+        uint32_t vv[kScanAhead];
+        int32_t nn[kScanAhead], kk[kScanAhead];
+#pragma unroll
+        for (int q = 0; q < kScanAhead; ++q) {
+            const int32_t i = base + q * id.nt;
+            vv[q] = 0u;
+            nn[q] = 0;
+            kk[q] = 0;
+            if (i < st.count) {
+                vv[q] = t.dv[i];
+                nn[q] = t.node[i];
+                kk[q] = t.kv[i];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kScanAhead; ++q) {
+            const int32_t i = base + q * id.nt;
+            if (i >= st.count)
+                continue;
+            const uint32_t v = vv[q];
+            if ((v & kMember) || (v & kDMask) == 0) {
+                if (v & (kLive | kFresh))
+                    t.dv[i] = v & ~(kLive | kFresh);
+                continue;
+            }
+            const double r = rank_of(c, (int32_t)(v & kDMask), kk[q], st.alpha);
+            t.rk[i] = r;
+            st.Rl += 1;
+            st.Gl += 1;
+            t.dv[i] = (v | kLive) & ~kFresh;
+            lo = fmin(lo, r);
+            if (before(r, nn[q], br, bu) && improves_add(st, (int32_t)(v & kDMask), kk[q])) {
+                br = r;
+                bu = nn[q];
+                bi = i;
+            }
+        }
+    }
+    team_max_range(sh, id, br, bu, bi, lo, hi);
+    if (bi < 0)
+        return 0;    // nothing improves: every queued entry is popped
+    BQ q;
+    bq_build(t, sh, st, id, q, br, lo, true, br, bu, bi);
+    uint32_t v = t.dv[bi];
+    int32_t k = t.kv[bi];
+    __syncthreads();
+    for (;;) {
+        // add bi; no thread reads its flags again before the row update's barriers
+        const int32_t d = (int32_t)(v & kDMask);
+        if (id.tid == 0)
+            t.dv[bi] = (v | kMember) & ~(kLive | kFresh);
+        st.K += 2 * (int64_t)d;
+        st.V += k;
+        st.nmem += 1;
+        st.M += 1;
+        moves += 1;
+        st.pr = br;
+        st.pu = bu;
+        set_logs(st);
+        team_row<GLOBAL, ROW_ADD>(t, sh, st, c, id, bu, true);
+        if (st.ovf)
+            return moves;
+        if ((int64_t)st.M > st.move_limit) {
+            st.err |= ERR_LIMIT;
+            return moves;
+        }
+        if ((st.M & 15) == 0 && team_over_budget(sh, id, st))
+            return moves;
+        if (sh.flen > max(512, st.count >> 4))
+            bq_rebuild(t, sh, st, id, q);
+        bi = bq_step(t, sh, st, id, q, br, bu, v, k);
+        if (bi < 0)
+            break;
+    }
+    // removal passes over a list of the members (in the scratch array)
+    if (id.tid == 0)
+        sh.m = 0;
+    __syncthreads();
+    for (int32_t i = id.tid; i < st.count; i += id.nt) {
+        if (t.dv[i] & kMember)
+            t.scr[atomicAdd(&sh.m, 1)] = i;
+    }
+    __syncthreads();
+    const int32_t ml = sh.m;
+    st.scanned += (uint64_t)st.count;
+    for (uint32_t pass = 0; k_prune == 0 || pass < k_prune; ++pass) {
+        st.Gu += (uint64_t)st.nmem;
+        int32_t cursor = -1;
+        bool removed = false;
+        for (;;) {
+            int32_t cu = INT32_MAX;
+            int32_t ci = -1;
+            st.scanned += (uint64_t)ml;
+            for (int32_t j = id.tid; j < ml; j += id.nt) {
+                const int32_t i = t.scr[j];
+                const uint32_t vm = t.dv[i];
+                if (!(vm & kMember))
+                    continue;
+                const int32_t u = t.node[i];
+                if (u <= cursor || u >= cu)
+                    continue;
+                if (improves_remove(st, (int32_t)(vm & kDMask), t.kv[i])) {
+                    cu = u;
+                    ci = i;
+                }
+            }
+            uint32_t vm = 0;
+            int32_t km = 0;
+            team_pick_min(sh, id, t, cu, ci, vm, km);
+            if (ci < 0)
+                break;
+            const int32_t d = (int32_t)(vm & kDMask);
+            if (id.tid == 0)
+                t.dv[ci] = vm & ~kMember;
+            st.K -= 2 * (int64_t)d;
+            st.V -= km;
             st.nmem -= 1;
             st.M += 1;
             moves += 1;
@@ -1285,7 +1874,10 @@ __device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh) {
         st.move_limit = 8 * (int64_t)A.g.n + 65536;
         st.t0 = wall_clock64();
         st.budget = (uint64_t)A.budget_ticks;
-        st.rows = st.row_len = st.inserted = st.written = 0;
+        st.rows = st.row_len = st.inserted = st.written = st.scanned = 0;
+        st.mrows = st.mrow_len = st.c_mrows = st.c_mrow_len = st.ins_mark = st.c_ins = 0;
+        st.srows = st.srow_len = 0;
+        st.emitted = false;
 
         const int32_t *init = nullptr;
         int32_t n_init = 0;
@@ -1327,6 +1919,13 @@ __device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh) {
                 break;
         }
         st.err = team_or(sh, id, st.err);
+        // seed-set gathers are the method's; a resumed set's are overhead
+        if (!(s0 > A.s_begin || A.resume)) {
+            st.srows = st.rows;
+            st.srow_len = st.row_len;
+        } else {
+            st.ins_mark = st.inserted;
+        }
 
         int64_t last_off = -1;
         int32_t last_cnt = 0;
@@ -1345,7 +1944,13 @@ __device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh) {
             int64_t moved = 0;
             for (;;) {
                 calls += 1;
-                const int64_t mv = team_grow<GLOBAL>(t, sh, st, c, id, A.k_prune);
+                // a table that starts the call with many entries keeps its
+                // queue bucketed by rank (st.count is the same in all threads)
+                int64_t mv;
+                if (GLOBAL && st.count >= A.queue_min)
+                    mv = team_grow_bq<GLOBAL>(t, sh, st, c, id, A.k_prune);
+                else
+                    mv = team_grow<GLOBAL>(t, sh, st, c, id, A.k_prune);
                 st.err = team_or(sh, id, st.err);
                 moved += mv;
                 if (st.ovf || st.err || mv == 0)
@@ -1401,8 +2006,13 @@ __device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh) {
                 A.rec.ctr[4 * r + 2] = st.M;
                 A.rec.ctr[4 * r + 3] = calls;
             }
+            st.c_mrows = st.mrows;
+            st.c_mrow_len = st.mrow_len;
+            st.c_ins = st.inserted - st.ins_mark;
+            st.emitted = true;
         }
         const uint64_t inserted = team_sum(sh, id, st.inserted);
+        const uint64_t cins = team_sum(sh, id, st.c_ins);
         if (id.tid == 0) {
             if (st.ovf) {
                 if (A.work_out) {
@@ -1415,13 +2025,22 @@ __device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh) {
             if (st.err)
                 atomicOr(A.err, st.err);
             if (!st.ovf) {
-                unsigned long long *sx = A.stat + 5 * A.tier;
+                unsigned long long *sx = A.stat + kStatWords * A.tier;
                 atomicAdd(&sx[0], (unsigned long long)st.rows);
                 atomicAdd(&sx[1], (unsigned long long)st.row_len);
                 atomicAdd(&sx[2], (unsigned long long)inserted);
                 atomicAdd(&sx[3], (unsigned long long)st.written);
                 atomicAdd(&sx[4], 1ull);
+                atomicAdd(&sx[5], (unsigned long long)st.scanned);
             }
+            unsigned long long *sa = A.stat + kStatWords * A.tier;
+            atomicAdd(&sa[6], (unsigned long long)st.c_mrows);
+            atomicAdd(&sa[7], (unsigned long long)st.c_mrow_len);
+            if (st.emitted) {
+                atomicAdd(&sa[8], (unsigned long long)st.srows);
+                atomicAdd(&sa[9], (unsigned long long)st.srow_len);
+            }
+            atomicAdd(&sa[10], (unsigned long long)cins);
         }
         if constexpr (GLOBAL) {
             // leave the slab's hash empty for the next community
@@ -1454,7 +2073,7 @@ __device__ __forceinline__ void team_global_entry(const SweepArgs &A) {
     const int slot = blockIdx.x;
     if (slot >= A.n_slots)
         return;
-    Tab t = carve(A.gtab + (int64_t)slot * A.gtab_stride, A.cap, A.hbits);
+    Tab t = carve_global(A.gtab + (int64_t)slot * A.gtab_stride, A.cap, A.hbits);
     run_team<true, PERSET>(A, t, sh);
 }
 
@@ -1893,6 +2512,178 @@ __global__ void counter_sum_kernel(const uint64_t *ctr, int64_t n_rec, unsigned 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Normalised mutual information of two covers (Sec. 4 compares community
+// sets of successive scales with the overlapping-community NMI of
+// Lancichinetti, Fortunato and Kertesz, 2009).  Entropies are in nats,
+// h(c) = (c / n) (L(n) - L(c)) for a count c of n nodes, taken from a table
+// built with the specified integer log, so that the admission test
+// h(a) + h(e) > h(b) + h(c) decides exactly as in any other implementation
+// of the same specification.  Empty communities are skipped.
+// ---------------------------------------------------------------------------
+__global__ void nmi_htab_kernel(double *h, int32_t n) {
+    const double ln_n = n > 0 ? ilog((uint64_t)n) : 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= n;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        if (c == 0) {
+            h[c] = 0.0;
+            continue;
+        }
+        const double t = ln_n - ilog((uint64_t)c);
+        const double p = (double)c / (double)n;
+        h[c] = p * t;
+    }
+}
+
+// H(X_k | Y) / H(X_k) for every community k of X, one wave per community
+// from a work counter: the wave counts X_k's intersections with every Y_l
+// through Y's node -> communities lists (cnt: one zeroed int32[ky] row per
+// wave slot, left zeroed), then takes the least admitted conditional
+// entropy over all non-empty Y_l.  term[k] = -1 marks an empty X_k.
+__global__ void __launch_bounds__(256) nmi_half_kernel(const int32_t *px, const int32_t *mx, int32_t kx,
+                                                       const int32_t *py, int32_t ky, const int32_t *node_ptr,
+                                                       const int32_t *node_sets, const double *h, int32_t n,
+                                                       int32_t *cnt_all, int32_t n_slots, unsigned *next,
+                                                       double *term) {
+    const int lane = threadIdx.x & 63;
+    const int slot = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (slot >= n_slots)
+        return;
+    int32_t *cnt = cnt_all + (int64_t)slot * ky;
+    // the item is wave-uniform and the loop has no lane-0 block at its end
+    for (;;) {
+        unsigned item = 0;
+        if (lane == 0)
+            item = atomicAdd(next, 1u);
+        item = (unsigned)__builtin_amdgcn_readfirstlane((int)item);
+        if (item >= (unsigned)kx)
+            break;
+        const int32_t k = (int32_t)item;
+        const int32_t x0 = px[k], x1 = px[k + 1];
+        const int32_t sx = x1 - x0;
+        double out = -1.0;
+        if (sx > 0) {
+            for (int32_t q = x0 + lane; q < x1; q += 64) {
+                const int32_t v = mx[q];
+                for (int32_t t = node_ptr[v]; t < node_ptr[v + 1]; ++t)
+                    atomicAdd(&cnt[node_sets[t]], 1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            const double hx = h[sx] + h[n - sx];
+            double best = 0.0;
+            int found = 0;
+            for (int32_t l = lane; l < ky; l += 64) {
+                const int32_t sy = py[l + 1] - py[l];
+                if (sy == 0)
+                    continue;
+                const int32_t a = atomicExch(&cnt[l], 0);   // read at L2 and leave it zero
+                const int32_t b = sx - a, c = sy - a, e = n - a - b - c;
+                const double ha = h[a], hb = h[b], hc = h[c], he = h[e];
+                if (!(ha + he > hb + hc))
+                    continue;
+                const double hxy = ((ha + hb) + hc) + he;
+                const double hy = h[sy] + h[n - sy];
+                const double cond = hxy - hy;
+                if (!found || cond < best) {
+                    best = cond;
+                    found = 1;
+                }
+            }
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double b2 = __shfl_xor(best, off);
+                const int f2 = __shfl_xor(found, off);
+                if (f2 && (!found || b2 < best)) {
+                    best = b2;
+                    found = 1;
+                }
+            }
+            if (!found)
+                best = hx;
+            out = hx > 0.0 ? best / hx : 0.0;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+        }
+        // every lane stores the same value
+        term[k] = out;
+    }
+}
+
+// Mean of the terms that are not -1 (one workgroup, fixed order), written
+// with its count: res[0] = mean, res[1] = count.
+__global__ void __launch_bounds__(1024) nmi_mean_kernel(const double *term, int32_t k, double *res) {
+    __shared__ double s[1024];
+    __shared__ int c[1024];
+    double acc = 0.0;
+    int cc = 0;
+    for (int32_t i = threadIdx.x; i < k; i += 1024) {
+        const double x = term[i];
+        if (x >= 0.0) {
+            acc += x;
+            cc += 1;
+        }
+    }
+    s[threadIdx.x] = acc;
+    c[threadIdx.x] = cc;
+    __syncthreads();
+    for (int off = 512; off >= 1; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            s[threadIdx.x] += s[threadIdx.x + off];
+            c[threadIdx.x] += c[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        res[0] = c[0] > 0 ? s[0] / (double)c[0] : 0.0;
+        res[1] = (double)c[0];
+    }
+}
+
+// Checks a cover given as CSR: offsets from 0 to total, non-decreasing;
+// every community strictly ascending with ids in [0, n).  Any breach sets
+// *bad.
+__global__ void cover_check_kernel(const int32_t *ptr, const int32_t *mem, int32_t k, int64_t total, int32_t n,
+                                   uint32_t *bad) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < k; j += stride) {
+        const int32_t a = ptr[j], b = ptr[j + 1];
+        if (b < a || a < 0 || (int64_t)b > total || (j == 0 && a != 0) || (j == k - 1 && (int64_t)b != total)) {
+            atomicOr(bad, 1u);
+            continue;
+        }
+        for (int32_t q = a; q < b; ++q) {
+            const int32_t v = mem[q];
+            if (v < 0 || v >= n || (q > a && v <= mem[q - 1])) {
+                atomicOr(bad, 1u);
+                break;
+            }
+        }
+    }
+}
+
+// Means of the p - 1 consecutive pair values of each window of p scales.
+__global__ void nmi_windows_kernel(const double *pair, int32_t S, int32_t p, double *out) {
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s > S - p)
+        return;
+    double acc = 0.0;
+    for (int32_t t = s; t < s + p - 1; ++t)
+        acc += pair[t];
+    out[s] = acc / (double)(p - 1);
+}
+
+// NMI from the two halves (N4: a cover without a non-empty community).
+__global__ void nmi_final_kernel(const double *hx, const double *hy, double *out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const bool ex = hx[1] > 0.0, ey = hy[1] > 0.0;
+        if (!ex || !ey)
+            *out = (!ex && !ey) ? 1.0 : 0.0;
+        else
+            *out = 1.0 - (hx[0] + hy[0]) / 2.0;
+    }
+}
+
 inline int grid_for(int64_t n, int block) {
     int64_t g = (n + block - 1) / block;
     if (g < 1)
@@ -2111,6 +2902,47 @@ hipError_t launch_partner(const int32_t *comm_ptr, const int32_t *members, const
         return e;
     hipLaunchKernelGGL(partner_kernel, dim3((n_slots + 3) / 4), dim3(256), 0, st, comm_ptr, members, node_ptr,
                        node_sets, list, n_list, n_comms, eta_num, eta_den, cnt_all, n_slots, next, partner);
+    return hipGetLastError();
+}
+
+hipError_t launch_nmi_htab(double *h, int32_t n, hipStream_t st) {
+    hipLaunchKernelGGL(nmi_htab_kernel, dim3(grid_for((int64_t)n + 1, 256)), dim3(256), 0, st, h, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_nmi_half(const int32_t *px, const int32_t *mx, int32_t kx, const int32_t *py, int32_t ky,
+                           const int32_t *node_ptr, const int32_t *node_sets, const double *h, int32_t n,
+                           int32_t *cnt_all, int32_t n_slots, unsigned *next, double *term, double *res,
+                           hipStream_t st) {
+    hipError_t e = launch_zero_bytes(next, 4, st);
+    if (e != hipSuccess)
+        return e;
+    if (kx > 0)
+        hipLaunchKernelGGL(nmi_half_kernel, dim3((n_slots + 3) / 4), dim3(256), 0, st, px, mx, kx, py, ky, node_ptr,
+                           node_sets, h, n, cnt_all, n_slots, next, term);
+    hipLaunchKernelGGL(nmi_mean_kernel, dim3(1), dim3(1024), 0, st, term, kx, res);
+    return hipGetLastError();
+}
+
+hipError_t launch_nmi_final(const double *hx, const double *hy, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(nmi_final_kernel, dim3(1), dim3(64), 0, st, hx, hy, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cover_check(const int32_t *ptr, const int32_t *mem, int32_t k, int64_t total, int32_t n,
+                              uint32_t *bad, hipStream_t st) {
+    hipError_t e = launch_zero_bytes(bad, 4, st);
+    if (e != hipSuccess || k == 0)
+        return e;
+    hipLaunchKernelGGL(cover_check_kernel, dim3(grid_for(k, 256) < 4096 ? grid_for(k, 256) : 4096), dim3(256), 0, st,
+                       ptr, mem, k, total, n, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_nmi_windows(const double *pair, int32_t S, int32_t p, double *out, hipStream_t st) {
+    if (p < 2 || p > S)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(nmi_windows_kernel, dim3((S - p + 1 + 255) / 256), dim3(256), 0, st, pair, S, p, out);
     return hipGetLastError();
 }
 

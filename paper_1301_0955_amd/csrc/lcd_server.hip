@@ -244,6 +244,7 @@ lcd_status launch_lane(lcd_server *S, Lane &L) {
     a.seed_nodes = L.seed_nodes;
     a.n_sets = nq;
     a.k_prune = S->prm.k_prune;
+    a.queue_min = queue_min_of(S->prm);
     a.resume = 0;
     a.rec = L.rec;
     a.pool = L.pool;

@@ -37,13 +37,17 @@ class lcd_params(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("pool_hint", ctypes.c_int64), ("watchdog_ms", ctypes.c_int32),
                 ("spill_mode", ctypes.c_int32), ("team_capacity", ctypes.c_int32),
-                ("team_waves", ctypes.c_int32), ("grow_calls", ctypes.c_int32)]
+                ("team_waves", ctypes.c_int32), ("grow_calls", ctypes.c_int32),
+                ("queue_min_entries", ctypes.c_int32)]
 
 
 class lcd_tier_stats(ctypes.Structure):
     _fields_ = [("rows_gathered", ctypes.c_int64), ("row_entries", ctypes.c_int64),
                 ("entries_created", ctypes.c_int64), ("members_written", ctypes.c_int64),
-                ("sets_finished", ctypes.c_int64)]
+                ("sets_finished", ctypes.c_int64), ("entries_scanned", ctypes.c_int64),
+                ("move_rows", ctypes.c_int64), ("move_row_entries", ctypes.c_int64),
+                ("seed_rows", ctypes.c_int64), ("seed_row_entries", ctypes.c_int64),
+                ("entries_committed", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -159,6 +163,12 @@ def library() -> ctypes.CDLL:
         "lcd_tune": (st, [P, P, ctypes.c_int32, P, P, ctypes.c_int32, ctypes.c_int32,
                           ctypes.POINTER(lcd_params), P, ctypes.POINTER(lcd_tune_report)]),
         "lcd_graph_untune": (st, [P]),
+        "lcd_cover_nmi": (st, [ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_int32, P, P,
+                               ctypes.POINTER(ctypes.c_double), P]),
+        "lcd_result_nmi": (st, [P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), P]),
+        "lcd_result_nmi_successive": (st, [P, ctypes.c_int32, P, P]),
+        "lcd_result_nmi_cover": (st, [P, ctypes.c_int32, ctypes.c_int32, P, P,
+                                      ctypes.POINTER(ctypes.c_double), P]),
         "lcd_last_error": (ctypes.c_char_p, []),
         "lcd_version": (ctypes.c_char_p, []),
     }
@@ -350,6 +360,28 @@ class Result:
                "lcd_result_overlap")
         return npt, nst[:tot]
 
+    def nmi(self, s1: int, s2: int) -> float:
+        """NMI of the community sets of scales s1 and s2 (lcd_result_nmi)."""
+        out = ctypes.c_double()
+        _check(library().lcd_result_nmi(self._h, s1, s2, ctypes.byref(out), _stream()), "lcd_result_nmi")
+        return out.value
+
+    def nmi_successive(self, p: int) -> np.ndarray:
+        """NMI averaged over p successive scales (lcd_result_nmi_successive)."""
+        out = np.zeros(max(self.n_scales - p + 1, 1), np.float64)
+        _check(library().lcd_result_nmi_successive(self._h, p, out.ctypes.data_as(P), _stream()),
+               "lcd_result_nmi_successive")
+        return out[:self.n_scales - p + 1]
+
+    def nmi_cover(self, s: int, cover) -> float:
+        """NMI of scale s's community set with a cover (list of ascending
+        node-id arrays), e.g. the planted communities."""
+        ptr, mem = _cover_dev(cover)
+        out = ctypes.c_double()
+        _check(library().lcd_result_nmi_cover(self._h, s, int(ptr.numel()) - 1, _ptr(ptr), _ptr(mem),
+                                              ctypes.byref(out), _stream()), "lcd_result_nmi_cover")
+        return out.value
+
     def counters(self, per_record: bool = False):
         tot = (ctypes.c_uint64 * 4)()
         pr = None
@@ -412,7 +444,8 @@ class Result:
 def make_params(k_prune: int = 0, mode: int = LCD_PERSISTENT, lds_capacity: int = 0,
                 waves_per_block: int = 0, blocks_per_cu: int = 0, use_graph: int = 0,
                 pool_hint: int = 0, watchdog_ms: int = 0, spill_mode: int = 0,
-                team_capacity: int = 0, team_waves: int = 0, grow_calls: int = 0) -> lcd_params:
+                team_capacity: int = 0, team_waves: int = 0, grow_calls: int = 0,
+                queue_min_entries: int = 0) -> lcd_params:
     p = lcd_params()
     library().lcd_params_default(ctypes.byref(p))
     p.k_prune = k_prune
@@ -428,6 +461,7 @@ def make_params(k_prune: int = 0, mode: int = LCD_PERSISTENT, lds_capacity: int 
     p.team_capacity = team_capacity
     p.team_waves = team_waves
     p.grow_calls = grow_calls
+    p.queue_min_entries = queue_min_entries
     return p
 
 
@@ -512,6 +546,26 @@ def lcd_seeds(graph: "Graph", perm, rule: int = 1) -> np.ndarray:
     _check(library().lcd_seeds(graph._h, int(rule), p.ctypes.data_as(P), LCD_MEM_HOST, _stream(),
                                out.ctypes.data_as(P), ctypes.byref(k)), "lcd_seeds")
     return out[:k.value].copy()
+
+
+def _cover_dev(cover):
+    sizes = [len(c) for c in cover]
+    ptr = np.zeros(len(cover) + 1, np.int32)
+    np.cumsum(sizes, out=ptr[1:])
+    mem = (np.concatenate([np.asarray(c, np.int32) for c in cover]) if ptr[-1] > 0
+           else np.zeros(1, np.int32))
+    return _dev(ptr, torch.int32), _dev(mem, torch.int32)
+
+
+def lcd_cover_nmi(n: int, cover_x, cover_y) -> float:
+    """NMI of two covers of n nodes on the device (lcd_cover_nmi); each cover
+    a list of strictly ascending node-id arrays."""
+    px, mx = _cover_dev(cover_x)
+    py, my = _cover_dev(cover_y)
+    out = ctypes.c_double()
+    _check(library().lcd_cover_nmi(int(n), int(px.numel()) - 1, _ptr(px), _ptr(mx), int(py.numel()) - 1,
+                                   _ptr(py), _ptr(my), ctypes.byref(out), _stream()), "lcd_cover_nmi")
+    return out.value
 
 
 def lcd_sweep_batch(graph: "Graph", scales, seed_ptr, seed_nodes, seed_graph, params=None, **kw):

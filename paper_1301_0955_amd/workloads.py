@@ -20,12 +20,51 @@ seed + 2, query stream = seed + 3.
 """
 from __future__ import annotations
 
+import ctypes
 import dataclasses
 import hashlib
 import math
+import os
+import subprocess
 from typing import Optional
 
 import numpy as np
+
+_GEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "gen")
+_GEN_SRC = os.path.join(_GEN_DIR, "lfr_gen.c")
+_GEN_LIB = os.path.join(_GEN_DIR, "liblfr_gen.so")
+_gen = None
+
+
+def build_generator(force: bool = True) -> str:
+    """Compile the C part of the input generator (gen/lfr_gen.c) with gcc."""
+    if (not force and os.path.exists(_GEN_LIB)
+            and os.path.getmtime(_GEN_LIB) >= os.path.getmtime(_GEN_SRC)):
+        return _GEN_LIB
+    tmp = _GEN_LIB + ".tmp%d" % os.getpid()
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", _GEN_SRC, "-o", tmp],
+                   check=True)
+    os.replace(tmp, _GEN_LIB)
+    return _GEN_LIB
+
+
+def _genlib():
+    global _gen
+    if _gen is None:
+        L = ctypes.CDLL(build_generator(force=False))
+        P = ctypes.c_void_p
+        L.lfrgen_match.restype = ctypes.c_int64
+        L.lfrgen_match.argtypes = [ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_int32,
+                                   ctypes.c_uint64, P, P, ctypes.c_int64]
+        L.lfrgen_csr.restype = ctypes.c_int
+        L.lfrgen_csr.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, ctypes.c_int32,
+                                 ctypes.c_uint64, P, P, P]
+        L.lfrgen_seed_rule1.restype = ctypes.c_int64
+        L.lfrgen_seed_rule1.argtypes = [ctypes.c_int64, P, P, P, P]
+        L.lfrgen_assign.restype = ctypes.c_int
+        L.lfrgen_assign.argtypes = [ctypes.c_int64, P, P, ctypes.c_int64, P, ctypes.c_uint64, P]
+        _gen = L
+    return _gen
 
 
 def _rng(seed: int) -> np.random.Generator:
@@ -327,6 +366,95 @@ def lfr_hierarchical(n: int, tau_deg: float, mean_deg: float, max_deg: int,
     return g
 
 
+def lfr_hierarchical_fast(n: int, tau_deg: float, mean_deg: float, max_deg: int,
+                          tau_comm: float = 1.5, cmin: int = 20, cmax: int = 200,
+                          mu: float = 0.3, levels: int = 3, fan: int = 10,
+                          weighted: bool = True, wmax: int = 16, seed: int = 1,
+                          rematch_rounds: int = 6) -> Graph:
+    """The construction of ``lfr_hierarchical`` for graphs of 10^7 nodes.
+    Degrees, community sizes and the stubs per level are drawn with numpy
+    as there.  Nodes are not placed in communities by a plain permutation:
+    as in the Lancichinetti-Fortunato construction, a node goes to a
+    community that can hold its internal stubs (size above (1 - mu) times
+    its degree), drawn at random among those with room, largest needs first
+    (gen/lfr_gen.c), so that hubs do not leak their edges out of small
+    communities; community ids are then shuffled before they are grouped
+    ``fan`` at a time.  The stub matching (shuffle inside each bucket, pair
+    in order, undo self-loops and repeated pairs and match their stubs
+    again) and the CSR assembly run in C on splitmix64 streams.  Weights
+    are uniform in 1..wmax per undirected edge."""
+    if levels not in (2, 3):
+        raise ValueError("levels must be 2 or 3")
+    L = _genlib()
+    rng = _rng(seed)
+    deg = powerlaw_degrees(rng, n, tau_deg, mean_deg, max_deg)
+    sizes = community_sizes(rng, n, tau_comm, cmin, cmax)
+    by_size = np.argsort(-sizes, kind="stable")
+    need = np.minimum(np.ceil((1.0 - mu) * deg).astype(np.int64) + 1, int(sizes.max()))
+    order = np.lexsort((rng.random(n), -need)).astype(np.int64)
+    slot = np.empty(n, np.int64)
+    need = np.ascontiguousarray(need, dtype=np.int64)
+    sorted_sizes = np.ascontiguousarray(sizes[by_size], dtype=np.int64)   # held across the call
+    if L.lfrgen_assign(n, need.ctypes.data, order.ctypes.data, sizes.size,
+                       sorted_sizes.ctypes.data, int(seed), slot.ctypes.data) != 0:
+        raise MemoryError("lfrgen_assign failed")
+    relabel = rng.permutation(sizes.size)          # random ids before grouping
+    comm_of = relabel[by_size[slot]]
+    csize = np.bincount(comm_of, minlength=sizes.size)[comm_of]
+    grp_of = comm_of // fan
+    sup_of = grp_of // fan
+    if levels == 2:
+        fracs = [1.0 - mu, mu / 2.0, mu / 2.0]
+        buckets = [comm_of, grp_of, np.zeros(n, dtype=np.int64)]
+    else:
+        fracs = [1.0 - mu, mu / 2.0, mu / 4.0, mu / 4.0]
+        buckets = [comm_of, grp_of, sup_of, np.zeros(n, dtype=np.int64)]
+    stubs = []
+    rem = deg.copy()
+    for li, f in enumerate(fracs[:-1]):
+        s = np.floor(f * deg + rng.random(n)).astype(np.int64)
+        if li == 0:
+            s = np.minimum(s, csize - 1)
+        s = np.minimum(s, rem)
+        stubs.append(s)
+        rem = rem - s
+    stubs.append(rem)
+    st = np.ascontiguousarray(np.stack(stubs), dtype=np.int64)
+    bk = np.ascontiguousarray(np.stack(buckets), dtype=np.int64)
+    cap = int(st.sum() // 2 + 16)
+    u = np.empty(cap, np.int32)
+    v = np.empty(cap, np.int32)
+    m = L.lfrgen_match(n, len(fracs), st.ctypes.data, bk.ctypes.data, rematch_rounds,
+                       int(seed), u.ctypes.data, v.ctypes.data, cap)
+    if m < 0:
+        raise MemoryError("lfrgen_match failed (%d)" % m)
+    del st, bk
+    if 2 * m >= 2**31:
+        raise ValueError("graph too large for int32 CSR")
+    row_ptr = np.empty(n + 1, np.int32)
+    col = np.empty(2 * m, np.int32)
+    w = np.empty(2 * m, np.uint8) if weighted else None
+    if L.lfrgen_csr(n, m, u.ctypes.data, v.ctypes.data, wmax if weighted else 0,
+                    int(seed) + 2, row_ptr.ctypes.data, col.ctypes.data,
+                    w.ctypes.data if weighted else None) != 0:
+        raise MemoryError("lfrgen_csr failed")
+    del u, v
+    g = Graph(n=int(n), row_ptr=row_ptr, col=col, w=w, meta={})
+    src = np.repeat(np.arange(n, dtype=np.int32), np.diff(row_ptr))
+    same_c = comm_of[src] == comm_of[col]
+    same_g = grp_of[src] == grp_of[col]
+    g.meta = dict(kind="lfr_hierarchical_fast", n=n, tau_deg=tau_deg, mean_deg=mean_deg,
+                  max_deg=max_deg, tau_comm=tau_comm, cmin=cmin, cmax=cmax, mu=mu,
+                  levels=levels, fan=fan, weighted=weighted, wmax=wmax, seed=seed,
+                  n_comms=int(sizes.size),
+                  achieved_mean_deg=float(g.nnz / n),
+                  achieved_max_deg=int(np.diff(row_ptr).max()),
+                  achieved_mu_comm=float(1.0 - same_c.mean()) if g.nnz else 0.0,
+                  achieved_mu_group=float(1.0 - same_g.mean()) if g.nnz else 0.0)
+    g.meta["_comm_of"] = comm_of
+    return g
+
+
 # ---------------------------------------------------------------------------
 # Tiny random graphs for exhaustive checks
 # ---------------------------------------------------------------------------
@@ -388,6 +516,20 @@ def seed_rule1(g: Graph, seed: int) -> tuple[np.ndarray, np.ndarray]:
             cand_l[v] = False
             cand_l[col[rp[v]:rp[v + 1]]] = False
     nodes = np.array(out, dtype=np.int32)
+    return np.arange(nodes.size + 1, dtype=np.int32), nodes
+
+
+def seed_rule1_fast(g: Graph, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """``seed_rule1`` with the scan in C (same permutation, same seeds)."""
+    perm = _rng(seed + 1).permutation(g.n).astype(np.int32)
+    out = np.empty(max(g.n, 1), np.int32)
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int32)    # held across the call
+    col = np.ascontiguousarray(g.col, dtype=np.int32)
+    k = _genlib().lfrgen_seed_rule1(g.n, rp.ctypes.data, col.ctypes.data, perm.ctypes.data,
+                                    out.ctypes.data)
+    if k < 0:
+        raise MemoryError("lfrgen_seed_rule1 failed")
+    nodes = out[:k].copy()
     return np.arange(nodes.size + 1, dtype=np.int32), nodes
 
 
@@ -467,6 +609,18 @@ def workload_large(seed: int = 1):
                          levels=3, weighted=True, seed=seed)
     sp, sn = seed_rule1(g, seed)
     return g, sp, sn, log_scales(64)
+
+
+def workload_xl(seed: int = 1):
+    """10M-node, ~10^8-edge three-level power-law graph (degree exponent
+    2.2, mean 20, max 5,000; community sizes exponent 1.5 on [20, 5,000],
+    so that a hub's internal edges fit its community;
+    mixing 0.3 halving per level; weights uniform in 1..16), rule-1 seeds,
+    32 scales on [0.5, 1]."""
+    g = lfr_hierarchical_fast(10_000_000, 2.2, 20.0, 5000, 1.5, 20, 5000, mu=0.3,
+                              levels=3, weighted=True, wmax=16, seed=seed)
+    sp, sn = seed_rule1_fast(g, seed)
+    return g, sp, sn, log_scales(32)
 
 
 def workload_multigraph(n_graphs: int = 64, nmin: int = 1000, nmax: int = 200_000, seed: int = 1):
