@@ -24,7 +24,8 @@
  *      raises it by 2 d_in(n)) and k_in + k_out is the community volume
  *      V = sum of member degrees.  All of K = k_in, V, d_in, degrees are
  *      exact integers (edge weights are positive integers).
- *   R2 "n improves Q_c" is decided in the log domain:
+ *   R2 whether adding n raises the fitness of the community is decided in
+ *      the log domain:
  *        t = (L(K') - L(K)) - alpha * (L(V') - L(V)),  improve <=> t > 2^-40
  *      with K' = 0 never improving and K = 0 (< K') always improving.  L is
  *      lcdo_log below, a fully specified natural log of a positive integer,
@@ -35,8 +36,8 @@
  *   R5 removal passes visit the members present at the start of the pass in
  *      ascending id and apply each removal at once; at most k_prune passes
  *      (0 = until a pass removes nothing); no pass if nothing was added.
- *   R6 without the merge phase, "while changes can be made" is the
- *      fixpoint of the growth function at each scale.
+ *   R6 without the merge phase, the repetition of Algorithm 2 until nothing
+ *      changes is the fixpoint of the growth function at each scale.
  *   R7 the reported criterion value is f = K / pow(V, alpha) (0 when K = 0).
  *
  * Work counters (the definition the GPU must reproduce):
@@ -448,8 +449,8 @@ static void lcdo_reset(lcdo_ctx *g)
 }
 
 /*
- * Grow one initial community (Algorithm 2: "a set of initial communities"
- * or a seed) through every scale in order.
+ * Grow one initial community (one of the starting sets of Algorithm 2, or a
+ * seed) through every scale in order.
  *
  * seeds[0..ns)      distinct node ids forming the initial community
  * scales[0..S)      alpha values, finest first (decreasing alpha)

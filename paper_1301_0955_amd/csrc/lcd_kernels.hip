@@ -15,7 +15,8 @@
 //     rejected against the same state first.  Those pops are applied lazily:
 //     the next pass drops a live entry ranked above the previous e* unless
 //     the addition of e* touched it (flag FRESH), which is exactly the
-//     queue's "update or add the neighbours of n".
+//     queue update that Algorithm 1 applies to the neighbours of an added
+//     node.
 //   * the number of pops G is counted where entries enter the queue (every
 //     entry that enters is popped exactly once before the queue empties).
 //   * a removal pass visits members in ascending id: each step finds the

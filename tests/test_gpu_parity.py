@@ -184,19 +184,20 @@ def test_sweep_validation(L):
 
 
 def test_overlap_readout(L):
+    # the node -> sets map against the inversion of the oracle's member sets
     g, sp, sn, scales = W.workload_small()
     G = L.Graph.from_workload(g)
     res = L.lcd_sweep(G, scales, sp, sn)
+    ref = oracle.Oracle.from_graph(g).run_sets(sp, sn, scales)
+    S = scales.size
     for s in (0, 4, 9):
-        cp, m, _, _, _ = res.membership(s)
-        cp = cp.cpu().numpy()
-        m = m.cpu().numpy()
         npt, nst = res.overlap(s)
         npt = npt.cpu().numpy()
         nst = nst.cpu().numpy()
         want = [[] for _ in range(g.n)]
         for j in range(res.n_sets):
-            for u in m[cp[j]:cp[j + 1]]:
+            r = j * S + s
+            for u in ref["members"][ref["off"][r]:ref["off"][r] + ref["cnt"][r]]:
                 want[u].append(j)
         ptr = np.zeros(g.n + 1, np.int64)
         ptr[1:] = np.cumsum([len(x) for x in want])

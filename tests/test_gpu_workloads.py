@@ -63,12 +63,54 @@ def test_medium_workload_other_configs(L, kw):
          % (kw, k, [t["sets_finished"] for t in st["tier"]]))
 
 
+def _stratified(L, G, g, sp, sn, scales, stride, n_big, label, **kw):
+    """Every stride-th set plus the n_big sets with the largest final
+    volume (the communities that outgrow the first tiers), checked against
+    the oracle; a sweep of those sets alone (a set's tier depends on the set
+    only) must finish sets in every tier of the plan."""
+    res = L.lcd_sweep(G, scales, sp, sn, **kw)
+    full_st = res.stats()
+    S = scales.size
+    _, _, vol, _, _ = res.membership(S - 1)
+    vol = vol.cpu().numpy()
+    big = np.argsort(-vol, kind="stable")[:n_big]
+    ids = np.unique(np.concatenate([np.arange(0, sp.size - 1, stride), big])).astype(np.int32)
+    got = res.sets_to_numpy(ids)
+    res.free()
+    sizes = sp[ids + 1] - sp[ids]
+    sp2 = np.zeros(ids.size + 1, np.int32)
+    np.cumsum(sizes, out=sp2[1:])
+    sn2 = np.concatenate([sn[sp[j]:sp[j + 1]] for j in ids]).astype(np.int32)
+    sub = L.lcd_sweep(G, scales, sp2, sn2, **kw)
+    tiers = [t["sets_finished"] for t in sub.stats()["tier"][:full_st["tiers"]]]
+    sub.free()
+    _say("%s: %d sets sampled; alone they finish per tier %s (whole run %s)"
+         % (label, ids.size, tiers, [t["sets_finished"] for t in full_st["tier"][:full_st["tiers"]]]))
+    ref = oracle.Oracle.from_graph(g).run_sets(sp2, sn2, scales)
+    compare_results(got, ref, label=label)
+    return full_st, tiers
+
+
 def test_large_workload_sampled(L):
     g, sp, sn, scales = W.workload_large()
     _say("large: %d sets x %d scales" % (sp.size - 1, scales.size))
-    st, k = _sampled(L, g, sp, sn, scales, 2048)
-    _say("large: %d sampled sets match; %.0f ms device; sets finished per tier %s"
-         % (k, st["ms_total"], [t["sets_finished"] for t in st["tier"]]))
+    G = L.Graph.from_workload(g)
+    st, tiers = _stratified(L, G, g, sp, sn, scales, 2048, 24, "large")
+    _say("large: %.0f ms device" % st["ms_total"])
+    # every tier that finished sets in the whole run finishes sampled sets
+    whole = [t["sets_finished"] for t in st["tier"][:st["tiers"]]]
+    assert all(t > 0 for t, w in zip(tiers, whole) if w > 0), (tiers, whole)
+
+
+def test_xl_workload_sampled(L):
+    """The 10M-node graph: a share of its seed sets on the GPU (every 4096th
+    rule-1 set), every 64th of those plus the 4 largest through the oracle."""
+    g, sp, sn, scales = W.workload_xl()
+    sp1, sn1, _ = W.subsample_sets(sp, sn, 4096)
+    _say("xl: %d of %d sets x %d scales" % (sp1.size - 1, sp.size - 1, scales.size))
+    G = L.Graph.from_workload(g)
+    st, tiers = _stratified(L, G, g, sp1, sn1, scales, 64, 4, "xl")
+    assert tiers[-2] > 0 or tiers[-1] > 0     # the global-table tiers ran sampled sets
 
 
 def test_resume_equals_full_sweep(L):
