@@ -102,10 +102,11 @@ typedef struct {
     int32_t grow_calls;      /* growth calls per (seed set, scale): 0 = until a call
                                 changes nothing (the default); n > 0 stops after
                                 n calls (lcd_sweep_merge makes one per round) */
-    int32_t queue_min_entries; /* workgroup tiers on global tables: a growth call whose
-                                table holds at least this many entries keeps its queue
-                                bucketed by rank (a step looks at the queue's head, not
-                                the whole table); 0 = default (8,192); results never
+    int32_t queue_min_entries; /* workgroup tiers on global tables: once the table of a
+                                growth call holds this many entries (checked after
+                                each addition) the call keeps its queue bucketed by
+                                rank (a step looks at the queue's head, not the
+                                whole table); 0 = default (8,192); results never
                                 depend on it */
 } lcd_params;
 

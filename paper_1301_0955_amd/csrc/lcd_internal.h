@@ -54,8 +54,8 @@ struct SweepArgs {
     int32_t n_sets;
     uint32_t k_prune;
     uint32_t max_calls;       // growth calls per (set, scale); 0 = until one changes nothing
-    int32_t queue_min;        // workgroup tiers on global tables: a growth call that starts
-                              // with at least this many table entries uses the bucketed queue
+    int32_t queue_min;        // workgroup tiers on global tables: a growth call switches to
+                              // the bucketed queue once its table holds this many entries
     int32_t resume;           // 1: start from the records of scale s_begin - 1
     Records rec;
     int32_t *pool;

@@ -977,8 +977,8 @@ __device__ int32_t team_ensure(const Tab &t, TeamSh &sh, St &st, const Ctx &c, b
     return idx;
 }
 
-// bqm: the table's queue is the rank-bucketed one of team_grow_bq (global
-// tables only); otherwise pops are applied lazily as in team_grow.
+// bqm: the table's queue is the rank-bucketed one (global tables only);
+// otherwise pops are applied lazily, by the next table scan.
 template <bool GLOBAL, int MODE>
 __device__ void team_row(const Tab &t, TeamSh &sh, St &st, const Ctx &c, const TeamId &id, int32_t n,
                          bool bqm = false) {
@@ -1107,105 +1107,12 @@ __device__ __forceinline__ void team_pick_min(TeamSh &sh, const TeamId &id, cons
 // flight per thread; the scans are latency-bound).
 constexpr int kScanAhead = 4;
 
-// One call of the growth function (Algorithm 1) by the whole workgroup.
+// Removal passes of one growth call over the whole table: members in
+// ascending id, each removal applied at once.  False when the call must
+// end early (move limit, budget).
 template <bool GLOBAL>
-__device__ int64_t team_grow(const Tab &t, TeamSh &sh, St &st, const Ctx &c, const TeamId &id,
-                             uint32_t k_prune) {
-    int64_t moves = 0;
-    bool creation = true;
-    for (;;) {
-        double br = -__builtin_huge_val();
-        int32_t bu = INT32_MAX;
-        int32_t bi = -1;
-        st.scanned += (uint64_t)st.count;
-        for (int32_t base = id.tid; base < st.count; base += kScanAhead * id.nt) {
-            uint32_t vv[kScanAhead];
-            double rr[kScanAhead];
-            int32_t nn[kScanAhead], kk[kScanAhead];
-#pragma unroll
-            for (int q = 0; q < kScanAhead; ++q) {
-                const int32_t i = base + q * id.nt;
-                vv[q] = 0u;
-                rr[q] = 0.0;
-                nn[q] = 0;
-                kk[q] = 0;
-                if (i < st.count) {
-                    vv[q] = t.dv[i];
-                    rr[q] = t.rk[i];
-                    nn[q] = t.node[i];
-                    kk[q] = t.kv[i];
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < kScanAhead; ++q) {
-                const int32_t i = base + q * id.nt;
-                if (i >= st.count)
-                    continue;
-                uint32_t v = vv[q];
-                double r = rr[q];
-                if (creation) {
-                    // the queue is built from every non-member with a link into c
-                    if ((v & kMember) || (v & kDMask) == 0) {
-                        if (v & (kLive | kFresh))
-                            t.dv[i] = v & ~(kLive | kFresh);
-                        continue;
-                    }
-                    r = rank_of(c, (int32_t)(v & kDMask), kk[q], st.alpha);
-                    t.rk[i] = r;
-                    st.Rl += 1;
-                    st.Gl += 1;
-                    v = (v | kLive) & ~kFresh;
-                    t.dv[i] = v;
-                } else {
-                    if (!(v & kLive))
-                        continue;
-                    if (v & kFresh) {
-                        v &= ~kFresh;
-                        t.dv[i] = v;
-                    } else if (before(r, nn[q], st.pr, st.pu)) {
-                        t.dv[i] = v & ~kLive;      // popped and rejected last step
-                        continue;
-                    }
-                }
-                if (before(r, nn[q], br, bu) && improves_add(st, (int32_t)(v & kDMask), kk[q])) {
-                    br = r;
-                    bu = nn[q];
-                    bi = i;
-                }
-            }
-        }
-        creation = false;
-        uint32_t v = 0;
-        int32_t k = 0;
-        team_pick_max(sh, id, t, br, bu, bi, v, k);
-        if (bi < 0)
-            break;
-        // add the best improving node; no thread reads its flags again
-        // before the barriers of the row update below
-        const int32_t d = (int32_t)(v & kDMask);
-        if (id.tid == 0)
-            t.dv[bi] = (v | kMember) & ~(kLive | kFresh);
-        st.K += 2 * (int64_t)d;
-        st.V += k;
-        st.nmem += 1;
-        st.M += 1;
-        moves += 1;
-        st.pr = br;
-        st.pu = bu;
-        set_logs(st);
-        team_row<GLOBAL, ROW_ADD>(t, sh, st, c, id, bu);
-        if (st.ovf)
-            return moves;
-        if ((int64_t)st.M > st.move_limit) {
-            st.err |= ERR_LIMIT;
-            return moves;
-        }
-        if ((st.M & 15) == 0 && team_over_budget(sh, id, st))
-            return moves;
-    }
-    if (moves == 0)
-        return 0;
-    // removal passes over the members in ascending id
+__device__ bool removal_scan(const Tab &t, TeamSh &sh, St &st, const Ctx &c, const TeamId &id,
+                             uint32_t k_prune, int64_t &moves) {
     for (uint32_t pass = 0; k_prune == 0 || pass < k_prune; ++pass) {
         st.Gu += (uint64_t)st.nmem;
         int32_t cursor = -1;
@@ -1262,15 +1169,15 @@ __device__ int64_t team_grow(const Tab &t, TeamSh &sh, St &st, const Ctx &c, con
             cursor = cu;
             if ((int64_t)st.M > st.move_limit) {
                 st.err |= ERR_LIMIT;
-                return moves;
+                return false;
             }
             if ((st.M & 15) == 0 && team_over_budget(sh, id, st))
-                return moves;
+                return false;
         }
         if (!removed)
             break;
     }
-    return moves;
+    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -1295,7 +1202,7 @@ __device__ int64_t team_grow(const Tab &t, TeamSh &sh, St &st, const Ctx &c, con
 //   * the queue is rebuilt (three table passes) when the fresh list grows
 //     past max(512, entries / 16).
 // Removal passes walk a list of the members instead of the whole table.
-// Same decisions, counters and results as team_grow.
+// Same decisions, counters and results as the scan-driven additions.
 // ---------------------------------------------------------------------------
 struct BQ {
     double rtop;     // rank of bucket 0's upper end
@@ -1428,9 +1335,10 @@ __device__ __forceinline__ void team_window(TeamSh &sh, const TeamId &id, double
 }
 
 // Counting-sort the queued entries into rank buckets, ranks in [rbot, rtop].
-// With pop_above, entries that pop before (pr, pu) are popped instead; entry
-// `skip` (the addition in progress) is left out.  Clears every kFresh flag
-// and empties the fresh list.
+// With pop_above, entries not re-ranked since (pr, pu) was added (no kFresh)
+// that pop before it are popped instead; entry `skip` (the addition in
+// progress) is left out.  Clears every kFresh flag and empties the fresh
+// list.
 __device__ void bq_build(const Tab &t, TeamSh &sh, St &st, const TeamId &id, BQ &q, double rtop,
                          double rbot, bool pop_above, double pr, int32_t pu, int32_t skip) {
     q.rtop = rtop;
@@ -1446,7 +1354,7 @@ __device__ void bq_build(const Tab &t, TeamSh &sh, St &st, const TeamId &id, BQ 
         if (!(v & kLive) || (v & kMember) || i == skip)
             continue;
         const double r = t.rk[i];
-        if (pop_above && before(r, t.node[i], pr, pu)) {
+        if (pop_above && !(v & kFresh) && before(r, t.node[i], pr, pu)) {
             t.dv[i] = v & ~(kLive | kFresh);
             continue;
         }
@@ -1511,6 +1419,29 @@ __device__ void bq_rebuild(const Tab &t, TeamSh &sh, St &st, const TeamId &id, B
     int32_t u = INT32_MAX, i = -1;
     team_max_range(sh, id, r, u, i, lo, hi);
     bq_build(t, sh, st, id, q, hi, lo, false, 0.0, 0, -1);
+}
+
+// Switch a call from lazy pops to the bucketed queue right after an
+// addition (st.pr, st.pu): the entries the lazy scan would drop next (not
+// re-ranked, ranked above the addition) are popped, every other queued entry
+// is bucketed.
+__device__ void bq_switch(const Tab &t, TeamSh &sh, St &st, const TeamId &id, BQ &q) {
+    double lo = __builtin_huge_val(), hi = -__builtin_huge_val();
+    st.scanned += (uint64_t)st.count;
+    for (int32_t i = id.tid; i < st.count; i += id.nt) {
+        const uint32_t v = t.dv[i];
+        if (!(v & kLive) || (v & kMember))
+            continue;
+        const double r = t.rk[i];
+        if (!(v & kFresh) && before(r, t.node[i], st.pr, st.pu))
+            continue;
+        lo = fmin(lo, r);
+        hi = fmax(hi, r);
+    }
+    double r = -__builtin_huge_val();
+    int32_t u = INT32_MAX, i = -1;
+    team_max_range(sh, id, r, u, i, lo, hi);
+    bq_build(t, sh, st, id, q, hi, lo, true, st.pr, st.pu, -1);
 }
 
 // The next addition: the entry the sequential queue would add next (the
@@ -1635,63 +1566,21 @@ __device__ int32_t bq_step(const Tab &t, TeamSh &sh, St &st, const TeamId &id, B
     return e;
 }
 
+// Additions from the bucketed queue until no queued entry improves (true)
+// or the call must end early (false: overflow, move limit, budget).
 template <bool GLOBAL>
-__device__ int64_t team_grow_bq(const Tab &t, TeamSh &sh, St &st, const Ctx &c, const TeamId &id,
-                                uint32_t k_prune) {
-    int64_t moves = 0;
-    // the queue is built from every non-member with a link into c; its best
-    // improving entry is the first addition
-    double br = -__builtin_huge_val(), lo = __builtin_huge_val(), hi = -__builtin_huge_val();
-    int32_t bu = INT32_MAX, bi = -1;
-    st.scanned += (uint64_t)st.count;
-    for (int32_t base = id.tid; base < st.count; base += kScanAhead * id.nt) {
-        uint32_t vv[kScanAhead];
-        int32_t nn[kScanAhead], kk[kScanAhead];
-#pragma unroll
-        for (int q = 0; q < kScanAhead; ++q) {
-            const int32_t i = base + q * id.nt;
-            vv[q] = 0u;
-            nn[q] = 0;
-            kk[q] = 0;
-            if (i < st.count) {
-                vv[q] = t.dv[i];
-                nn[q] = t.node[i];
-                kk[q] = t.kv[i];
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < kScanAhead; ++q) {
-            const int32_t i = base + q * id.nt;
-            if (i >= st.count)
-                continue;
-            const uint32_t v = vv[q];
-            if ((v & kMember) || (v & kDMask) == 0) {
-                if (v & (kLive | kFresh))
-                    t.dv[i] = v & ~(kLive | kFresh);
-                continue;
-            }
-            const double r = rank_of(c, (int32_t)(v & kDMask), kk[q], st.alpha);
-            t.rk[i] = r;
-            st.Rl += 1;
-            st.Gl += 1;
-            t.dv[i] = (v | kLive) & ~kFresh;
-            lo = fmin(lo, r);
-            if (before(r, nn[q], br, bu) && improves_add(st, (int32_t)(v & kDMask), kk[q])) {
-                br = r;
-                bu = nn[q];
-                bi = i;
-            }
-        }
-    }
-    team_max_range(sh, id, br, bu, bi, lo, hi);
-    if (bi < 0)
-        return 0;    // nothing improves: every queued entry is popped
-    BQ q;
-    bq_build(t, sh, st, id, q, br, lo, true, br, bu, bi);
-    uint32_t v = t.dv[bi];
-    int32_t k = t.kv[bi];
-    __syncthreads();
+__device__ bool bq_additions(const Tab &t, TeamSh &sh, St &st, const Ctx &c, const TeamId &id, BQ &q,
+                             int64_t &moves) {
     for (;;) {
+        if (sh.flen > max(512, st.count >> 4))
+            bq_rebuild(t, sh, st, id, q);
+        double br;
+        int32_t bu;
+        uint32_t v;
+        int32_t k;
+        const int32_t bi = bq_step(t, sh, st, id, q, br, bu, v, k);
+        if (bi < 0)
+            return true;
         // add bi; no thread reads its flags again before the row update's barriers
         const int32_t d = (int32_t)(v & kDMask);
         if (id.tid == 0)
@@ -1706,20 +1595,22 @@ __device__ int64_t team_grow_bq(const Tab &t, TeamSh &sh, St &st, const Ctx &c, 
         set_logs(st);
         team_row<GLOBAL, ROW_ADD>(t, sh, st, c, id, bu, true);
         if (st.ovf)
-            return moves;
+            return false;
         if ((int64_t)st.M > st.move_limit) {
             st.err |= ERR_LIMIT;
-            return moves;
+            return false;
         }
         if ((st.M & 15) == 0 && team_over_budget(sh, id, st))
-            return moves;
-        if (sh.flen > max(512, st.count >> 4))
-            bq_rebuild(t, sh, st, id, q);
-        bi = bq_step(t, sh, st, id, q, br, bu, v, k);
-        if (bi < 0)
-            break;
+            return false;
     }
-    // removal passes over a list of the members (in the scratch array)
+}
+
+// Removal passes of one growth call over a list of the members gathered
+// once (global tables), same order and decisions as removal_scan.
+template <bool GLOBAL>
+__device__ bool removal_members(const Tab &t, TeamSh &sh, St &st, const Ctx &c, const TeamId &id,
+                                uint32_t k_prune, int64_t &moves) {
+    // a list of the members (in the scratch array)
     if (id.tid == 0)
         sh.m = 0;
     __syncthreads();
@@ -1770,14 +1661,138 @@ __device__ int64_t team_grow_bq(const Tab &t, TeamSh &sh, St &st, const Ctx &c, 
             cursor = cu;
             if ((int64_t)st.M > st.move_limit) {
                 st.err |= ERR_LIMIT;
-                return moves;
+                return false;
             }
             if ((st.M & 15) == 0 && team_over_budget(sh, id, st))
-                return moves;
+                return false;
         }
         if (!removed)
             break;
     }
+    return true;
+}
+
+
+// One call of the growth function (Algorithm 1) by the whole workgroup.
+// Additions start with full-table scans and lazy pops; on a global table
+// whose entry count reaches queue_min (the count is the same in all
+// threads) the call switches to the bucketed queue for the rest of its
+// additions and to member-list removal passes.
+template <bool GLOBAL>
+__device__ int64_t team_grow(const Tab &t, TeamSh &sh, St &st, const Ctx &c, const TeamId &id,
+                             uint32_t k_prune, int32_t queue_min) {
+    int64_t moves = 0;
+    bool creation = true;
+    bool bucketed = false;
+    for (;;) {
+        double br = -__builtin_huge_val();
+        int32_t bu = INT32_MAX;
+        int32_t bi = -1;
+        st.scanned += (uint64_t)st.count;
+        for (int32_t base = id.tid; base < st.count; base += kScanAhead * id.nt) {
+            uint32_t vv[kScanAhead];
+            double rr[kScanAhead];
+            int32_t nn[kScanAhead], kk[kScanAhead];
+#pragma unroll
+            for (int q = 0; q < kScanAhead; ++q) {
+                const int32_t i = base + q * id.nt;
+                vv[q] = 0u;
+                rr[q] = 0.0;
+                nn[q] = 0;
+                kk[q] = 0;
+                if (i < st.count) {
+                    vv[q] = t.dv[i];
+                    rr[q] = t.rk[i];
+                    nn[q] = t.node[i];
+                    kk[q] = t.kv[i];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kScanAhead; ++q) {
+                const int32_t i = base + q * id.nt;
+                if (i >= st.count)
+                    continue;
+                uint32_t v = vv[q];
+                double r = rr[q];
+                if (creation) {
+                    // the queue is built from every non-member with a link into c
+                    if ((v & kMember) || (v & kDMask) == 0) {
+                        if (v & (kLive | kFresh))
+                            t.dv[i] = v & ~(kLive | kFresh);
+                        continue;
+                    }
+                    r = rank_of(c, (int32_t)(v & kDMask), kk[q], st.alpha);
+                    t.rk[i] = r;
+                    st.Rl += 1;
+                    st.Gl += 1;
+                    v = (v | kLive) & ~kFresh;
+                    t.dv[i] = v;
+                } else {
+                    if (!(v & kLive))
+                        continue;
+                    if (v & kFresh) {
+                        v &= ~kFresh;
+                        t.dv[i] = v;
+                    } else if (before(r, nn[q], st.pr, st.pu)) {
+                        t.dv[i] = v & ~kLive;      // popped and rejected last step
+                        continue;
+                    }
+                }
+                if (before(r, nn[q], br, bu) && improves_add(st, (int32_t)(v & kDMask), kk[q])) {
+                    br = r;
+                    bu = nn[q];
+                    bi = i;
+                }
+            }
+        }
+        creation = false;
+        uint32_t v = 0;
+        int32_t k = 0;
+        team_pick_max(sh, id, t, br, bu, bi, v, k);
+        if (bi < 0)
+            break;
+        // add the best improving node; no thread reads its flags again
+        // before the barriers of the row update below
+        const int32_t d = (int32_t)(v & kDMask);
+        if (id.tid == 0)
+            t.dv[bi] = (v | kMember) & ~(kLive | kFresh);
+        st.K += 2 * (int64_t)d;
+        st.V += k;
+        st.nmem += 1;
+        st.M += 1;
+        moves += 1;
+        st.pr = br;
+        st.pu = bu;
+        set_logs(st);
+        team_row<GLOBAL, ROW_ADD>(t, sh, st, c, id, bu);
+        if (st.ovf)
+            return moves;
+        if ((int64_t)st.M > st.move_limit) {
+            st.err |= ERR_LIMIT;
+            return moves;
+        }
+        if ((st.M & 15) == 0 && team_over_budget(sh, id, st))
+            return moves;
+        if constexpr (GLOBAL) {
+            if (st.count >= queue_min) {
+                BQ q;
+                bq_switch(t, sh, st, id, q);
+                if (!bq_additions<GLOBAL>(t, sh, st, c, id, q, moves))
+                    return moves;
+                bucketed = true;
+                break;
+            }
+        }
+    }
+    if (moves == 0)
+        return 0;
+    if constexpr (GLOBAL) {
+        if (bucketed) {
+            removal_members<GLOBAL>(t, sh, st, c, id, k_prune, moves);
+            return moves;
+        }
+    }
+    removal_scan<GLOBAL>(t, sh, st, c, id, k_prune, moves);
     return moves;
 }
 
@@ -1945,13 +1960,7 @@ __device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh) {
             int64_t moved = 0;
             for (;;) {
                 calls += 1;
-                // a table that starts the call with many entries keeps its
-                // queue bucketed by rank (st.count is the same in all threads)
-                int64_t mv;
-                if (GLOBAL && st.count >= A.queue_min)
-                    mv = team_grow_bq<GLOBAL>(t, sh, st, c, id, A.k_prune);
-                else
-                    mv = team_grow<GLOBAL>(t, sh, st, c, id, A.k_prune);
+                const int64_t mv = team_grow<GLOBAL>(t, sh, st, c, id, A.k_prune, A.queue_min);
                 st.err = team_or(sh, id, st.err);
                 moved += mv;
                 if (st.ovf || st.err || mv == 0)

@@ -109,6 +109,10 @@ def test_small_workload_per_scale_loop(L, kw):
     ("workgroup tiers: three waves", dict(lds_capacity=128, team_capacity=256, team_waves=3)),
     ("one-wave global tiers", dict(lds_capacity=64, spill_mode=1)),
     ("one-wave global tier, then workgroups", dict(lds_capacity=64, spill_mode=2)),
+    ("global tables, rank-bucketed queue in every call", dict(lds_capacity=64, team_capacity=128,
+                                                             queue_min_entries=1)),
+    ("global tables, queue bucketed from 160 entries on", dict(lds_capacity=64, team_capacity=128,
+                                                              queue_min_entries=160)),
 ])
 def test_small_workload_spill_tiers(L, label, kw):
     # a 64-entry tier-0 table sends nearly every community to the later tiers

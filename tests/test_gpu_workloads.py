@@ -55,7 +55,8 @@ def test_medium_workload_sampled(L):
 
 @pytest.mark.parametrize("kw", [dict(lds_capacity=256), dict(lds_capacity=2048),
                                 dict(lds_capacity=512, spill_mode=1),
-                                dict(lds_capacity=64, team_capacity=1024, team_waves=4)])
+                                dict(lds_capacity=64, team_capacity=1024, team_waves=4),
+                                dict(lds_capacity=64, team_capacity=256, queue_min_entries=600)])
 def test_medium_workload_other_configs(L, kw):
     g, sp, sn, scales = W.workload_medium()
     st, k = _sampled(L, g, sp, sn, scales, 64, **kw)
