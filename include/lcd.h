@@ -239,6 +239,47 @@ lcd_status lcd_sweep(const lcd_graph *g, const double *scales, int32_t n_scales,
                      int32_t mem_kind, const lcd_params *params, void *stream,
                      lcd_result **out);
 
+/*
+ * lcd_sweep for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same sweep and
+ * the same records, written into caller buffers; the library allocates
+ * nothing, on the device or the host.  Its working memory (work queues,
+ * counters, LCD_NOALLOC_TABLES global-memory tables of the workgroup tier)
+ * is one static device array of LCD_NOALLOC_SCRATCH_BYTES that each GPU the
+ * library runs on holds until the process ends.  Every call on a GPU uses
+ * that GPU's array, so calls that overlap on one GPU race: issue them in
+ * order.
+ *   scales, seed_ptr, seed_nodes  device arrays, rules as in lcd_sweep;
+ *            n_seed_nodes = seed_ptr[n_sets] (the length of seed_nodes)
+ *   rec_off int64, rec_cnt int32, rec_k int64, rec_v int64, rec_f double
+ *            (n_sets * n_scales each) and rec_ctr uint64 (4 per record):
+ *            device arrays; record r = set * n_scales + s as in lcd_sweep:
+ *            members of r at members[rec_off[r] .. + rec_cnt[r]), ascending
+ *   members  device int32[members_cap]; *members_used (host) receives the
+ *            entries the sweep wrote or needed
+ *   params   as lcd_sweep (spill_mode 0, persistent mode, no use_graph)
+ * Limits: n_sets <= LCD_NOALLOC_MAX_SETS, n_scales <= LCD_NOALLOC_MAX_SCALES,
+ * seed sets of at most LCD_NOALLOC_MAX_SEED_SET nodes, and tables of at most
+ * LCD_NOALLOC_TABLE_ENTRIES entries per community (larger communities need
+ * lcd_sweep's whole-graph tier).
+ * Errors: LCD_EINVAL for arguments outside the rules (inputs are checked on
+ * the device); LCD_ECAPACITY when a limit above is passed or members_cap is
+ * too small (*members_used then holds the size needed; the records are not
+ * valid); LCD_EDEVICE for a failed launch or a kernel error.  Blocking.
+ */
+#define LCD_NOALLOC_SCRATCH_BYTES (24 << 20)
+#define LCD_NOALLOC_MAX_SETS 65536
+#define LCD_NOALLOC_MAX_SCALES 1024
+#define LCD_NOALLOC_MAX_SEED_SET 4096
+#define LCD_NOALLOC_TABLE_ENTRIES 16384
+#define LCD_NOALLOC_TABLES 32
+lcd_status lcd_sweep_into(const lcd_graph *g, const double *scales, int32_t n_scales,
+                          const int32_t *seed_ptr, const int32_t *seed_nodes, int32_t n_sets,
+                          int64_t n_seed_nodes, const lcd_params *params, int64_t *rec_off,
+                          int32_t *rec_cnt, int64_t *rec_k, int64_t *rec_v, double *rec_f,
+                          uint64_t *rec_ctr, int32_t *members, int64_t members_cap,
+                          int64_t *members_used, void *stream);
+
 /* Result of lcd_tune(). */
 typedef struct {
     lcd_params best;          /* the chosen sizing (the graph keeps it) */

@@ -7,7 +7,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", f) for f in ("lcd_api.hip", "lcd_kernels.hip", "lcd_server.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("lcd_api.hip", "lcd_kernels.hip", "lcd_server.hip",
+                                                "lcd_noalloc.hip")]
 LIB = os.path.join(HERE, "liblcd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -169,6 +169,9 @@ def library() -> ctypes.CDLL:
         "lcd_result_nmi_successive": (st, [P, ctypes.c_int32, P, P]),
         "lcd_result_nmi_cover": (st, [P, ctypes.c_int32, ctypes.c_int32, P, P,
                                       ctypes.POINTER(ctypes.c_double), P]),
+        "lcd_sweep_into": (st, [P, P, ctypes.c_int32, P, P, ctypes.c_int32, ctypes.c_int64,
+                                ctypes.POINTER(lcd_params), P, P, P, P, P, P, P, ctypes.c_int64,
+                                ctypes.POINTER(ctypes.c_int64), P]),
         "lcd_last_error": (ctypes.c_char_p, []),
         "lcd_version": (ctypes.c_char_p, []),
     }
@@ -566,6 +569,39 @@ def lcd_cover_nmi(n: int, cover_x, cover_y) -> float:
     _check(library().lcd_cover_nmi(int(n), int(px.numel()) - 1, _ptr(px), _ptr(mx), int(py.numel()) - 1,
                                    _ptr(py), _ptr(my), ctypes.byref(out), _stream()), "lcd_cover_nmi")
     return out.value
+
+
+def lcd_sweep_into(graph: "Graph", scales, seed_ptr, seed_nodes, members_cap: int, out: Optional[dict] = None,
+                   params: Optional[lcd_params] = None, **kw) -> dict:
+    """lcd_sweep_into: the sweep with caller-owned device outputs and no
+    allocation inside the library.  ``out`` may hold the output tensors
+    (rec_off, rec_cnt, rec_k, rec_v, rec_f, rec_ctr, members) from an earlier
+    call of at least this size; missing ones are allocated here, by the
+    caller's side.  Returns the tensors and ``members_used``."""
+    sc = _dev(scales, torch.float64)
+    sp = _dev(seed_ptr, torch.int32)
+    sn = _dev(seed_nodes, torch.int32)
+    ns = int(sp.numel()) - 1
+    S = int(sc.numel())
+    R = max(ns * S, 1)
+    o = dict(out or {})
+    spec = dict(rec_off=(R, torch.int64), rec_cnt=(R, torch.int32), rec_k=(R, torch.int64),
+                rec_v=(R, torch.int64), rec_f=(R, torch.float64), rec_ctr=(4 * R, torch.int64),
+                members=(max(int(members_cap), 1), torch.int32))
+    for k, (size, dt) in spec.items():
+        if k not in o or o[k].numel() < size:
+            o[k] = torch.empty(size, dtype=dt, device="cuda")
+    if sn.numel() == 0:
+        sn = torch.zeros(1, dtype=torch.int32, device="cuda")
+    prm = params if params is not None else make_params(**kw)
+    used = ctypes.c_int64()
+    _check(library().lcd_sweep_into(graph._h, _ptr(sc), S, _ptr(sp), _ptr(sn), ns,
+                                    int(seed_ptr[-1]) if ns > 0 else 0, ctypes.byref(prm),
+                                    _ptr(o["rec_off"]), _ptr(o["rec_cnt"]), _ptr(o["rec_k"]), _ptr(o["rec_v"]),
+                                    _ptr(o["rec_f"]), _ptr(o["rec_ctr"]), _ptr(o["members"]), int(members_cap),
+                                    ctypes.byref(used), _stream()), "lcd_sweep_into")
+    o["members_used"] = used.value
+    return o
 
 
 def lcd_sweep_batch(graph: "Graph", scales, seed_ptr, seed_nodes, seed_graph, params=None, **kw):
