@@ -60,7 +60,8 @@ typedef enum {
     LCD_EDEVICE = 3,    /* a HIP call failed or a kernel reported an error */
     LCD_EAGAIN = 4,     /* result not ready yet (server poll) */
     LCD_ECAPACITY = 5,  /* a caller buffer or a fixed capacity is too small */
-    LCD_ESTATE = 6      /* the handle is not in a state that allows the call */
+    LCD_ESTATE = 6,     /* the handle is not in a state that allows the call */
+    LCD_ECANCELED = 7   /* a server query that lcd_server_cancel withdrew */
 } lcd_status;
 
 enum { LCD_MEM_HOST = 0, LCD_MEM_DEVICE = 1 };
@@ -69,6 +70,15 @@ enum { LCD_MEM_HOST = 0, LCD_MEM_DEVICE = 1 };
 enum {
     LCD_PERSISTENT = 0,     /* all scales and seed sets in one persistent launch */
     LCD_PER_SCALE_LOOP = 1  /* one launch per scale, state re-read from memory */
+};
+
+/* lcd_params.output_mode: how a sweep stores each (seed set, scale) community.
+ * Either way the readout calls return whole sorted member lists. */
+enum {
+    LCD_OUT_FULL = 0,   /* a scale where anything moved stores its sorted member list */
+    LCD_OUT_DELTA = 1   /* a set's first scale stores its sorted member list; every
+                           later scale only the sorted ids that joined and left since
+                           the scale before (lcd_result_delta reads them) */
 };
 
 typedef struct lcd_graph lcd_graph;
@@ -108,6 +118,10 @@ typedef struct {
                                 rank (a step looks at the queue's head, not the
                                 whole table); 0 = default (8,192); results never
                                 depend on it */
+    int32_t output_mode;     /* LCD_OUT_FULL (default) or LCD_OUT_DELTA: lcd_sweep and
+                                lcd_sweep_batch only (the other calls store full
+                                lists); it changes what the member pool holds, never
+                                the communities read back */
 } lcd_params;
 
 /* Work of one table tier (0 = one wave per community with an LDS table; the
@@ -423,6 +437,24 @@ lcd_status lcd_result_counters(const lcd_result *r, uint64_t *totals, uint64_t *
                                int32_t mem_kind, void *stream);
 
 /*
+ * What changed at one scale, for a sweep run with output_mode = LCD_OUT_DELTA
+ * (LCD_ESTATE otherwise).  Paper: Sec. 2 and Algorithm 2 (the community of
+ * one scale is the starting point of the next, so consecutive scales differ
+ * by the nodes the growth function added and removed).  For set j: the ids
+ * that joined its community between scale_idx - 1 and scale_idx at
+ * added[add_ptr[j] .. add_ptr[j+1]), those that left at
+ * removed[rem_ptr[j] .. rem_ptr[j+1]), each run ascending; at scale 0 (and at
+ * any scale stored as a full list) the whole community counts as added.
+ *   add_ptr, rem_ptr int64[n_sets+1]; added, removed int32 (sizes from
+ *   lcd_result_delta_sizes); all in mem_kind memory.
+ * Blocking.
+ */
+lcd_status lcd_result_delta_sizes(const lcd_result *r, int32_t scale_idx, int64_t *n_added,
+                                  int64_t *n_removed);
+lcd_status lcd_result_delta(const lcd_result *r, int32_t scale_idx, int64_t *add_ptr, int32_t *added,
+                            int64_t *rem_ptr, int32_t *removed, int32_t mem_kind, void *stream);
+
+/*
  * Every scale of selected seed sets, in host memory.  For the q-th id and
  * scale s (record o = q * n_scales + s): members[rec_off[o] .. +rec_cnt[o])
  * ascending, k_in[o], vol[o], f[o], ctr[4*o .. 4*o+4) (G, R, M, C).
@@ -532,6 +564,7 @@ typedef struct {
     int32_t max_lanes_busy;   /* most lanes with a batch on the device at once */
     int32_t spill_tables[2];  /* global-memory tables per spill lane, per global tier */
     int32_t pad;
+    int64_t cancelled;        /* queries withdrawn by lcd_server_cancel */
 } lcd_server_stats;
 
 /*
@@ -573,6 +606,17 @@ lcd_status lcd_server_poll(lcd_server *s, uint64_t ticket, int32_t *members, int
 /* Block until the ticket is done (LCD_OK) or timeout_ms passes (LCD_EAGAIN);
  * timeout_ms < 0 waits without limit.  Does not retire the ticket. */
 lcd_status lcd_server_wait(lcd_server *s, uint64_t ticket, int32_t timeout_ms);
+
+/*
+ * Withdraw a query.  Not part of the paper's method: serving plumbing for
+ * callers that no longer need an answer.  A query still waiting for a lane
+ * is dropped at once; one already on the device finishes there and its
+ * result is discarded.  Either way the ticket then ends with
+ * LCD_ECANCELED (poll retires it).  Returns LCD_OK when the query was
+ * withdrawn, LCD_ESTATE when it had already completed (its result stays
+ * available), LCD_EINVAL for an unknown ticket.  Thread-safe.
+ */
+lcd_status lcd_server_cancel(lcd_server *s, uint64_t ticket);
 
 lcd_status lcd_server_get_stats(lcd_server *s, lcd_server_stats *out);
 

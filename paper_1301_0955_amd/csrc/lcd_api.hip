@@ -498,6 +498,8 @@ void result_release(lcd_result *r) {
     dev_free(r->rec.V);
     dev_free(r->rec.f);
     dev_free(r->rec.ctr);
+    dev_free(r->rec.dadd);
+    dev_free(r->rec.drem);
     dev_free(r->pool);
     dev_free(r->ctl);
     dev_free(r->cursor);
@@ -834,6 +836,8 @@ lcd_status lcd_sweep(const lcd_graph *g, const double *scales, int32_t n_scales,
         prm.watchdog_ms = 20000;
     if (prm.grow_calls < 0)
         return fail(LCD_EINVAL, "grow_calls must be >= 0");
+    if (prm.output_mode != LCD_OUT_FULL && prm.output_mode != LCD_OUT_DELTA)
+        return fail(LCD_EINVAL, "unknown output_mode %d", prm.output_mode);
     apply_tuned(g, prm);
     hipStream_t st = (hipStream_t)stream;
     std::vector<double> sc;
@@ -895,7 +899,10 @@ lcd_status lcd_sweep(const lcd_graph *g, const double *scales, int32_t n_scales,
         (s = dev_alloc(&r->work[2], (size_t)std::max(n_sets, 1))) != LCD_OK ||
         (s = dev_alloc(&r->ordered[0], (size_t)std::max(n_sets, 1))) != LCD_OK ||
         (s = dev_alloc(&r->ordered[1], (size_t)std::max(n_sets, 1))) != LCD_OK ||
-        (s = dev_alloc(&r->ordered[2], (size_t)std::max(n_sets, 1))) != LCD_OK) {
+        (s = dev_alloc(&r->ordered[2], (size_t)std::max(n_sets, 1))) != LCD_OK ||
+        (prm.output_mode == LCD_OUT_DELTA &&
+         ((s = dev_alloc(&r->rec.dadd, std::max<size_t>(R, 1))) != LCD_OK ||
+          (s = dev_alloc(&r->rec.drem, std::max<size_t>(R, 1))) != LCD_OK))) {
         result_release(r);
         return s;
     }
@@ -921,6 +928,9 @@ lcd_status lcd_sweep(const lcd_graph *g, const double *scales, int32_t n_scales,
     *out = r;
     return LCD_OK;
 }
+
+// rounds of seed selection queued between two reads of the undecided count
+constexpr int32_t kSeedBatch = 64;
 
 lcd_status lcd_seeds(const lcd_graph *g, int32_t rule, const int32_t *perm, int32_t mem_kind, void *stream,
                      int32_t *out_seeds, int32_t *n_seeds) {
@@ -965,7 +975,7 @@ lcd_status lcd_seeds(const lcd_graph *g, int32_t rule, const int32_t *perm, int3
     if ((s = dev_alloc(&d_perm, n)) != LCD_OK || (s = dev_alloc(&pos, n)) != LCD_OK ||
         (s = dev_alloc(&flag, n)) != LCD_OK || (s = dev_alloc(&at, n)) != LCD_OK ||
         (s = dev_alloc(&bs, (size_t)nb + 1)) != LCD_OK || (s = dev_alloc(&stt, n)) != LCD_OK ||
-        (s = dev_alloc(&sel, n)) != LCD_OK || (s = dev_alloc(&cnt, 1)) != LCD_OK) {
+        (s = dev_alloc(&sel, n)) != LCD_OK || (s = dev_alloc(&cnt, kSeedBatch)) != LCD_OK) {
         release();
         return s;
     }
@@ -981,19 +991,25 @@ lcd_status lcd_seeds(const lcd_graph *g, int32_t rule, const int32_t *perm, int3
     if (e == hipSuccess)
         e = launch_seed_init(g->row_ptr, d_perm, n, pos, stt, st);
     // each round settles at least the first undecided candidate in visiting
-    // order, so at most n rounds run; usually a few dozen
+    // order, so at most n rounds run; usually a few dozen.  Rounds are queued
+    // in batches (4, 8, ... up to kSeedBatch): round k of a batch counts the
+    // undecided candidates into cnt[k] and does nothing once the round before
+    // counted none, and the host reads the batch's last count only.
     int64_t rounds = 0;
-    for (; e == hipSuccess && rounds <= (int64_t)n; ++rounds) {
+    bool settled = false;
+    for (int32_t batch = 4; e == hipSuccess && !settled && rounds <= (int64_t)n;
+         batch = std::min(2 * batch, kSeedBatch)) {
         unsigned undecided = 0;
-        e = launch_zero_bytes(cnt, 4, st);
+        e = launch_zero_bytes(cnt, 4 * (int64_t)batch, st);
+        for (int32_t k = 0; k < batch && e == hipSuccess; ++k)
+            e = launch_seed_round(rule, g->row_ptr, g->col, pos, stt, sel, n, k > 0 ? cnt + (k - 1) : nullptr,
+                                  cnt + k, st);
+        rounds += batch;
         if (e == hipSuccess)
-            e = launch_seed_round(rule, g->row_ptr, g->col, pos, stt, sel, n, cnt, st);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(&undecided, cnt, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+            e = hipMemcpyAsync(&undecided, cnt + (batch - 1), sizeof(unsigned), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess)
             e = hipStreamSynchronize(st);
-        if (e == hipSuccess && undecided == 0)
-            break;
+        settled = e == hipSuccess && undecided == 0;
     }
     int32_t total = 0;
     if (e == hipSuccess)
@@ -1007,8 +1023,8 @@ lcd_status lcd_seeds(const lcd_graph *g, int32_t rule, const int32_t *perm, int3
     release();
     if (e != hipSuccess)
         return fail(LCD_EDEVICE, "seed selection: %s", hipGetErrorString(e));
-    if (rounds > (int64_t)n)
-        return fail(LCD_EDEVICE, "seed selection did not settle in %d rounds", n);
+    if (!settled)
+        return fail(LCD_EDEVICE, "seed selection did not settle in %lld rounds", (long long)rounds);
     *n_seeds = total;
     return LCD_OK;
 }
@@ -1602,6 +1618,63 @@ lcd_status check_int32_total(int64_t total, int32_t scale_idx) {
     return LCD_OK;
 }
 
+// Sorted member lists of scale s at the offsets out_ptr (device) for the
+// listed sets (nullptr: every set, n = n_sets).  Full output copies them
+// from the pool (every set only); delta output rebuilds them on the device
+// from each set's records.
+lcd_status scale_members(const lcd_result *r, int32_t s, const int32_t *sets, int32_t n, const int32_t *out_ptr,
+                         int32_t *members, hipStream_t st) {
+    if (!r->rec.drem) {
+        if (sets)
+            return fail(LCD_ESTATE, "internal: listed sets need delta output");
+        const hipError_t e = launch_scale_gather(r->rec, r->pool, r->scales, r->S, s, r->n_sets, out_ptr, members,
+                                                 nullptr, nullptr, nullptr, st);
+        if (e != hipSuccess)
+            return fail(LCD_EDEVICE, "member readout: %s", hipGetErrorString(e));
+        return LCD_OK;
+    }
+    int64_t *ev = nullptr, *ev_off = nullptr;
+    uint32_t *err = nullptr;
+    int32_t *scr = nullptr;
+    int64_t total = 0;
+    uint32_t h_err = 0;
+    lcd_status x = LCD_OK;
+    hipError_t e = hipSuccess;
+    if ((x = dev_alloc(&ev, (size_t)std::max(n, 1))) != LCD_OK || (x = dev_alloc(&ev_off, (size_t)n + 1)) != LCD_OK ||
+        (x = dev_alloc(&err, 1)) != LCD_OK)
+        goto done;
+    e = launch_zero_bytes(err, 4, st);
+    if (e == hipSuccess)
+        e = launch_delta_events(r->rec, r->S, s, sets, n, ev, ev_off, err, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&total, ev_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        x = fail(LCD_EDEVICE, "delta readout: %s", hipGetErrorString(e));
+        goto done;
+    }
+    if ((x = dev_alloc(&scr, (size_t)std::max<int64_t>(total, 1))) != LCD_OK)
+        goto done;
+    e = launch_delta_rebuild(r->rec, r->pool, r->S, s, sets, n, ev_off, scr, out_ptr, members, err, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&h_err, err, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess)
+        x = fail(LCD_EDEVICE, "delta readout: %s", hipGetErrorString(e));
+    else if (h_err)
+        x = fail(LCD_EDEVICE, "delta readout of scale %d: %s", s,
+                 h_err & 1u ? "a set has no full member list before this scale"
+                            : "a rebuilt list disagrees with its recorded size");
+done:
+    dev_free(ev);
+    dev_free(ev_off);
+    dev_free(err);
+    dev_free(scr);
+    return x;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1666,9 +1739,11 @@ lcd_status lcd_result_membership(const lcd_result *r, int32_t scale_idx, int32_t
         vv = vol ? tmp_v : nullptr;
         ff = f ? tmp_f : nullptr;
     }
+    if (m && r->rec.drem && (s = scale_members(r, scale_idx, nullptr, r->n_sets, cp, m, st)) != LCD_OK)
+        goto done;
     {
         hipError_t e = launch_scale_gather(r->rec, r->pool, r->scales, r->S, scale_idx, r->n_sets, cp,
-                                           m, kk, vv, ff, st);
+                                           r->rec.drem ? nullptr : m, kk, vv, ff, st);
         if (e == hipSuccess && host) {
             if (comm_ptr)
                 e = hipMemcpyAsync(comm_ptr, cp, sizeof(int32_t) * (ns + 1), hipMemcpyDeviceToHost, st);
@@ -1726,10 +1801,9 @@ lcd_status lcd_result_overlap(const lcd_result *r, int32_t scale_idx, int32_t *n
         if ((s = dev_alloc(&np, (size_t)n + 1)) != LCD_OK || (s = dev_alloc(&nsets, (size_t)tot)) != LCD_OK)
             goto done;
     }
-    e = launch_scale_gather(r->rec, r->pool, r->scales, r->S, scale_idx, r->n_sets, cp, mem, nullptr,
-                            nullptr, nullptr, st);
-    if (e == hipSuccess)
-        e = launch_overlap(cp, mem, tot, r->n_sets, n, np, nsets, cnt, bs, st);
+    if ((s = scale_members(r, scale_idx, nullptr, r->n_sets, cp, mem, st)) != LCD_OK)
+        goto done;
+    e = launch_overlap(cp, mem, tot, r->n_sets, n, np, nsets, cnt, bs, st);
     if (e == hipSuccess && mem_kind == LCD_MEM_HOST) {
         e = hipMemcpyAsync(node_ptr, np, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess && tot)
@@ -1812,7 +1886,7 @@ lcd_status lcd_result_sets(const lcd_result *r, const int32_t *set_ids, int32_t 
         for (int32_t s = 0; s < S; ++s) {
             rec_off[o + s] = pos;
             rec_cnt[o + s] = cnt[s];
-            if (members && pos + cnt[s] <= members_cap && cnt[s] > 0)
+            if (!r->rec.drem && members && pos + cnt[s] <= members_cap && cnt[s] > 0)
                 HIPCHK(hipMemcpy(members + pos, r->pool + off[s], sizeof(int32_t) * (size_t)cnt[s],
                                  hipMemcpyDeviceToHost));
             pos += cnt[s];
@@ -1822,7 +1896,128 @@ lcd_status lcd_result_sets(const lcd_result *r, const int32_t *set_ids, int32_t 
     if (members && pos > members_cap)
         return fail(LCD_ECAPACITY, "members buffer holds %lld entries, %lld needed",
                     (long long)members_cap, (long long)pos);
+    if (r->rec.drem && members && n_ids > 0 && pos > 0) {
+        // delta output: every scale's lists rebuilt on the device straight
+        // to their places in one buffer, then one copy
+        if (pos > (int64_t)INT32_MAX)
+            return fail(LCD_ECAPACITY, "selected sets list %lld members; at most 2^31 - 1 per call", (long long)pos);
+        int32_t *d_ids = nullptr, *d_ptr = nullptr, *d_mem = nullptr;
+        std::vector<int32_t> ptr((size_t)n_ids);
+        lcd_status x = LCD_OK;
+        if ((x = dev_alloc(&d_ids, (size_t)n_ids)) != LCD_OK || (x = dev_alloc(&d_ptr, (size_t)n_ids)) != LCD_OK ||
+            (x = dev_alloc(&d_mem, (size_t)pos)) != LCD_OK) {
+            dev_free(d_ids);
+            dev_free(d_ptr);
+            return x;
+        }
+        hipError_t e = hipMemcpy(d_ids, set_ids, sizeof(int32_t) * (size_t)n_ids, hipMemcpyHostToDevice);
+        for (int32_t s = 0; s < S && e == hipSuccess && x == LCD_OK; ++s) {
+            for (int32_t q = 0; q < n_ids; ++q)
+                ptr[q] = (int32_t)rec_off[(size_t)q * S + s];
+            e = hipMemcpy(d_ptr, ptr.data(), sizeof(int32_t) * (size_t)n_ids, hipMemcpyHostToDevice);
+            if (e == hipSuccess)
+                x = scale_members(r, s, d_ids, n_ids, d_ptr, d_mem, nullptr);
+        }
+        if (e == hipSuccess && x == LCD_OK)
+            e = hipMemcpy(members, d_mem, sizeof(int32_t) * (size_t)pos, hipMemcpyDeviceToHost);
+        dev_free(d_ids);
+        dev_free(d_ptr);
+        dev_free(d_mem);
+        if (x != LCD_OK)
+            return x;
+        if (e != hipSuccess)
+            return fail(LCD_EDEVICE, "sets readout: %s", hipGetErrorString(e));
+    }
     return LCD_OK;
+}
+
+lcd_status lcd_result_delta_sizes(const lcd_result *r, int32_t scale_idx, int64_t *n_added, int64_t *n_removed) {
+    if (!r || !n_added || !n_removed)
+        return fail(LCD_EINVAL, "null argument");
+    if (scale_idx < 0 || scale_idx >= r->S)
+        return fail(LCD_EINVAL, "scale index %d out of range", scale_idx);
+    if (!r->rec.drem)
+        return fail(LCD_ESTATE, "the sweep stored full lists (output_mode LCD_OUT_DELTA gives deltas)");
+    const size_t n = (size_t)r->n_sets;
+    int64_t *na = nullptr, *nr = nullptr, *ao = nullptr, *ro = nullptr;
+    lcd_status x = LCD_OK;
+    int64_t h[2] = {0, 0};
+    if ((x = dev_alloc(&na, std::max<size_t>(n, 1))) == LCD_OK && (x = dev_alloc(&nr, std::max<size_t>(n, 1))) == LCD_OK &&
+        (x = dev_alloc(&ao, n + 1)) == LCD_OK && (x = dev_alloc(&ro, n + 1)) == LCD_OK) {
+        hipError_t e = launch_delta_lists(r->rec, r->pool, r->S, scale_idx, r->n_sets, na, nr, ao, ro, nullptr,
+                                          nullptr, nullptr);
+        if (e == hipSuccess)
+            e = hipMemcpy(&h[0], ao + n, sizeof(int64_t), hipMemcpyDeviceToHost);
+        if (e == hipSuccess)
+            e = hipMemcpy(&h[1], ro + n, sizeof(int64_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess)
+            x = fail(LCD_EDEVICE, "delta sizes: %s", hipGetErrorString(e));
+    }
+    dev_free(na);
+    dev_free(nr);
+    dev_free(ao);
+    dev_free(ro);
+    CHK(x);
+    *n_added = h[0];
+    *n_removed = h[1];
+    return LCD_OK;
+}
+
+lcd_status lcd_result_delta(const lcd_result *r, int32_t scale_idx, int64_t *add_ptr, int32_t *added,
+                            int64_t *rem_ptr, int32_t *removed, int32_t mem_kind, void *stream) {
+    if (!r || !add_ptr || !rem_ptr)
+        return fail(LCD_EINVAL, "null argument");
+    if (scale_idx < 0 || scale_idx >= r->S)
+        return fail(LCD_EINVAL, "scale index %d out of range", scale_idx);
+    if (mem_kind != LCD_MEM_HOST && mem_kind != LCD_MEM_DEVICE)
+        return fail(LCD_EINVAL, "unknown mem_kind %d", mem_kind);
+    if (!r->rec.drem)
+        return fail(LCD_ESTATE, "the sweep stored full lists (output_mode LCD_OUT_DELTA gives deltas)");
+    int64_t ta = 0, tr = 0;
+    CHK(lcd_result_delta_sizes(r, scale_idx, &ta, &tr));
+    if ((ta > 0 && !added) || (tr > 0 && !removed))
+        return fail(LCD_EINVAL, "null output");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t n = (size_t)r->n_sets;
+    const bool host = mem_kind == LCD_MEM_HOST;
+    int64_t *na = nullptr, *nr = nullptr, *ao = add_ptr, *ro = rem_ptr;
+    int32_t *da = added, *dr = removed;
+    lcd_status x = LCD_OK;
+    hipError_t e = hipSuccess;
+    if ((x = dev_alloc(&na, std::max<size_t>(n, 1))) != LCD_OK || (x = dev_alloc(&nr, std::max<size_t>(n, 1))) != LCD_OK)
+        goto done;
+    if (host) {
+        ao = ro = nullptr;
+        da = dr = nullptr;
+        if ((x = dev_alloc(&ao, n + 1)) != LCD_OK || (x = dev_alloc(&ro, n + 1)) != LCD_OK ||
+            (x = dev_alloc(&da, (size_t)std::max<int64_t>(ta, 1))) != LCD_OK ||
+            (x = dev_alloc(&dr, (size_t)std::max<int64_t>(tr, 1))) != LCD_OK)
+            goto done;
+    }
+    e = launch_delta_lists(r->rec, r->pool, r->S, scale_idx, r->n_sets, na, nr, ao, ro, da, dr, st);
+    if (e == hipSuccess && host) {
+        e = hipMemcpyAsync(add_ptr, ao, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(rem_ptr, ro, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && ta)
+            e = hipMemcpyAsync(added, da, sizeof(int32_t) * (size_t)ta, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && tr)
+            e = hipMemcpyAsync(removed, dr, sizeof(int32_t) * (size_t)tr, hipMemcpyDeviceToHost, st);
+    }
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess)
+        x = fail(LCD_EDEVICE, "delta readout: %s", hipGetErrorString(e));
+done:
+    dev_free(na);
+    dev_free(nr);
+    if (host) {
+        dev_free(ao);
+        dev_free(ro);
+        dev_free(da);
+        dev_free(dr);
+    }
+    return x;
 }
 
 }  // extern "C"
@@ -1897,12 +2092,8 @@ lcd_status scale_cover(const lcd_result *r, int32_t s, hipStream_t st, int32_t *
         x = check_int32_total(*tot, s);
     if (x == LCD_OK)
         x = dev_alloc(mem, (size_t)std::max<int64_t>(*tot, 1));
-    if (x == LCD_OK) {
-        const hipError_t e = launch_scale_gather(r->rec, r->pool, r->scales, r->S, s, r->n_sets, *ptr, *mem,
-                                                 nullptr, nullptr, nullptr, st);
-        if (e != hipSuccess)
-            x = fail(LCD_EDEVICE, "scale cover: %s", hipGetErrorString(e));
-    }
+    if (x == LCD_OK)
+        x = scale_members(r, s, nullptr, r->n_sets, *ptr, *mem, st);
     if (x != LCD_OK) {
         dev_free(*ptr);
         dev_free(*mem);

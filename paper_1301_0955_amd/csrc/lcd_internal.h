@@ -19,13 +19,22 @@ struct GraphDev {
 };
 
 // Per-record outputs; record r = set * S + s.
+//
+// Full output: the pool holds record r's sorted member list at off[r]
+// (cnt[r] ids; a scale where nothing moved shares the list before it).
+// Delta output (dadd, drem non-null): drem[r] < 0 marks a full sorted list
+// of cnt[r] ids at off[r] (the first scale a set grew from its seeds);
+// otherwise off[r] holds dadd[r] sorted ids that joined since record r - 1,
+// then drem[r] sorted ids that left.  cnt[r] is the member count either way.
 struct Records {
-    int64_t *off;             // member-pool offset of the sorted member list
+    int64_t *off;             // member-pool offset of the record's ids
     int32_t *cnt;             // number of members
     int64_t *K;               // k_in
     int64_t *V;               // k_in + k_out
     double *f;                // K / pow(V, alpha)
     uint64_t *ctr;            // G, R, M, C
+    int32_t *dadd;            // delta output: ids added (nullptr: full output)
+    int32_t *drem;            // delta output: ids removed, -1 for a full list
 };
 
 // Error bits written by the kernels.
@@ -81,6 +90,8 @@ struct SweepArgs {
     int32_t n_slots;          // global tiers: number of tables
     int64_t budget_ticks;     // watchdog: wall-clock ticks one seed set may take
     const double *alpha_set;  // query kernels: one scale per set (S = 1); nullptr for sweeps
+    uint32_t *done_flags;     // query kernels: set to 1 (system scope) once set j's record
+                              // and members are final; nullptr for none
     int32_t kind;             // TIER_* below: which kernel runs this tier
 };
 
@@ -128,6 +139,21 @@ hipError_t tier_blocks_per_cu(int32_t kind, int32_t waves, size_t lds_bytes, int
 // comm_ptr[0..n_sets] (int32, wraps past 2^31 - 1) and the exact total in *total
 hipError_t launch_scale_scan(const Records &rec, int32_t S, int32_t s, int32_t n_sets,
                              int32_t *comm_ptr, long long *total, hipStream_t st);
+// Delta output readout (see Records): ids per listed set in the records
+// that rebuild scale s (ev) and their exclusive prefix (ev_off, n + 1
+// entries; bit 1 of *err: a set without a full list); the rebuilt sorted
+// member lists at out_ptr offsets (scratch holds ev_off[n] ids; bit 2 of
+// *err: a count that disagrees with the record); and the added / removed
+// ids of scale s with their offsets (n + 1 entries each; a full list counts
+// as added; a null added or removed skips that side).
+hipError_t launch_delta_events(const Records &rec, int32_t S, int32_t s, const int32_t *sets, int32_t n,
+                               int64_t *ev, int64_t *ev_off, uint32_t *err, hipStream_t st);
+hipError_t launch_delta_rebuild(const Records &rec, const int32_t *pool, int32_t S, int32_t s,
+                                const int32_t *sets, int32_t n, const int64_t *ev_off, int32_t *scratch,
+                                const int32_t *out_ptr, int32_t *members, uint32_t *err, hipStream_t st);
+hipError_t launch_delta_lists(const Records &rec, const int32_t *pool, int32_t S, int32_t s, int32_t n,
+                              int64_t *na, int64_t *nr, int64_t *add_off, int64_t *rem_off, int32_t *added,
+                              int32_t *removed, hipStream_t st);
 hipError_t launch_scale_gather(const Records &rec, const int32_t *pool, const double *scales,
                                int32_t S, int32_t s, int32_t n_sets, const int32_t *comm_ptr,
                                int32_t *members, int64_t *k_in, int64_t *vol, double *f,
@@ -169,11 +195,13 @@ hipError_t launch_order_spills(const int32_t *in, const uint32_t *count, uint32_
 hipError_t launch_exclusive_scan(const int32_t *in, int64_t n, int32_t *out, int32_t *block_sums,
                                  hipStream_t st);
 // seed selection: pos/st setup, one selection round (adds the number of
-// undecided candidates at its start to *undecided), and the ordered output
+// undecided candidates at its start to *undecided; does nothing when prev
+// is non-null and *prev is 0), and the ordered output
 hipError_t launch_seed_init(const int32_t *row_ptr, const int32_t *perm, int32_t n, int32_t *pos,
                             uint8_t *st, hipStream_t s);
 hipError_t launch_seed_round(int32_t rule, const int32_t *row_ptr, const int32_t *col, const int32_t *pos,
-                             uint8_t *st, uint8_t *sel, int32_t n, unsigned *undecided, hipStream_t s);
+                             uint8_t *st, uint8_t *sel, int32_t n, const unsigned *prev, unsigned *undecided,
+                             hipStream_t s);
 hipError_t launch_seed_collect(const int32_t *perm, const uint8_t *st, int32_t n, int32_t *flag, int32_t *at,
                                int32_t *block_sums, int32_t *out, hipStream_t s);
 

@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "lcd_internal.h"
 
 namespace lcd {
@@ -35,10 +37,15 @@ namespace {
 
 constexpr double kMargin = 0x1p-40;   // improvement threshold on the log-fitness gain
 constexpr double kFilter = 1e-9;      // certified pre-test margin (see improves_add)
-constexpr uint32_t kDMask = (1u << 28) - 1;
+constexpr uint32_t kDMask = (1u << 27) - 1;   // d (weighted degrees stay below 2^27)
 constexpr uint32_t kMember = 1u << 31;
 constexpr uint32_t kLive = 1u << 30;
 constexpr uint32_t kFresh = 1u << 29;
+// delta output: member at the set's last emitted record
+constexpr uint32_t kWas = 1u << 28;
+// bucketed queue: re-ranked by the latest addition, not yet seen by a
+// fresh-list scan
+constexpr uint32_t kTouch = 1u << 27;
 
 // ---------------------------------------------------------------------------
 // L(x): natural log of an integer 1 <= x < 2^53.  x = m 2^e with m in
@@ -315,7 +322,7 @@ __device__ void row_update(const Tab &t, St &st, const Ctx &c, int32_t n, int la
                     const int32_t k = t.kv[idx];
                     t.rk[idx] = rank_of(c, d, k, st.alpha);
                     st.Rl += 1;
-                    t.dv[idx] = (uint32_t)d | kLive | kFresh;
+                    t.dv[idx] = (v & kWas) | (uint32_t)d | kLive | kFresh;
                 }
             }
         }
@@ -591,6 +598,53 @@ __device__ void wave_sort(int32_t *a, int32_t m, int lane) {
 
 // PERSET: each set carries its own scale (query batches, one record per
 // set); otherwise every set runs through scales[s_begin, s_end).
+// Delta output: the first scale of the set's last full list at or before
+// scale s_last (-1 if there is none), and the pool span of record r.
+__device__ __forceinline__ int32_t delta_key_scale(const Records &rec, int32_t S, int32_t set, int32_t s_last) {
+    int32_t sk = s_last;
+    while (sk >= 0 && rec.drem[(int64_t)set * S + sk] >= 0)
+        --sk;
+    return sk;
+}
+
+__device__ __forceinline__ int32_t record_len(const Records &rec, int64_t r) {
+    return rec.drem[r] < 0 ? rec.cnt[r] : rec.dadd[r] + rec.drem[r];
+}
+
+// Delta output, one wave: rebuild in the table the members recorded for
+// scale s_last by toggling kMember | kWas for every id of the last full
+// list and of each delta after it (an id joins and leaves alternately, so
+// the members are the ids seen an odd number of times).  False when a
+// record lies outside the pool (it overflowed: the host runs the sweep
+// again); no full list before s_last is an error (ERR_MISSING).
+template <bool GLOBAL>
+__device__ bool wave_toggle_records(const SweepArgs &A, const Tab &t, St &st, const Ctx &c, int32_t set,
+                                    int32_t s_last, int lane) {
+    const int32_t sk = delta_key_scale(A.rec, A.S, set, s_last);
+    if (sk < 0) {
+        st.err |= ERR_MISSING;
+        return true;
+    }
+    for (int32_t s = sk; s <= s_last; ++s) {
+        const int64_t r = (int64_t)set * A.S + s;
+        const int64_t off = A.rec.off[r];
+        const int32_t len = record_len(A.rec, r);
+        if (off < 0 || len < 0 || off + len > A.pool_cap)
+            return false;
+        for (int32_t base = 0; base < len; base += 64) {
+            const bool act = base + lane < len;
+            const int32_t u = act ? A.pool[off + base + lane] : 0;
+            const int32_t idx = tab_ensure<GLOBAL>(t, st, c, act, u, lane);
+            if (st.ovf)
+                return true;
+            if (act && idx >= 0)
+                t.dv[idx] ^= (kMember | kWas);
+            wsync<GLOBAL>();
+        }
+    }
+    return true;
+}
+
 template <bool GLOBAL, bool PERSET>
 __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
     Ctx c;
@@ -678,7 +732,28 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
         const int32_t *init = nullptr;
         int32_t n_init = 0;
         bool bad = false;
-        if (s0 > A.s_begin || A.resume) {
+        // delta output: the table's kWas flags hold the last record's members
+        bool keyed = false;
+        if ((s0 > A.s_begin || A.resume) && A.rec.drem) {
+            // the members of scale s0 - 1 from its full list and deltas,
+            // then gathered (any order) for the initialisation below
+            bad = !wave_toggle_records<GLOBAL>(A, t, st, c, set, s0 - 1, lane);
+            if (!bad && !st.ovf && !st.err) {
+                int32_t m = 0;
+                for (int32_t base = 0; base < st.count; base += 64) {
+                    const int32_t i = base + lane;
+                    const bool ism = i < st.count && (t.dv[i] & kMember);
+                    const uint64_t bm = __ballot(ism);
+                    if (ism)
+                        t.scr[m + __popcll(bm & lanes_below(lane))] = t.node[i];
+                    m += __popcll(bm);
+                }
+                wsync<GLOBAL>();
+                init = t.scr;
+                n_init = m;
+                keyed = true;
+            }
+        } else if (s0 > A.s_begin || A.resume) {
             const int64_t r = (int64_t)set * A.S + (s0 - 1);
             const int64_t off = A.rec.off[r];
             n_init = A.rec.cnt[r];
@@ -690,7 +765,7 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
             init = A.seed_nodes + A.seed_ptr[set];
             n_init = A.seed_ptr[set + 1] - A.seed_ptr[set];
         }
-        for (int32_t q = 0; q < n_init && !bad; ++q) {
+        for (int32_t q = 0; q < n_init && !bad && !st.ovf; ++q) {
             const int32_t u = init[q];
             const int32_t idx = tab_ensure<GLOBAL>(t, st, c, lane == 0, u, lane);
             if (st.ovf)
@@ -754,15 +829,59 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
             const int64_t r = (int64_t)set * A.S + s;
             const uint64_t G = wave_sum((uint64_t)st.Gl) + st.Gu;
             const uint64_t R = wave_sum((uint64_t)st.Rl);
-            if (s == s0 || moved > 0) {
-                // members, sorted, into the pool
+            int32_t dadd = 0, drem = 0;
+            if ((s == s0 || moved > 0) && keyed) {
+                // delta output: ids that joined (from the front of the
+                // scratch array) and left (from its back) since the last
+                // record, each run sorted, into the pool
+                int32_t na = 0, nr = 0;
+                for (int32_t base = 0; base < st.count; base += 64) {
+                    const int32_t i = base + lane;
+                    const uint32_t v = i < st.count ? t.dv[i] : 0u;
+                    const bool add = (v & kMember) && !(v & kWas);
+                    const bool rem = (v & kWas) && !(v & kMember);
+                    const uint64_t ba = __ballot(add);
+                    const uint64_t br = __ballot(rem);
+                    if (add)
+                        t.scr[na + __popcll(ba & lanes_below(lane))] = t.node[i];
+                    if (rem)
+                        t.scr[t.cap - 1 - (nr + __popcll(br & lanes_below(lane)))] = t.node[i];
+                    if (add || rem)
+                        t.dv[i] = v ^ kWas;
+                    na += __popcll(ba);
+                    nr += __popcll(br);
+                }
+                wsync<GLOBAL>();
+                wave_sort<GLOBAL>(t.scr, na, lane);
+                wave_sort<GLOBAL>(t.scr + (t.cap - nr), nr, lane);
+                unsigned long long off = 0;
+                if (lane == 0)
+                    off = atomicAdd(A.pool_cursor, (unsigned long long)(na + nr));
+                off = __shfl(off, 0);
+                if ((int64_t)off + na + nr <= A.pool_cap) {
+                    for (int32_t i = lane; i < na; i += 64)
+                        A.pool[off + i] = t.scr[i];
+                    for (int32_t i = lane; i < nr; i += 64)
+                        A.pool[off + na + i] = t.scr[t.cap - nr + i];
+                }
+                last_off = (int64_t)off;
+                last_cnt = st.nmem;
+                dadd = na;
+                drem = nr;
+                st.written += (uint64_t)(na + nr);
+            } else if (s == s0 || moved > 0) {
+                // members, sorted, into the pool (delta output: the set's
+                // full list, and kWas := kMember)
                 int32_t m = 0;
                 for (int32_t base = 0; base < st.count; base += 64) {
                     const int32_t i = base + lane;
-                    const bool ism = i < st.count && (t.dv[i] & kMember);
+                    const uint32_t v = i < st.count ? t.dv[i] : 0u;
+                    const bool ism = v & kMember;
                     const uint64_t bm = __ballot(ism);
                     if (ism)
                         t.scr[m + __popcll(bm & lanes_below(lane))] = t.node[i];
+                    if (A.rec.drem && i < st.count && ism != (bool)(v & kWas))
+                        t.dv[i] = v ^ kWas;
                     m += __popcll(bm);
                 }
                 wsync<GLOBAL>();
@@ -777,11 +896,21 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
                 }
                 last_off = (int64_t)off;
                 last_cnt = m;
+                dadd = m;
+                drem = -1;
+                keyed = A.rec.drem != nullptr;
                 st.written += (uint64_t)m;
+            } else if (keyed) {
+                // delta output, nothing moved: an empty delta
+                last_cnt = st.nmem;
             }
             if (lane == 0) {
                 A.rec.off[r] = last_off;
                 A.rec.cnt[r] = last_cnt;
+                if (A.rec.drem) {
+                    A.rec.dadd[r] = dadd;
+                    A.rec.drem[r] = drem;
+                }
                 A.rec.K[r] = st.K;
                 A.rec.V[r] = st.V;
                 A.rec.f[r] = st.K == 0 ? 0.0 : (double)st.K / pow((double)st.V, st.alpha);
@@ -789,6 +918,15 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
                 A.rec.ctr[4 * r + 1] = R;
                 A.rec.ctr[4 * r + 2] = st.M;
                 A.rec.ctr[4 * r + 3] = calls;
+            }
+            if constexpr (PERSET) {
+                // a query's record and members are final: publish them to
+                // the host (every lane's stores, then the flag)
+                if (A.done_flags) {
+                    __threadfence_system();
+                    if (lane == 0)
+                        __hip_atomic_store(&A.done_flags[set], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                }
             }
             st.c_mrows = st.mrows;
             st.c_mrow_len = st.mrow_len;
@@ -889,6 +1027,7 @@ struct TeamSh {
     unsigned long long off;
     int32_t count;    // dense entries claimed (may pass cap on overflow)
     int32_t m;        // members gathered for emission
+    int32_t m2;       // delta output: ids that left, gathered for emission
     int32_t bidx;     // broadcast dense index
     uint32_t item;
     uint32_t ovf;
@@ -896,6 +1035,8 @@ struct TeamSh {
     uint32_t abort;
     // rank-bucketed queue (global tables)
     int32_t flen;                       // fresh-list appends (may pass the capacity)
+    uint32_t ev;                        // the chosen addition's d|flags and degree
+    int32_t ek;
     int32_t bstart[kBuckets + 1];       // queue positions of each bucket
     uint32_t fill[kBuckets];            // bucket counts, then fill cursors
     double r2[2 * kTeamMaxWaves];       // more reduction slots
@@ -1021,10 +1162,14 @@ __device__ void team_row(const Tab &t, TeamSh &sh, St &st, const Ctx &c, const T
                 if (v & kMember) {
                     t.dv[idx] = (v & ~kDMask) | (uint32_t)d;
                 } else if (GLOBAL && bqm) {
-                    // bucketed queue: popped entries are marked, and an entry
-                    // whose rank changes moves to the fresh list (its queue
-                    // slot is stale while kFresh is set)
-                    if (!(v & kLive))
+                    // bucketed queue: queue entries are popped eagerly (flag
+                    // cleared); fresh-list entries ranked above the addition
+                    // just made were popped before it, which the next
+                    // fresh-list scan applies.  An entry whose rank changes
+                    // moves to the fresh list (its queue slot is stale while
+                    // kFresh is set), marked kTouch until that scan.
+                    const bool popped = !(v & kLive) || ((v & kFresh) && before(t.rk[idx], u, st.pr, st.pu));
+                    if (popped)
                         st.Gl += 1;
                     const int32_t k = t.kv[idx];
                     t.rk[idx] = rank_of(c, d, k, st.alpha);
@@ -1034,7 +1179,7 @@ __device__ void team_row(const Tab &t, TeamSh &sh, St &st, const Ctx &c, const T
                         if (pos < t.cap)
                             t.fr[pos] = idx;
                     }
-                    t.dv[idx] = (uint32_t)d | kLive | kFresh;
+                    t.dv[idx] = (v & kWas) | (uint32_t)d | kLive | kFresh | kTouch;
                 } else {
                     const bool queued = (v & kLive) && !before(t.rk[idx], u, st.pr, st.pu);
                     if (!queued)
@@ -1042,7 +1187,7 @@ __device__ void team_row(const Tab &t, TeamSh &sh, St &st, const Ctx &c, const T
                     const int32_t k = t.kv[idx];
                     t.rk[idx] = rank_of(c, d, k, st.alpha);
                     st.Rl += 1;
-                    t.dv[idx] = (uint32_t)d | kLive | kFresh;
+                    t.dv[idx] = (v & kWas) | (uint32_t)d | kLive | kFresh;
                 }
             }
         }
@@ -1334,13 +1479,25 @@ __device__ __forceinline__ void team_window(TeamSh &sh, const TeamId &id, double
     __syncthreads();
 }
 
+// Which queued entries a build pops first: those that pop before the last
+// addition (pr, pu) and were not re-ranked by it.  After lazy-scan
+// additions that is an entry without kFresh; in the bucketed queue, a
+// fresh-list entry without kTouch.
+enum { POP_LAZY_SCAN = 1, POP_FRESH_LIST = 2 };
+
+__device__ __forceinline__ bool build_pops(uint32_t v, int pop_mode) {
+    if (pop_mode == POP_LAZY_SCAN)
+        return !(v & kFresh);
+    if (pop_mode == POP_FRESH_LIST)
+        return (v & kFresh) && !(v & kTouch);
+    return false;
+}
+
 // Counting-sort the queued entries into rank buckets, ranks in [rbot, rtop].
-// With pop_above, entries not re-ranked since (pr, pu) was added (no kFresh)
-// that pop before it are popped instead; entry `skip` (the addition in
-// progress) is left out.  Clears every kFresh flag and empties the fresh
-// list.
+// Entries that build_pops names and that pop before (pr, pu) are popped
+// instead.  Clears every kFresh and kTouch flag and empties the fresh list.
 __device__ void bq_build(const Tab &t, TeamSh &sh, St &st, const TeamId &id, BQ &q, double rtop,
-                         double rbot, bool pop_above, double pr, int32_t pu, int32_t skip) {
+                         double rbot, int pop_mode, double pr, int32_t pu) {
     q.rtop = rtop;
     q.scale = rtop > rbot ? (double)kBuckets / (rtop - rbot) : 0.0;
     st.scanned += 2 * (uint64_t)st.count;
@@ -1351,15 +1508,18 @@ __device__ void bq_build(const Tab &t, TeamSh &sh, St &st, const TeamId &id, BQ 
     __syncthreads();
     for (int32_t i = id.tid; i < st.count; i += id.nt) {
         const uint32_t v = t.dv[i];
-        if (!(v & kLive) || (v & kMember) || i == skip)
-            continue;
-        const double r = t.rk[i];
-        if (pop_above && !(v & kFresh) && before(r, t.node[i], pr, pu)) {
-            t.dv[i] = v & ~(kLive | kFresh);
+        if (!(v & kLive) || (v & kMember)) {
+            if (v & (kFresh | kTouch))
+                t.dv[i] = v & ~(kFresh | kTouch);   // a popped fresh-list entry
             continue;
         }
-        if (v & kFresh)
-            t.dv[i] = v & ~kFresh;
+        const double r = t.rk[i];
+        if (build_pops(v, pop_mode) && before(r, t.node[i], pr, pu)) {
+            t.dv[i] = v & ~(kLive | kFresh | kTouch);
+            continue;
+        }
+        if (v & (kFresh | kTouch))
+            t.dv[i] = v & ~(kFresh | kTouch);
         atomicAdd(&sh.fill[bucket_of(r, q)], 1u);
     }
     __syncthreads();
@@ -1393,7 +1553,7 @@ __device__ void bq_build(const Tab &t, TeamSh &sh, St &st, const TeamId &id, BQ 
     __syncthreads();
     for (int32_t i = id.tid; i < st.count; i += id.nt) {
         const uint32_t v = t.dv[i];
-        if (!(v & kLive) || (v & kMember) || i == skip)
+        if (!(v & kLive) || (v & kMember))
             continue;
         const uint32_t pos = atomicAdd(&sh.fill[bucket_of(t.rk[i], q)], 1u);
         t.sq[pos] = i;
@@ -1403,7 +1563,9 @@ __device__ void bq_build(const Tab &t, TeamSh &sh, St &st, const TeamId &id, BQ 
     q.cp = 0;
 }
 
-// Rebuild the queue from every queued entry (fresh ones included).
+// Rebuild the queue from every queued entry (fresh ones included), right
+// after an addition (st.pr, st.pu): the fresh-list pops still pending are
+// applied first.
 __device__ void bq_rebuild(const Tab &t, TeamSh &sh, St &st, const TeamId &id, BQ &q) {
     double lo = __builtin_huge_val(), hi = -__builtin_huge_val();
     st.scanned += (uint64_t)st.count;
@@ -1411,6 +1573,8 @@ __device__ void bq_rebuild(const Tab &t, TeamSh &sh, St &st, const TeamId &id, B
         const uint32_t v = t.dv[i];
         if ((v & kLive) && !(v & kMember)) {
             const double r = t.rk[i];
+            if (build_pops(v, POP_FRESH_LIST) && before(r, t.node[i], st.pr, st.pu))
+                continue;
             lo = fmin(lo, r);
             hi = fmax(hi, r);
         }
@@ -1418,7 +1582,41 @@ __device__ void bq_rebuild(const Tab &t, TeamSh &sh, St &st, const TeamId &id, B
     double r = -__builtin_huge_val();
     int32_t u = INT32_MAX, i = -1;
     team_max_range(sh, id, r, u, i, lo, hi);
-    bq_build(t, sh, st, id, q, hi, lo, false, 0.0, 0, -1);
+    bq_build(t, sh, st, id, q, hi, lo, POP_FRESH_LIST, st.pr, st.pu);
+}
+
+// Up to kScanAhead entries of an index list per thread (positions
+// j0 + q * nt below lim), all loads issued before any is used: the index
+// loads, then the entries' fields (i < 0: no entry).
+struct Batch {
+    int32_t i[kScanAhead];
+    uint32_t v[kScanAhead];
+    double r[kScanAhead];
+    int32_t u[kScanAhead];
+    int32_t k[kScanAhead];
+};
+
+__device__ __forceinline__ void load_batch(const Tab &t, const int32_t *list, int32_t j0, int32_t lim, int32_t nt,
+                                           Batch &b) {
+#pragma unroll
+    for (int q = 0; q < kScanAhead; ++q) {
+        const int32_t j = j0 + q * nt;
+        b.i[q] = j < lim ? list[j] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kScanAhead; ++q) {
+        b.v[q] = 0u;
+        b.r[q] = 0.0;
+        b.u[q] = 0;
+        b.k[q] = 0;
+        if (b.i[q] >= 0) {
+            const int32_t i = b.i[q];
+            b.v[q] = t.dv[i];
+            b.r[q] = t.rk[i];
+            b.u[q] = t.node[i];
+            b.k[q] = t.kv[i];
+        }
+    }
 }
 
 // Switch a call from lazy pops to the bucketed queue right after an
@@ -1433,7 +1631,7 @@ __device__ void bq_switch(const Tab &t, TeamSh &sh, St &st, const TeamId &id, BQ
         if (!(v & kLive) || (v & kMember))
             continue;
         const double r = t.rk[i];
-        if (!(v & kFresh) && before(r, t.node[i], st.pr, st.pu))
+        if (build_pops(v, POP_LAZY_SCAN) && before(r, t.node[i], st.pr, st.pu))
             continue;
         lo = fmin(lo, r);
         hi = fmax(hi, r);
@@ -1441,32 +1639,55 @@ __device__ void bq_switch(const Tab &t, TeamSh &sh, St &st, const TeamId &id, BQ
     double r = -__builtin_huge_val();
     int32_t u = INT32_MAX, i = -1;
     team_max_range(sh, id, r, u, i, lo, hi);
-    bq_build(t, sh, st, id, q, hi, lo, true, st.pr, st.pu, -1);
+    bq_build(t, sh, st, id, q, hi, lo, POP_LAZY_SCAN, st.pr, st.pu);
 }
 
 // The next addition: the entry the sequential queue would add next (the
 // first improving entry in rank order), popping every queued entry ranked
-// above it.  Returns its index, or -1 when no queued entry improves (all of
-// them are popped then); er, eu, ev, ek get its rank, id, d|flags, degree.
+// above it.  Returns its index, or -1 when no queued entry improves (every
+// queued entry is popped then); er, eu, ev, ek get its rank, id, d|flags,
+// degree.  The fresh list's pops are applied lazily: its scan drops the
+// entries that an addition did not re-rank and that rank above it (the
+// last addition is st.pr, st.pu).  A first window of at most one entry per
+// thread keeps its entry in registers for its pops.
 __device__ int32_t bq_step(const Tab &t, TeamSh &sh, St &st, const TeamId &id, BQ &q, double &er, int32_t &eu,
                            uint32_t &ev, int32_t &ek) {
     const int32_t flen = min(sh.flen, t.cap);
     st.scanned += (uint64_t)flen;
     double fr = -__builtin_huge_val();
     int32_t fu = INT32_MAX, fi = -1;
+    uint32_t my_fv = 0u;
+    int32_t my_fk = 0;
     for (int32_t j = id.tid; j < flen; j += id.nt) {
         const int32_t i = t.fr[j];
-        const uint32_t v = t.dv[i];
+        uint32_t v = t.dv[i];
         if ((v & (kLive | kFresh | kMember)) != (kLive | kFresh))
             continue;
         const double r = t.rk[i];
         const int32_t u = t.node[i];
-        if (before(r, u, fr, fu) && improves_add(st, (int32_t)(v & kDMask), t.kv[i])) {
+        const int32_t k = t.kv[i];
+        if (v & kTouch) {
+            v &= ~kTouch;
+            t.dv[i] = v;
+        } else if (before(r, u, st.pr, st.pu)) {
+            // popped before the last addition; it keeps kFresh (and its
+            // slot in the list), so that a later re-rank does not list it
+            // twice
+            t.dv[i] = v & ~kLive;
+            continue;
+        }
+        if (before(r, u, fr, fu) && improves_add(st, (int32_t)(v & kDMask), k)) {
             fr = r;
             fu = u;
             fi = i;
+            my_fv = v;
+            my_fk = k;
         }
     }
+    const int32_t my_fi = fi;
+    int32_t my_wi = -1;
+    uint32_t my_wv = 0u;
+    int32_t my_wk = 0;
     int32_t cp = q.cp;
     int32_t win = id.nt;
     bool first = true;
@@ -1483,8 +1704,15 @@ __device__ int32_t bq_step(const Tab &t, TeamSh &sh, St &st, const TeamId &id, B
                 b1 = b0 + 1;
             end = sh.bstart[b1];
         }
+        // a window of at most one entry per thread stays in registers
+        const bool cached = end - cp <= id.nt;
+        int32_t ci = -1;
+        uint32_t cv = 0u;
+        double cr = 0.0;
+        int32_t cu = 0;
         double wr = -__builtin_huge_val(), mr = 0.0;
         int32_t wu = INT32_MAX, wi = -1, mu = 0, mi = -1;
+        my_wi = -1;
         st.scanned += (uint64_t)(end - cp);
         for (int32_t j = cp + id.tid; j < end; j += id.nt) {
             const int32_t i = t.sq[j];
@@ -1493,17 +1721,25 @@ __device__ int32_t bq_step(const Tab &t, TeamSh &sh, St &st, const TeamId &id, B
                 continue;
             const double r = t.rk[i];
             const int32_t u = t.node[i];
+            const int32_t k = t.kv[i];
+            ci = i;
+            cv = v;
+            cr = r;
+            cu = u;
             if (mi < 0 || pops_after(r, u, mr, mu)) {
                 mr = r;
                 mu = u;
                 mi = i;
             }
-            if (before(r, u, wr, wu) && improves_add(st, (int32_t)(v & kDMask), t.kv[i])) {
+            if (before(r, u, wr, wu) && improves_add(st, (int32_t)(v & kDMask), k)) {
                 wr = r;
                 wu = u;
                 wi = i;
+                my_wv = v;
+                my_wk = k;
             }
         }
+        my_wi = wi;
         if (!first) {
             fr = -__builtin_huge_val();
             fu = INT32_MAX;
@@ -1533,13 +1769,18 @@ __device__ int32_t bq_step(const Tab &t, TeamSh &sh, St &st, const TeamId &id, B
             decided = true;
         }
         // pops in the window: entries ranked above the addition, or all
-        for (int32_t j = cp + id.tid; j < end; j += id.nt) {
-            const int32_t i = t.sq[j];
-            const uint32_t v = t.dv[i];
-            if ((v & (kLive | kFresh | kMember)) != kLive || i == e)
-                continue;
-            if (!decided || e < 0 || before(t.rk[i], t.node[i], er, eu))
-                t.dv[i] = v & ~kLive;
+        if (cached) {
+            if (ci >= 0 && ci != e && (!decided || e < 0 || before(cr, cu, er, eu)))
+                t.dv[ci] = cv & ~kLive;
+        } else {
+            for (int32_t j = cp + id.tid; j < end; j += id.nt) {
+                const int32_t i = t.sq[j];
+                const uint32_t v = t.dv[i];
+                if ((v & (kLive | kFresh | kMember)) != kLive || i == e)
+                    continue;
+                if (!decided || e < 0 || before(t.rk[i], t.node[i], er, eu))
+                    t.dv[i] = v & ~kLive;
+            }
         }
         if (decided)
             break;
@@ -1547,22 +1788,18 @@ __device__ int32_t bq_step(const Tab &t, TeamSh &sh, St &st, const TeamId &id, B
         win *= 2;
         __syncthreads();
     }
-    // pops in the fresh list
-    for (int32_t j = id.tid; j < flen; j += id.nt) {
-        const int32_t i = t.fr[j];
-        const uint32_t v = t.dv[i];
-        if ((v & (kLive | kFresh | kMember)) != (kLive | kFresh) || i == e)
-            continue;
-        if (e < 0 || before(t.rk[i], t.node[i], er, eu))
-            t.dv[i] = v & ~(kLive | kFresh);
-    }
     // buckets before the addition's hold only popped entries now
     q.cp = (e >= 0 && from_q) ? sh.bstart[bucket_of(er, q)] : cp;
-    if (e >= 0) {
-        ev = t.dv[e];
-        ek = t.kv[e];
+    // the thread that found the addition hands on its flags and degree
+    if (e >= 0 && (from_q ? my_wi == e : my_fi == e)) {
+        sh.ev = from_q ? my_wv : my_fv;
+        sh.ek = from_q ? my_wk : my_fk;
     }
     __syncthreads();
+    if (e >= 0) {
+        ev = sh.ev;
+        ek = sh.ek;
+    }
     return e;
 }
 
@@ -1584,7 +1821,7 @@ __device__ bool bq_additions(const Tab &t, TeamSh &sh, St &st, const Ctx &c, con
         // add bi; no thread reads its flags again before the row update's barriers
         const int32_t d = (int32_t)(v & kDMask);
         if (id.tid == 0)
-            t.dv[bi] = (v | kMember) & ~(kLive | kFresh);
+            t.dv[bi] = (v | kMember) & ~(kLive | kFresh | kTouch);
         st.K += 2 * (int64_t)d;
         st.V += k;
         st.nmem += 1;
@@ -1629,17 +1866,20 @@ __device__ bool removal_members(const Tab &t, TeamSh &sh, St &st, const Ctx &c, 
             int32_t cu = INT32_MAX;
             int32_t ci = -1;
             st.scanned += (uint64_t)ml;
-            for (int32_t j = id.tid; j < ml; j += id.nt) {
-                const int32_t i = t.scr[j];
-                const uint32_t vm = t.dv[i];
-                if (!(vm & kMember))
-                    continue;
-                const int32_t u = t.node[i];
-                if (u <= cursor || u >= cu)
-                    continue;
-                if (improves_remove(st, (int32_t)(vm & kDMask), t.kv[i])) {
-                    cu = u;
-                    ci = i;
+            for (int32_t j0 = id.tid; j0 < ml; j0 += kScanAhead * id.nt) {
+                Batch b;
+                load_batch(t, t.scr, j0, ml, id.nt, b);
+#pragma unroll
+                for (int x = 0; x < kScanAhead; ++x) {
+                    if (b.i[x] < 0 || !(b.v[x] & kMember))
+                        continue;
+                    const int32_t u = b.u[x];
+                    if (u <= cursor || u >= cu)
+                        continue;
+                    if (improves_remove(st, (int32_t)(b.v[x] & kDMask), b.k[x])) {
+                        cu = u;
+                        ci = b.i[x];
+                    }
                 }
             }
             uint32_t vm = 0;
@@ -1717,15 +1957,15 @@ __device__ int64_t team_grow(const Tab &t, TeamSh &sh, St &st, const Ctx &c, con
                 if (creation) {
                     // the queue is built from every non-member with a link into c
                     if ((v & kMember) || (v & kDMask) == 0) {
-                        if (v & (kLive | kFresh))
-                            t.dv[i] = v & ~(kLive | kFresh);
+                        if (v & (kLive | kFresh | kTouch))
+                            t.dv[i] = v & ~(kLive | kFresh | kTouch);
                         continue;
                     }
                     r = rank_of(c, (int32_t)(v & kDMask), kk[q], st.alpha);
                     t.rk[i] = r;
                     st.Rl += 1;
                     st.Gl += 1;
-                    v = (v | kLive) & ~kFresh;
+                    v = (v | kLive) & ~(kFresh | kTouch);
                     t.dv[i] = v;
                 } else {
                     if (!(v & kLive))
@@ -1796,6 +2036,42 @@ __device__ int64_t team_grow(const Tab &t, TeamSh &sh, St &st, const Ctx &c, con
     return moves;
 }
 
+// One compare-exchange round of the bitonic network over a[0..m): pair q
+// of the round compares positions (i, l); kScanAhead pairs per thread with
+// all loads issued first (the pairs of a round are disjoint).
+template <typename PairOf>
+__device__ __forceinline__ void team_sort_round(int32_t *a, int32_t m, int32_t half_n, const TeamId &id,
+                                                PairOf pair_of) {
+    for (int32_t q0 = id.tid; q0 < half_n; q0 += kScanAhead * id.nt) {
+        int32_t ii[kScanAhead], ll[kScanAhead], xx[kScanAhead], yy[kScanAhead];
+#pragma unroll
+        for (int x = 0; x < kScanAhead; ++x) {
+            const int32_t q = q0 + x * id.nt;
+            ii[x] = -1;
+            ll[x] = -1;
+            if (q < half_n) {
+                pair_of(q, ii[x], ll[x]);
+                if (ll[x] >= m)
+                    ii[x] = -1;
+            }
+            xx[x] = 0;
+            yy[x] = 0;
+            if (ii[x] >= 0) {
+                xx[x] = a[ii[x]];
+                yy[x] = a[ll[x]];
+            }
+        }
+#pragma unroll
+        for (int x = 0; x < kScanAhead; ++x) {
+            if (ii[x] >= 0 && xx[x] > yy[x]) {
+                a[ii[x]] = yy[x];
+                a[ll[x]] = xx[x];
+            }
+        }
+    }
+    __syncthreads();
+}
+
 // Ascending sort of a[0..m) by the workgroup (same network as wave_sort).
 __device__ void team_sort(int32_t *a, int32_t m, const TeamId &id) {
     int32_t P = 1;
@@ -1804,35 +2080,51 @@ __device__ void team_sort(int32_t *a, int32_t m, const TeamId &id) {
     const int32_t half_n = P >> 1;
     for (int32_t k = 2; k <= P; k <<= 1) {
         const int32_t hk = k >> 1;
-        for (int32_t q = id.tid; q < half_n; q += id.nt) {
+        team_sort_round(a, m, half_n, id, [=](int32_t q, int32_t &i, int32_t &l) {
             const int32_t blk = q / hk;
             const int32_t off = q - blk * hk;
-            const int32_t i = blk * k + off;
-            const int32_t l = blk * k + k - 1 - off;
-            if (l < m) {
-                const int32_t x = a[i], y = a[l];
-                if (x > y) {
-                    a[i] = y;
-                    a[l] = x;
-                }
-            }
-        }
-        __syncthreads();
+            i = blk * k + off;
+            l = blk * k + k - 1 - off;
+        });
         for (int32_t j = k >> 2; j >= 1; j >>= 1) {
-            for (int32_t q = id.tid; q < half_n; q += id.nt) {
-                const int32_t i = (q / j) * 2 * j + (q % j);
-                const int32_t l = i + j;
-                if (l < m) {
-                    const int32_t x = a[i], y = a[l];
-                    if (x > y) {
-                        a[i] = y;
-                        a[l] = x;
-                    }
-                }
+            team_sort_round(a, m, half_n, id, [=](int32_t q, int32_t &i, int32_t &l) {
+                i = (q / j) * 2 * j + (q % j);
+                l = i + j;
+            });
+        }
+    }
+}
+
+// Delta output, one workgroup: wave_toggle_records for the workgroup.
+template <bool GLOBAL>
+__device__ bool team_toggle_records(const SweepArgs &A, const Tab &t, TeamSh &sh, St &st, const Ctx &c,
+                                    const TeamId &id, int32_t set, int32_t s_last) {
+    const int32_t sk = delta_key_scale(A.rec, A.S, set, s_last);
+    if (sk < 0) {
+        st.err |= ERR_MISSING;
+        return true;
+    }
+    for (int32_t s = sk; s <= s_last; ++s) {
+        const int64_t r = (int64_t)set * A.S + s;
+        const int64_t off = A.rec.off[r];
+        const int32_t len = record_len(A.rec, r);
+        if (off < 0 || len < 0 || off + len > A.pool_cap)
+            return false;
+        for (int32_t base = 0; base < len; base += id.nt) {
+            const bool act = base + id.tid < len;
+            const int32_t u = act ? A.pool[off + base + id.tid] : 0;
+            const int32_t idx = team_ensure<GLOBAL>(t, sh, st, c, act, u);
+            if (sh.ovf) {
+                st.ovf = true;
+                return true;
             }
+            if (act && idx >= 0)
+                t.dv[idx] ^= (kMember | kWas);
+            st.count = min(sh.count, t.cap);
             __syncthreads();
         }
     }
+    return true;
 }
 
 template <bool GLOBAL, bool PERSET>
@@ -1898,7 +2190,24 @@ __device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh) {
         const int32_t *init = nullptr;
         int32_t n_init = 0;
         bool bad = false;
-        if (s0 > A.s_begin || A.resume) {
+        bool keyed = false;   // delta output (see run_wave)
+        if ((s0 > A.s_begin || A.resume) && A.rec.drem) {
+            bad = !team_toggle_records<GLOBAL>(A, t, sh, st, c, id, set, s0 - 1);
+            st.err = team_or(sh, id, st.err);
+            if (!bad && !st.ovf && !st.err) {
+                if (id.tid == 0)
+                    sh.m = 0;
+                __syncthreads();
+                for (int32_t i = id.tid; i < st.count; i += id.nt) {
+                    if (t.dv[i] & kMember)
+                        t.scr[atomicAdd(&sh.m, 1)] = t.node[i];
+                }
+                __syncthreads();
+                init = t.scr;
+                n_init = sh.m;
+                keyed = true;
+            }
+        } else if (s0 > A.s_begin || A.resume) {
             const int64_t r = (int64_t)set * A.S + (s0 - 1);
             const int64_t off = A.rec.off[r];
             n_init = A.rec.cnt[r];
@@ -1910,7 +2219,7 @@ __device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh) {
             init = A.seed_nodes + A.seed_ptr[set];
             n_init = A.seed_ptr[set + 1] - A.seed_ptr[set];
         }
-        for (int32_t q = 0; q < n_init && !bad; ++q) {
+        for (int32_t q = 0; q < n_init && !bad && !st.ovf; ++q) {
             const int32_t u = init[q];
             const int32_t idx = team_ensure<GLOBAL>(t, sh, st, c, id.tid == 0, u);
             if (sh.ovf) {
@@ -1979,15 +2288,58 @@ __device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh) {
             const int64_t r = (int64_t)set * A.S + s;
             const uint64_t G = team_sum(sh, id, (uint64_t)st.Gl) + st.Gu;
             const uint64_t R = team_sum(sh, id, (uint64_t)st.Rl);
-            if (s == s0 || moved > 0) {
+            int32_t dadd = 0, drem = 0;
+            if ((s == s0 || moved > 0) && keyed) {
+                // delta output (see run_wave)
+                if (id.tid == 0) {
+                    sh.m = 0;
+                    sh.m2 = 0;
+                }
+                __syncthreads();
+                for (int32_t i = id.tid; i < st.count; i += id.nt) {
+                    const uint32_t v = t.dv[i];
+                    const bool add = (v & kMember) && !(v & kWas);
+                    const bool rem = (v & kWas) && !(v & kMember);
+                    if (add)
+                        t.scr[atomicAdd(&sh.m, 1)] = t.node[i];
+                    if (rem)
+                        t.scr[t.cap - 1 - atomicAdd(&sh.m2, 1)] = t.node[i];
+                    if (add || rem)
+                        t.dv[i] = v ^ kWas;
+                }
+                __syncthreads();
+                const int32_t na = sh.m, nr = sh.m2;
+                team_sort(t.scr, na, id);
+                team_sort(t.scr + (t.cap - nr), nr, id);
+                if (id.tid == 0)
+                    sh.off = atomicAdd(A.pool_cursor, (unsigned long long)(na + nr));
+                __syncthreads();
+                const unsigned long long off = sh.off;
+                if ((int64_t)off + na + nr <= A.pool_cap) {
+                    for (int32_t i = id.tid; i < na; i += id.nt)
+                        A.pool[off + i] = t.scr[i];
+                    for (int32_t i = id.tid; i < nr; i += id.nt)
+                        A.pool[off + na + i] = t.scr[t.cap - nr + i];
+                }
+                last_off = (int64_t)off;
+                last_cnt = st.nmem;
+                dadd = na;
+                drem = nr;
+                st.written += (uint64_t)(na + nr);
+                __syncthreads();
+            } else if (s == s0 || moved > 0) {
                 if (id.tid == 0)
                     sh.m = 0;
                 __syncthreads();
                 for (int32_t i = id.tid; i < st.count; i += id.nt) {
-                    if (t.dv[i] & kMember) {
+                    const uint32_t v = t.dv[i];
+                    const bool ism = v & kMember;
+                    if (ism) {
                         const int32_t p = atomicAdd(&sh.m, 1);
                         t.scr[p] = t.node[i];
                     }
+                    if (A.rec.drem && ism != (bool)(v & kWas))
+                        t.dv[i] = v ^ kWas;
                 }
                 __syncthreads();
                 const int32_t m = sh.m;
@@ -2002,12 +2354,21 @@ __device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh) {
                 }
                 last_off = (int64_t)off;
                 last_cnt = m;
+                dadd = m;
+                drem = -1;
+                keyed = A.rec.drem != nullptr;
                 st.written += (uint64_t)m;
                 __syncthreads();
+            } else if (keyed) {
+                last_cnt = st.nmem;
             }
             if (id.tid == 0) {
                 A.rec.off[r] = last_off;
                 A.rec.cnt[r] = last_cnt;
+                if (A.rec.drem) {
+                    A.rec.dadd[r] = dadd;
+                    A.rec.drem[r] = drem;
+                }
                 A.rec.K[r] = st.K;
                 A.rec.V[r] = st.V;
                 A.rec.f[r] = st.K == 0 ? 0.0 : (double)st.K / pow((double)st.V, st.alpha);
@@ -2015,6 +2376,15 @@ __device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh) {
                 A.rec.ctr[4 * r + 1] = R;
                 A.rec.ctr[4 * r + 2] = st.M;
                 A.rec.ctr[4 * r + 3] = calls;
+            }
+            if constexpr (PERSET) {
+                // see run_wave: every thread's stores, then the flag
+                if (A.done_flags) {
+                    __threadfence_system();
+                    __syncthreads();
+                    if (id.tid == 0)
+                        __hip_atomic_store(&A.done_flags[set], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                }
             }
             st.c_mrows = st.mrows;
             st.c_mrow_len = st.mrow_len;
@@ -2205,6 +2575,156 @@ __global__ void __launch_bounds__(256) scale_gather_kernel(Records rec, const in
     }
 }
 
+// Delta output readout.  The members of scale s of a set are the ids that
+// occur an odd number of times among the ids of its records from its last
+// full list at or before s through s (every id alternately joins and
+// leaves).  sets: listed set ids (nullptr: set q for q < n).
+
+// Per listed set: ids in those records (ev[q]); a set with no full list
+// before s sets bit 1 of *err.
+__global__ void delta_events_kernel(Records rec, int32_t S, int32_t s, const int32_t *sets, int32_t n,
+                                    int64_t *ev, uint32_t *err) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t set = sets ? sets[q] : (int32_t)q;
+        const int32_t sk = delta_key_scale(rec, S, set, s);
+        int64_t e = 0;
+        if (sk < 0)
+            atomicOr(err, 1u);
+        else
+            for (int32_t x = sk; x <= s; ++x)
+                e += record_len(rec, (int64_t)set * S + x);
+        ev[q] = e;
+    }
+}
+
+// Exclusive prefix sums of x[0..n) into out[0..n] (one block).
+__global__ void __launch_bounds__(1024) scan_i64_kernel(const int64_t *x, int64_t n, int64_t *out) {
+    __shared__ int64_t part[1024];
+    const int tid = threadIdx.x;
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t lo = tid * per;
+    const int64_t hi = lo + per < n ? lo + per : n;
+    int64_t sum = 0;
+    for (int64_t j = lo; j < hi; ++j)
+        sum += x[j];
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int64_t run = part[tid] - sum;
+    for (int64_t j = lo; j < hi; ++j) {
+        const int64_t v = x[j];
+        out[j] = run;
+        run += v;
+    }
+    if (tid == 1023)
+        out[n] = part[1023];
+}
+
+// One workgroup per listed set: its records' ids into scratch[ev_off[q]..),
+// sorted, then the ids of odd multiplicity, in order, to
+// members[out_ptr[q]..).  A count other than the record's sets bit 2 of
+// *err.
+__global__ void __launch_bounds__(256) delta_rebuild_kernel(Records rec, const int32_t *pool, int32_t S,
+                                                            int32_t s, const int32_t *sets, int32_t n,
+                                                            const int64_t *ev_off, int32_t *scratch,
+                                                            const int32_t *out_ptr, int32_t *members,
+                                                            uint32_t *err) {
+    TeamId id;
+    id.tid = (int)threadIdx.x;
+    id.nt = (int)blockDim.x;
+    id.lane = id.tid & 63;
+    id.wid = id.tid >> 6;
+    id.nw = id.nt >> 6;
+    __shared__ int32_t wcount[kTeamMaxWaves];
+    for (int64_t q = blockIdx.x; q < n; q += gridDim.x) {
+        const int32_t set = sets ? sets[q] : (int32_t)q;
+        const int32_t sk = delta_key_scale(rec, S, set, s);
+        if (sk < 0)
+            continue;   // reported by delta_events_kernel
+        int32_t *a = scratch + ev_off[q];
+        int64_t pos = 0;
+        for (int32_t x = sk; x <= s; ++x) {
+            const int64_t r = (int64_t)set * S + x;
+            const int64_t off = rec.off[r];
+            const int32_t len = record_len(rec, r);
+            for (int32_t i = id.tid; i < len; i += id.nt)
+                a[pos + i] = pool[off + i];
+            pos += len;
+        }
+        const int32_t E = (int32_t)pos;
+        __syncthreads();
+        team_sort(a, E, id);
+        int32_t outn = 0;
+        const int32_t dst = out_ptr[q];
+        for (int32_t base = 0; base < E; base += id.nt) {
+            const int32_t p = base + id.tid;
+            bool keep = false;
+            if (p < E && (p == 0 || a[p - 1] != a[p])) {
+                int32_t L = 1;
+                while (p + L < E && a[p + L] == a[p])
+                    ++L;
+                keep = (L & 1) != 0;
+            }
+            const uint64_t bm = __ballot(keep);
+            if (id.lane == 0)
+                wcount[id.wid] = __popcll(bm);
+            __syncthreads();
+            int32_t before_w = 0, total = 0;
+            for (int w = 0; w < id.nw; ++w) {
+                if (w < id.wid)
+                    before_w += wcount[w];
+                total += wcount[w];
+            }
+            if (keep)
+                members[dst + outn + before_w + __popcll(bm & lanes_below(id.lane))] = a[p];
+            outn += total;
+            __syncthreads();
+        }
+        if (id.tid == 0 && outn != rec.cnt[(int64_t)set * S + s])
+            atomicOr(err, 2u);
+        __syncthreads();
+    }
+}
+
+// Per set: the ids added and removed at scale s (a full list counts as
+// added), their counts first.
+__global__ void delta_counts_kernel(Records rec, int32_t S, int32_t s, int32_t n, int64_t *na, int64_t *nr) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = j * S + s;
+        const bool full = rec.drem[r] < 0;
+        na[j] = full ? rec.cnt[r] : rec.dadd[r];
+        nr[j] = full ? 0 : rec.drem[r];
+    }
+}
+
+__global__ void __launch_bounds__(256) delta_gather_kernel(Records rec, const int32_t *pool, int32_t S,
+                                                           int32_t s, int32_t n, const int64_t *add_off,
+                                                           int32_t *added, const int64_t *rem_off,
+                                                           int32_t *removed) {
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (j >= n)
+        return;
+    const int64_t r = j * S + s;
+    const int64_t off = rec.off[r];
+    const int32_t a = (int32_t)(add_off[j + 1] - add_off[j]);
+    const int32_t m = (int32_t)(rem_off[j + 1] - rem_off[j]);
+    if (added)
+        for (int32_t i = lane; i < a; i += 64)
+            added[add_off[j] + i] = pool[off + i];
+    if (removed)
+        for (int32_t i = lane; i < m; i += 64)
+            removed[rem_off[j] + i] = pool[off + a + i];
+}
+
 __global__ void overlap_count_kernel(const int32_t *members, int64_t total, int32_t *cnt) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -2232,9 +2752,15 @@ __global__ void seed_init_kernel(const int32_t *row_ptr, const int32_t *perm, in
     }
 }
 
+// A round whose previous round counted no undecided candidate (*prev == 0)
+// does nothing, so that the host can queue many rounds and read the count
+// once.
 template <int R>
 __global__ void seed_select_kernel(const int32_t *row_ptr, const int32_t *col, const int32_t *pos,
-                                   const uint8_t *st, uint8_t *sel, int32_t n, unsigned *undecided) {
+                                   const uint8_t *st, uint8_t *sel, int32_t n, const unsigned *prev,
+                                   unsigned *undecided) {
+    if (prev && *prev == 0u)
+        return;
     unsigned cnt = 0;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
@@ -2266,7 +2792,9 @@ __global__ void seed_select_kernel(const int32_t *row_ptr, const int32_t *col, c
 // below is the same value from whichever thread makes it.
 template <int R>
 __global__ void seed_apply_kernel(const int32_t *row_ptr, const int32_t *col, const uint8_t *sel,
-                                  uint8_t *st, int32_t n) {
+                                  uint8_t *st, int32_t n, const unsigned *undecided) {
+    if (*undecided == 0u)
+        return;   // the round found nothing to decide (and wrote no selection)
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
         if (!sel[v])
@@ -2810,6 +3338,40 @@ hipError_t launch_scale_gather(const Records &rec, const int32_t *pool, const do
     return hipGetLastError();
 }
 
+hipError_t launch_delta_events(const Records &rec, int32_t S, int32_t s, const int32_t *sets, int32_t n,
+                               int64_t *ev, int64_t *ev_off, uint32_t *err, hipStream_t st) {
+    if (n > 0) {
+        hipLaunchKernelGGL(delta_events_kernel, dim3((unsigned)std::min<int64_t>(4096, (n + 255) / 256)), dim3(256),
+                           0, st, rec, S, s, sets, n, ev, err);
+    }
+    hipLaunchKernelGGL(scan_i64_kernel, dim3(1), dim3(1024), 0, st, ev, (int64_t)n, ev_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_delta_rebuild(const Records &rec, const int32_t *pool, int32_t S, int32_t s,
+                                const int32_t *sets, int32_t n, const int64_t *ev_off, int32_t *scratch,
+                                const int32_t *out_ptr, int32_t *members, uint32_t *err, hipStream_t st) {
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(delta_rebuild_kernel, dim3((unsigned)std::min<int64_t>(65536, n)), dim3(256), 0, st, rec,
+                       pool, S, s, sets, n, ev_off, scratch, out_ptr, members, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_delta_lists(const Records &rec, const int32_t *pool, int32_t S, int32_t s, int32_t n,
+                              int64_t *na, int64_t *nr, int64_t *add_off, int64_t *rem_off, int32_t *added,
+                              int32_t *removed, hipStream_t st) {
+    if (n > 0)
+        hipLaunchKernelGGL(delta_counts_kernel, dim3((unsigned)std::min<int64_t>(4096, (n + 255) / 256)),
+                           dim3(256), 0, st, rec, S, s, n, na, nr);
+    hipLaunchKernelGGL(scan_i64_kernel, dim3(1), dim3(1024), 0, st, na, (int64_t)n, add_off);
+    hipLaunchKernelGGL(scan_i64_kernel, dim3(1), dim3(1024), 0, st, nr, (int64_t)n, rem_off);
+    if ((added || removed) && n > 0)
+        hipLaunchKernelGGL(delta_gather_kernel, dim3((n + 3) / 4), dim3(256), 0, st, rec, pool, S, s, n, add_off,
+                           added, rem_off, removed);
+    return hipGetLastError();
+}
+
 hipError_t launch_overlap(const int32_t *comm_ptr, const int32_t *members, int64_t total,
                                int32_t n_sets, int32_t n, int32_t *node_ptr, int32_t *node_sets,
                                int32_t *cnt, int32_t *block_sums, hipStream_t st) {
@@ -2873,16 +3435,17 @@ hipError_t launch_seed_init(const int32_t *row_ptr, const int32_t *perm, int32_t
 }
 
 hipError_t launch_seed_round(int32_t rule, const int32_t *row_ptr, const int32_t *col, const int32_t *pos,
-                             uint8_t *st, uint8_t *sel, int32_t n, unsigned *undecided, hipStream_t s) {
+                             uint8_t *st, uint8_t *sel, int32_t n, const unsigned *prev, unsigned *undecided,
+                             hipStream_t s) {
     if (n == 0)
         return hipSuccess;
     const dim3 g(grid_for(n, 256)), b(256);
     if (rule == 1) {
-        hipLaunchKernelGGL(seed_select_kernel<1>, g, b, 0, s, row_ptr, col, pos, st, sel, n, undecided);
-        hipLaunchKernelGGL(seed_apply_kernel<1>, g, b, 0, s, row_ptr, col, sel, st, n);
+        hipLaunchKernelGGL(seed_select_kernel<1>, g, b, 0, s, row_ptr, col, pos, st, sel, n, prev, undecided);
+        hipLaunchKernelGGL(seed_apply_kernel<1>, g, b, 0, s, row_ptr, col, sel, st, n, undecided);
     } else if (rule == 2) {
-        hipLaunchKernelGGL(seed_select_kernel<2>, g, b, 0, s, row_ptr, col, pos, st, sel, n, undecided);
-        hipLaunchKernelGGL(seed_apply_kernel<2>, g, b, 0, s, row_ptr, col, sel, st, n);
+        hipLaunchKernelGGL(seed_select_kernel<2>, g, b, 0, s, row_ptr, col, pos, st, sel, n, prev, undecided);
+        hipLaunchKernelGGL(seed_apply_kernel<2>, g, b, 0, s, row_ptr, col, sel, st, n, undecided);
     } else {
         return hipErrorInvalidValue;
     }

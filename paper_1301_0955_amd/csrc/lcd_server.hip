@@ -50,6 +50,7 @@ struct Query {
     double alpha = 0.0;
     int64_t reserve = 0;        // member-pool entries reserved at admission
     bool solo = false;          // rerun alone after its batch's pool overflowed
+    bool cancel = false;        // withdrawn while on the device: drop its result
     bool done = false;
     lcd_status status = LCD_EAGAIN;
     std::string msg;
@@ -67,6 +68,29 @@ lcd_status host_alloc(T **p, size_t count) {
         *p = nullptr;
         (void)hipGetLastError();
         return fail(LCD_ENOMEM, "hipHostMalloc of %zu bytes failed", count * sizeof(T));
+    }
+    return LCD_OK;
+}
+
+// Pinned host memory the device writes while a kernel runs and the host
+// reads as soon as a flag says so (fine-grained, coherent); *dev gets the
+// device's address of it.
+template <typename T>
+lcd_status host_alloc_coherent(T **p, T **dev, size_t count) {
+    *p = nullptr;
+    *dev = nullptr;
+    if (count == 0)
+        count = 1;
+    hipError_t e = hipHostMalloc((void **)p, count * sizeof(T), hipHostMallocCoherent | hipHostMallocMapped);
+    if (e == hipSuccess)
+        e = hipHostGetDevicePointer((void **)dev, (void *)*p, 0);
+    if (e != hipSuccess) {
+        if (*p)
+            (void)hipHostFree((void *)*p);
+        *p = nullptr;
+        *dev = nullptr;
+        (void)hipGetLastError();
+        return fail(LCD_ENOMEM, "coherent hipHostMalloc of %zu bytes failed", count * sizeof(T));
     }
     return LCD_OK;
 }
@@ -98,8 +122,13 @@ struct Lane {
     double *alpha = nullptr;
     int32_t *seed_ptr = nullptr;
     int32_t *seed_nodes = nullptr;
+    // records, member pool and completion flags: coherent pinned host
+    // memory written by the kernels (device addresses here, host ones in
+    // h_off .. h_pool, h_flags), so that a query completes when its own
+    // flag is set, not when its batch ends
     Records rec{};
     int32_t *pool = nullptr;
+    uint32_t *flags = nullptr;
     Counters *ctl = nullptr;
     unsigned long long *cursor = nullptr;
     int32_t *work[kMaxTiers - 1] = {nullptr, nullptr, nullptr};
@@ -118,8 +147,10 @@ struct Lane {
     int32_t *h_pool = nullptr;
     Counters *h_ctl = nullptr;
     int32_t *h_work0 = nullptr;
-    // batch in flight
+    uint32_t *h_flags = nullptr;
+    // batch in flight; taken[i]: query i already completed from its flag
     std::vector<Query *> batch;
+    std::vector<char> taken;
     bool busy = false;
     int64_t t_start = 0;
 };
@@ -128,13 +159,6 @@ void lane_release(Lane &L) {
     dev_free(L.alpha);
     dev_free(L.seed_ptr);
     dev_free(L.seed_nodes);
-    dev_free(L.rec.off);
-    dev_free(L.rec.cnt);
-    dev_free(L.rec.K);
-    dev_free(L.rec.V);
-    dev_free(L.rec.f);
-    dev_free(L.rec.ctr);
-    dev_free(L.pool);
     dev_free(L.ctl);
     dev_free(L.cursor);
     for (auto &w : L.work)
@@ -154,6 +178,7 @@ void lane_release(Lane &L) {
     host_free(L.h_pool);
     host_free(L.h_ctl);
     host_free(L.h_work0);
+    host_free(L.h_flags);
     if (L.done)
         (void)hipEventDestroy(L.done);
     if (L.st)
@@ -162,10 +187,12 @@ void lane_release(Lane &L) {
     L.st = nullptr;
 }
 
-// Device bytes of one lane's buffers (without the spill tables).
+// Device bytes of one lane's buffers (without the spill tables; records
+// and member pool are host memory).
 int64_t lane_bytes(int32_t max_q, int64_t max_seed, int64_t pool_cap) {
-    return (int64_t)max_q * (8 + 4 + 8 + 4 + 8 + 8 + 8 + 32 + 8) + max_seed * 4 + pool_cap * 4 +
-           8 * kCursorWords + (int64_t)sizeof(Counters) + 256 * 16;
+    (void)pool_cap;
+    return (int64_t)max_q * (8 + 4 + 4 + 4 * (kMaxTiers - 1)) + max_seed * 4 + 8 * kCursorWords +
+           (int64_t)sizeof(Counters) + 256 * 16;
 }
 
 }  // namespace
@@ -211,6 +238,9 @@ lcd_status launch_lane(lcd_server *S, Lane &L) {
         pos += (int64_t)q->seeds.size();
     }
     L.h_seed_ptr[nq] = (int32_t)pos;
+    for (int32_t i = 0; i < nq; ++i)
+        __atomic_store_n(&L.h_flags[i], 0u, __ATOMIC_RELAXED);
+    L.taken.assign((size_t)nq, 0);
     hipStream_t st = L.st;
     HIPCHK(hipMemcpyAsync(L.alpha, L.h_alpha, sizeof(double) * nq, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(L.seed_ptr, L.h_seed_ptr, sizeof(int32_t) * (nq + 1), hipMemcpyHostToDevice, st));
@@ -254,16 +284,11 @@ lcd_status launch_lane(lcd_server *S, Lane &L) {
     a.err = (uint32_t *)(L.cursor + 1);
     a.stat = L.cursor + 2;
     a.budget_ticks = S->prm.watchdog_ms < 0 ? 0 : g->dev.wall_khz * (int64_t)S->prm.watchdog_ms;
+    a.done_flags = L.flags;
     const TierSpec &T0 = S->tp.t[0];
     const int32_t blocks0 = std::min<int32_t>(T0.blocks, (nq + T0.waves - 1) / T0.waves);
     int32_t launches = 0;
     CHK(enqueue_tiers(a, S->tp, G.first, G.last, blocks0, L.slab, L.work, nullptr, st, nullptr, &launches));
-    HIPCHK(hipMemcpyAsync(L.h_off, L.rec.off, sizeof(int64_t) * nq, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(L.h_cnt, L.rec.cnt, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(L.h_K, L.rec.K, sizeof(int64_t) * nq, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(L.h_V, L.rec.V, sizeof(int64_t) * nq, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(L.h_f, L.rec.f, sizeof(double) * nq, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(L.h_ctr, L.rec.ctr, sizeof(uint64_t) * 4 * nq, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(L.h_cursor, L.cursor, 8 * kCursorWords, hipMemcpyDeviceToHost, st));
     if (G.last < S->tp.n) {
         HIPCHK(hipMemcpyAsync(L.h_ctl, L.ctl, sizeof(Counters), hipMemcpyDeviceToHost, st));
@@ -273,8 +298,29 @@ lcd_status launch_lane(lcd_server *S, Lane &L) {
     return LCD_OK;
 }
 
-// The lane's batch has finished on the device: fetch member lists and fill
-// the queries.  Called without the lock.  `again`: queries to run again
+// Result of query i of the lane's batch from the host-visible records and
+// pool; false when its members did not fit the pool.
+bool fill_query(Lane &L, int32_t i, Query *q, int64_t t_done) {
+    const int64_t off = L.h_off[i];
+    const int32_t cnt = L.h_cnt[i];
+    if (off < 0 || cnt < 0 || off + cnt > L.pool_cap)
+        return false;
+    q->members.assign(L.h_pool + off, L.h_pool + off + cnt);
+    q->info.n_members = cnt;
+    q->info.k_in = L.h_K[i];
+    q->info.vol = L.h_V[i];
+    q->info.f = L.h_f[i];
+    for (int c = 0; c < 4; ++c)
+        q->info.ctr[c] = L.h_ctr[4 * i + c];
+    q->info.t_done_ns = t_done;
+    q->info.batch_size = (int32_t)L.batch.size();
+    q->info.lane = L.id;
+    q->status = LCD_OK;
+    return true;
+}
+
+// The lane's batch has finished on the device: fill the queries not yet
+// completed from their flags.  Called without the lock.  `again`: queries to run again
 // alone (the batch outgrew the lane's pool); `forward`: queries that
 // overflowed the last tier of the lane's stage.
 lcd_status collect_lane(lcd_server *S, Lane &L, std::vector<Query *> &again,
@@ -298,40 +344,41 @@ lcd_status collect_lane(lcd_server *S, Lane &L, std::vector<Query *> &again,
             spilled[i] = 1;
         }
     }
-    const int64_t used = std::min<int64_t>((int64_t)L.h_cursor[0], L.pool_cap);
-    if (used > 0) {
-        HIPCHK(hipMemcpyAsync(L.h_pool, L.pool, sizeof(int32_t) * used, hipMemcpyDeviceToHost, L.st));
-        HIPCHK(hipStreamSynchronize(L.st));
-    }
     const int64_t t_done = now_ns();
     for (int32_t i = 0; i < nq; ++i) {
         Query *q = L.batch[i];
+        if (L.taken[i])
+            continue;
         if (spilled[i]) {
             forward.push_back(q);
             continue;
         }
-        const int64_t off = L.h_off[i];
-        const int32_t cnt = L.h_cnt[i];
-        if (off < 0 || off + cnt > L.pool_cap) {
+        if (!fill_query(L, i, q, t_done)) {
             // the batch outgrew the lane's pool: this query runs again alone
             q->solo = true;
             q->reserve = L.pool_cap;
             again.push_back(q);
-            continue;
         }
-        q->members.assign(L.h_pool + off, L.h_pool + off + cnt);
-        q->info.n_members = cnt;
-        q->info.k_in = L.h_K[i];
-        q->info.vol = L.h_V[i];
-        q->info.f = L.h_f[i];
-        for (int c = 0; c < 4; ++c)
-            q->info.ctr[c] = L.h_ctr[4 * i + c];
-        q->info.t_done_ns = t_done;
-        q->info.batch_size = nq;
-        q->info.lane = L.id;
-        q->status = LCD_OK;
     }
     return LCD_OK;
+}
+
+// Queries of a running batch whose flags are set: results straight from
+// the coherent host buffers.  Called without the lock; the queries it
+// returns are completed by the caller.
+void harvest_lane(Lane &L, std::vector<Query *> &out) {
+    const int32_t nq = (int32_t)L.batch.size();
+    int64_t t_done = 0;
+    for (int32_t i = 0; i < nq; ++i) {
+        if (L.taken[i] || __atomic_load_n(&L.h_flags[i], __ATOMIC_ACQUIRE) == 0u)
+            continue;
+        if (t_done == 0)
+            t_done = now_ns();
+        if (fill_query(L, i, L.batch[i], t_done)) {
+            L.taken[i] = 1;
+            out.push_back(L.batch[i]);
+        }
+    }
 }
 
 // Fill L.batch from queue (FIFO) within the lane's limits.  Lock held.
@@ -354,6 +401,22 @@ void admit(lcd_server *S, Lane &L, std::deque<Query *> &queue, bool count_slots)
     }
 }
 
+// A query leaves the server's bookkeeping (lock held): done, counted; one
+// withdrawn while it ran ends cancelled instead.
+void finish_query(lcd_server *S, Query *q) {
+    if (q->cancel) {
+        q->status = LCD_ECANCELED;
+        q->msg = "query cancelled";
+        q->members.clear();
+        S->stats.cancelled += 1;
+    } else if (q->status == LCD_OK) {
+        S->stats.completed += 1;
+    } else {
+        S->stats.failed += 1;
+    }
+    q->done = true;
+}
+
 void worker_main(lcd_server *S) {
     (void)hipSetDevice(S->g->device);
     std::unique_lock<std::mutex> lk(S->mu);
@@ -364,6 +427,18 @@ void worker_main(lcd_server *S) {
             if (!L.busy)
                 continue;
             lk.unlock();
+            std::vector<Query *> early;
+            harvest_lane(L, early);
+            if (!early.empty()) {
+                lk.lock();
+                for (Query *qq : early) {
+                    finish_query(S, qq);
+                    S->in_flight -= 1;
+                }
+                S->cv_done.notify_all();
+                progress = true;
+                lk.unlock();
+            }
             const hipError_t q = hipEventQuery(L.done);
             std::vector<Query *> again, forward;
             lcd_status s = LCD_OK;
@@ -386,7 +461,10 @@ void worker_main(lcd_server *S) {
                 again.clear();
                 forward.clear();
             }
-            for (Query *qq : L.batch) {
+            for (size_t bi = 0; bi < L.batch.size(); ++bi) {
+                Query *qq = L.batch[bi];
+                if (L.taken[bi])
+                    continue;   // completed from its flag
                 bool moved = false;
                 for (Query *a : again)
                     moved |= a == qq;
@@ -397,13 +475,21 @@ void worker_main(lcd_server *S) {
                 if (s != LCD_OK) {
                     qq->status = s;
                     qq->msg = msg;
-                    S->stats.failed += 1;
-                } else {
-                    S->stats.completed += 1;
                 }
-                qq->done = true;
+                finish_query(S, qq);
                 S->in_flight -= 1;
             }
+            // withdrawn queries go no further
+            for (auto *lst : {&again, &forward})
+                for (auto it = lst->begin(); it != lst->end();) {
+                    if ((*it)->cancel) {
+                        finish_query(S, *it);
+                        S->in_flight -= 1;
+                        it = lst->erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
             // queries to run again keep their place at the front of their stage
             std::deque<Query *> &back = L.stage == 0 ? S->pending : S->forwarded[L.stage];
             for (auto it = again.rbegin(); it != again.rend(); ++it)
@@ -509,13 +595,14 @@ lcd_status lane_init(lcd_server *S, Lane &L, int id, int32_t max_q, int64_t max_
     CHK(dev_alloc(&L.alpha, max_q));
     CHK(dev_alloc(&L.seed_ptr, (size_t)max_q + 1));
     CHK(dev_alloc(&L.seed_nodes, (size_t)max_seed));
-    CHK(dev_alloc(&L.rec.off, max_q));
-    CHK(dev_alloc(&L.rec.cnt, max_q));
-    CHK(dev_alloc(&L.rec.K, max_q));
-    CHK(dev_alloc(&L.rec.V, max_q));
-    CHK(dev_alloc(&L.rec.f, max_q));
-    CHK(dev_alloc(&L.rec.ctr, 4 * (size_t)max_q));
-    CHK(dev_alloc(&L.pool, (size_t)pool_cap));
+    CHK(host_alloc_coherent(&L.h_off, &L.rec.off, max_q));
+    CHK(host_alloc_coherent(&L.h_cnt, &L.rec.cnt, max_q));
+    CHK(host_alloc_coherent(&L.h_K, &L.rec.K, max_q));
+    CHK(host_alloc_coherent(&L.h_V, &L.rec.V, max_q));
+    CHK(host_alloc_coherent(&L.h_f, &L.rec.f, max_q));
+    CHK(host_alloc_coherent(&L.h_ctr, &L.rec.ctr, 4 * (size_t)max_q));
+    CHK(host_alloc_coherent(&L.h_pool, &L.pool, (size_t)pool_cap));
+    CHK(host_alloc_coherent(&L.h_flags, &L.flags, max_q));
     CHK(dev_alloc(&L.ctl, 1));
     CHK(dev_alloc(&L.cursor, kCursorWords));
     for (auto &w : L.work)
@@ -523,14 +610,7 @@ lcd_status lane_init(lcd_server *S, Lane &L, int id, int32_t max_q, int64_t max_
     CHK(host_alloc(&L.h_alpha, max_q));
     CHK(host_alloc(&L.h_seed_ptr, (size_t)max_q + 1));
     CHK(host_alloc(&L.h_seed_nodes, (size_t)max_seed));
-    CHK(host_alloc(&L.h_off, max_q));
-    CHK(host_alloc(&L.h_cnt, max_q));
-    CHK(host_alloc(&L.h_K, max_q));
-    CHK(host_alloc(&L.h_V, max_q));
-    CHK(host_alloc(&L.h_f, max_q));
-    CHK(host_alloc(&L.h_ctr, 4 * (size_t)max_q));
     CHK(host_alloc(&L.h_cursor, kCursorWords));
-    CHK(host_alloc(&L.h_pool, (size_t)pool_cap));
     CHK(host_alloc(&L.h_ctl, 1));
     CHK(host_alloc(&L.h_work0, max_q));
     for (int k = 0; k < S->tp.n; ++k)
@@ -790,6 +870,40 @@ lcd_status lcd_server_wait(lcd_server *S, uint64_t ticket, int32_t timeout_ms) {
         S->cv_done.wait(lk, ready);
     else if (!S->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready))
         return LCD_EAGAIN;
+    return LCD_OK;
+}
+
+lcd_status lcd_server_cancel(lcd_server *S, uint64_t ticket) {
+    if (!S)
+        return fail(LCD_EINVAL, "null server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->tickets.find(ticket);
+    if (it == S->tickets.end())
+        return fail(LCD_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    Query *q = it->second;
+    if (q->done)
+        return q->status == LCD_ECANCELED ? LCD_OK : fail(LCD_ESTATE, "the query has already completed");
+    q->cancel = true;
+    // waiting for a lane: drop it now (a stage-0 query holds no slot yet, a
+    // forwarded one does)
+    auto drop = [q](std::deque<Query *> &dq) {
+        for (auto d = dq.begin(); d != dq.end(); ++d)
+            if (*d == q) {
+                dq.erase(d);
+                return true;
+            }
+        return false;
+    };
+    bool dropped = drop(S->pending);
+    for (int k = 1; k < S->n_stages && !dropped; ++k)
+        if (drop(S->forwarded[k])) {
+            dropped = true;
+            S->in_flight -= 1;
+        }
+    if (dropped) {
+        finish_query(S, q);
+        S->cv_done.notify_all();
+    }
     return LCD_OK;
 }
 

@@ -17,12 +17,13 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblcd.so")
 
-LCD_OK, LCD_EINVAL, LCD_ENOMEM, LCD_EDEVICE, LCD_EAGAIN, LCD_ECAPACITY, LCD_ESTATE = range(7)
+LCD_OK, LCD_EINVAL, LCD_ENOMEM, LCD_EDEVICE, LCD_EAGAIN, LCD_ECAPACITY, LCD_ESTATE, LCD_ECANCELED = range(8)
 LCD_MEM_HOST, LCD_MEM_DEVICE = 0, 1
 LCD_PERSISTENT, LCD_PER_SCALE_LOOP = 0, 1
+LCD_OUT_FULL, LCD_OUT_DELTA = 0, 1
 
 _STATUS = {0: "LCD_OK", 1: "LCD_EINVAL", 2: "LCD_ENOMEM", 3: "LCD_EDEVICE", 4: "LCD_EAGAIN",
-           5: "LCD_ECAPACITY", 6: "LCD_ESTATE"}
+           5: "LCD_ECAPACITY", 6: "LCD_ESTATE", 7: "LCD_ECANCELED"}
 
 
 class LcdError(RuntimeError):
@@ -38,7 +39,7 @@ class lcd_params(ctypes.Structure):
                 ("pool_hint", ctypes.c_int64), ("watchdog_ms", ctypes.c_int32),
                 ("spill_mode", ctypes.c_int32), ("team_capacity", ctypes.c_int32),
                 ("team_waves", ctypes.c_int32), ("grow_calls", ctypes.c_int32),
-                ("queue_min_entries", ctypes.c_int32)]
+                ("queue_min_entries", ctypes.c_int32), ("output_mode", ctypes.c_int32)]
 
 
 class lcd_tier_stats(ctypes.Structure):
@@ -99,7 +100,7 @@ class lcd_server_stats(ctypes.Structure):
                 ("lanes", ctypes.c_int32), ("spill_lanes", ctypes.c_int32),
                 ("max_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
                 ("max_lanes_busy", ctypes.c_int32), ("spill_tables", ctypes.c_int32 * 2),
-                ("pad", ctypes.c_int32)]
+                ("pad", ctypes.c_int32), ("cancelled", ctypes.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("spill_tables", "pad")}
@@ -142,6 +143,9 @@ def library() -> ctypes.CDLL:
         "lcd_result_sizes": (st, [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
         "lcd_result_membership": (st, [P, ctypes.c_int32, P, P, P, P, P, ctypes.c_int32, P]),
         "lcd_result_overlap": (st, [P, ctypes.c_int32, P, P, ctypes.c_int32, P]),
+        "lcd_result_delta_sizes": (st, [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int64)]),
+        "lcd_result_delta": (st, [P, ctypes.c_int32, P, P, P, P, ctypes.c_int32, P]),
         "lcd_result_counters": (st, [P, P, P, ctypes.c_int32, P]),
         "lcd_result_stats": (st, [P, ctypes.POINTER(lcd_sweep_stats)]),
         "lcd_result_sets": (st, [P, P, ctypes.c_int32, P, P, P, ctypes.c_int64,
@@ -158,6 +162,7 @@ def library() -> ctypes.CDLL:
         "lcd_server_poll": (st, [P, ctypes.c_uint64, P, ctypes.c_int32,
                                  ctypes.POINTER(lcd_query_info)]),
         "lcd_server_wait": (st, [P, ctypes.c_uint64, ctypes.c_int32]),
+        "lcd_server_cancel": (st, [P, ctypes.c_uint64]),
         "lcd_server_get_stats": (st, [P, ctypes.POINTER(lcd_server_stats)]),
         "lcd_server_destroy": (st, [P]),
         "lcd_tune": (st, [P, P, ctypes.c_int32, P, P, ctypes.c_int32, ctypes.c_int32,
@@ -354,6 +359,21 @@ class Result:
                                                LCD_MEM_DEVICE, _stream()), "lcd_result_membership")
         return cp, m[:tot], k[:self.n_sets], v[:self.n_sets], f[:self.n_sets]
 
+    def delta(self, s: int):
+        """(add_ptr, added, rem_ptr, removed) at scale s, device tensors: the
+        ids that joined and left each set's community since scale s - 1
+        (a sweep with output_mode=LCD_OUT_DELTA)."""
+        na, nr = ctypes.c_int64(), ctypes.c_int64()
+        _check(library().lcd_result_delta_sizes(self._h, s, ctypes.byref(na), ctypes.byref(nr)),
+               "lcd_result_delta_sizes")
+        ap = torch.empty(self.n_sets + 1, dtype=torch.int64, device="cuda")
+        rp = torch.empty(self.n_sets + 1, dtype=torch.int64, device="cuda")
+        a = torch.empty(max(na.value, 1), dtype=torch.int32, device="cuda")
+        r = torch.empty(max(nr.value, 1), dtype=torch.int32, device="cuda")
+        _check(library().lcd_result_delta(self._h, s, _ptr(ap), _ptr(a), _ptr(rp), _ptr(r), LCD_MEM_DEVICE,
+                                          _stream()), "lcd_result_delta")
+        return ap, a[:na.value], rp, r[:nr.value]
+
     def overlap(self, s: int):
         """(node_ptr, node_sets) at scale s, device tensors."""
         tot = self.sizes(s)
@@ -448,7 +468,7 @@ def make_params(k_prune: int = 0, mode: int = LCD_PERSISTENT, lds_capacity: int 
                 waves_per_block: int = 0, blocks_per_cu: int = 0, use_graph: int = 0,
                 pool_hint: int = 0, watchdog_ms: int = 0, spill_mode: int = 0,
                 team_capacity: int = 0, team_waves: int = 0, grow_calls: int = 0,
-                queue_min_entries: int = 0) -> lcd_params:
+                queue_min_entries: int = 0, output_mode: int = LCD_OUT_FULL) -> lcd_params:
     p = lcd_params()
     library().lcd_params_default(ctypes.byref(p))
     p.k_prune = k_prune
@@ -465,6 +485,7 @@ def make_params(k_prune: int = 0, mode: int = LCD_PERSISTENT, lds_capacity: int 
     p.team_waves = team_waves
     p.grow_calls = grow_calls
     p.queue_min_entries = queue_min_entries
+    p.output_mode = output_mode
     return p
 
 
@@ -690,6 +711,15 @@ class Server:
         if s == LCD_EAGAIN:
             return False
         _check(s, "lcd_server_wait")
+        return True
+
+    def cancel(self, ticket: int) -> bool:
+        """Withdraw a query: True if it was withdrawn (its ticket ends with
+        LCD_ECANCELED), False if it had already completed."""
+        s = library().lcd_server_cancel(self._h, ticket)
+        if s == LCD_ESTATE:
+            return False
+        _check(s, "lcd_server_cancel")
         return True
 
     def result(self, ticket: int, timeout_ms: int = -1):

@@ -140,3 +140,50 @@ def test_server_errors_and_capacity(L, graph):
         r = srv.result(srv.submit([5], 0.8), 60_000)
         ref = _oracle_one(oracle.Oracle.from_graph(g), [5], 0.8)
         _same(r, ref, "after watchdog")
+
+
+def test_server_small_budget_and_cancel(L, graph):
+    """Admission under a forced small memory budget (the smallest the lanes
+    accept: one table of each global tier per lane that runs it), with every
+    result still equal to the oracle's; a budget below it is refused; and
+    cancellation: a withdrawn query ends LCD_ECANCELED whether it was still
+    waiting or already on the device, the rest are answered exactly."""
+    import re
+    g = graph
+    G = L.Graph.from_workload(g)
+    with pytest.raises(L.LcdError) as e:
+        L.Server(G, mem_budget=1 << 20)
+    assert e.value.status == L.LCD_ENOMEM
+    need = int(re.search(r"below the (\d+) bytes", str(e.value)).group(1))
+    o = oracle.Oracle.from_graph(g)
+    _, sets, alphas = W.query_stream(g, 160, 2000.0, max_size=256, seed=23)
+    heavy = [(W.bfs_prefix(g, r, 256), 0.5) for r in (3, 1201)]
+    queries = heavy + list(zip(sets, alphas))
+    with L.Server(G, mem_budget=need + (1 << 20)) as srv:
+        st = srv.stats()
+        assert all(x <= 1 for x in st["spill_tables"]), st
+        tickets = [srv.submit(s, a) for s, a in queries]
+        # withdraw every fifth query at once (most are still waiting), and
+        # the first heavy one after it has started
+        cut = set(range(2, len(queries), 5))
+        withdrawn = {i for i in cut if srv.cancel(tickets[i])}
+        assert withdrawn
+        if srv.cancel(tickets[0]):
+            withdrawn.add(0)
+        for i, t in enumerate(tickets):
+            assert srv.wait(t, 120_000)
+            if i in withdrawn:
+                with pytest.raises(L.LcdError) as e:
+                    srv.poll(t)
+                assert e.value.status == L.LCD_ECANCELED
+                continue
+            _same(srv.poll(t), _oracle_one(o, *queries[i]), "small budget, query %d" % i)
+        st = srv.stats()
+        assert st["cancelled"] == len(withdrawn)
+        assert st["completed"] == len(queries) - len(withdrawn)
+        _say("small budget %d B: tables %s, %d withdrawn, stats %s" % (need, st["spill_tables"], len(withdrawn), st))
+        # a completed query can no longer be withdrawn
+        t = srv.submit([5], 0.8)
+        srv.wait(t, 60_000)
+        assert not srv.cancel(t)
+        _same(srv.poll(t), _oracle_one(o, [5], 0.8), "after cancel")
