@@ -108,7 +108,7 @@ typedef struct {
     int32_t team_capacity;   /* spill_mode 0: entries of the workgroup tier's LDS table;
                                 0 = max(1,024, 2 lds_capacity), within one workgroup's LDS */
     int32_t team_waves;      /* waves per community in the workgroup tiers, 1..8;
-                                0 = 4 */
+                                0 = 4 (2 on graphs of 4M+ nodes) */
     int32_t grow_calls;      /* growth calls per (seed set, scale): 0 = until a call
                                 changes nothing (the default); n > 0 stops after
                                 n calls (lcd_sweep_merge makes one per round) */
@@ -116,7 +116,7 @@ typedef struct {
                                 growth call holds this many entries (checked after
                                 each addition) the call keeps its queue bucketed by
                                 rank (a step looks at the queue's head, not the
-                                whole table); 0 = default (8,192); results never
+                                whole table); 0 = default (1,024); results never
                                 depend on it */
     int32_t output_mode;     /* LCD_OUT_FULL (default) or LCD_OUT_DELTA: lcd_sweep and
                                 lcd_sweep_batch only (the other calls store full
@@ -334,7 +334,9 @@ lcd_status lcd_graph_untune(lcd_graph *g);
  * receives the seeds in order of selection, *n_seeds their number; seed j
  * is the singleton seed set j of a sweep.  Computed in parallel rounds that
  * give exactly the sequential result.  LCD_EINVAL if perm is not a
- * permutation.  Blocking.
+ * permutation.  The graph keeps the call's device workspace (about 22 bytes
+ * per node) for the next call, so calls on one graph must not overlap.
+ * Blocking.
  */
 lcd_status lcd_seeds(const lcd_graph *g, int32_t rule, const int32_t *perm, int32_t mem_kind, void *stream,
                      int32_t *out_seeds, int32_t *n_seeds);

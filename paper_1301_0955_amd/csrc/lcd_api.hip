@@ -106,7 +106,10 @@ lcd_status plan_tiers(const DevInfo &dev, int32_t n, const lcd_params &p, TierPl
     };
     if (p.team_waves < 0 || 64 * p.team_waves > kTeamMaxThreads)
         return fail(LCD_EINVAL, "team_waves must be in [0, %d]", kTeamMaxThreads / 64);
-    const int32_t team_waves = p.team_waves > 0 ? p.team_waves : 4;
+    // graphs of millions of nodes: their sets are chains of thousands of
+    // dependent steps on global tables, and two waves per set keep twice as
+    // many sets in flight at a step cost little above four waves'
+    const int32_t team_waves = p.team_waves > 0 ? p.team_waves : (n >= (4 << 20) ? 2 : 4);
     // workgroups of a workgroup tier that stay resident on the whole chip
     auto resident = [&](int32_t kind, int32_t waves, size_t lds) -> int32_t {
         int32_t nb = 0;
@@ -805,6 +808,7 @@ lcd_status lcd_graph_free(lcd_graph *g) {
     dev_free(g->logtab);
     dev_free(g->slab[0].buf);
     dev_free(g->slab[1].buf);
+    dev_free(g->seed_ws);
     delete g;
     return LCD_OK;
 }
@@ -956,37 +960,29 @@ lcd_status lcd_seeds(const lcd_graph *g, int32_t rule, const int32_t *perm, int3
     if (n == 0)
         return LCD_OK;
     const int nb = (int)(((int64_t)n + 1023) / 1024);
-    int32_t *d_perm = nullptr, *pos = nullptr, *flag = nullptr, *at = nullptr, *bs = nullptr, *out = nullptr;
-    uint8_t *stt = nullptr, *sel = nullptr;
-    unsigned *cnt = nullptr;
-    auto release = [&]() {
-        dev_free(d_perm);
-        dev_free(pos);
-        dev_free(flag);
-        dev_free(at);
-        dev_free(bs);
-        dev_free(stt);
-        dev_free(sel);
-        dev_free(cnt);
-        if (mem_kind == LCD_MEM_HOST)
-            dev_free(out);
-    };
-    lcd_status s = LCD_OK;
-    if ((s = dev_alloc(&d_perm, n)) != LCD_OK || (s = dev_alloc(&pos, n)) != LCD_OK ||
-        (s = dev_alloc(&flag, n)) != LCD_OK || (s = dev_alloc(&at, n)) != LCD_OK ||
-        (s = dev_alloc(&bs, (size_t)nb + 1)) != LCD_OK || (s = dev_alloc(&stt, n)) != LCD_OK ||
-        (s = dev_alloc(&sel, n)) != LCD_OK || (s = dev_alloc(&cnt, kSeedBatch)) != LCD_OK) {
-        release();
-        return s;
+    // one device workspace per graph, allocated on the first call: perm,
+    // pos, flag (also the round's one-hop minima), at, block sums, out
+    // (int32), state and selection (uint8), the round counters
+    auto al = [](int64_t x) { return (x + 255) / 256 * 256; };
+    const int64_t n4 = al(4 * (int64_t)n), n1 = al((int64_t)n);
+    const int64_t ws = 5 * n4 + al(4 * ((int64_t)nb + 1)) + 2 * n1 + al(4 * (int64_t)kSeedBatch);
+    lcd_graph *gw = const_cast<lcd_graph *>(g);
+    if (gw->seed_ws_bytes < ws) {
+        dev_free(gw->seed_ws);
+        gw->seed_ws_bytes = 0;
+        CHK(dev_alloc(&gw->seed_ws, (size_t)ws));
+        gw->seed_ws_bytes = ws;
     }
-    if (mem_kind == LCD_MEM_HOST) {
-        if ((s = dev_alloc(&out, n)) != LCD_OK) {
-            release();
-            return s;
-        }
-    } else {
-        out = out_seeds;
-    }
+    char *p = gw->seed_ws;
+    int32_t *d_perm = (int32_t *)p;
+    int32_t *pos = (int32_t *)(p + n4);
+    int32_t *flag = (int32_t *)(p + 2 * n4);
+    int32_t *at = (int32_t *)(p + 3 * n4);
+    int32_t *out = mem_kind == LCD_MEM_HOST ? (int32_t *)(p + 4 * n4) : out_seeds;
+    int32_t *bs = (int32_t *)(p + 5 * n4);
+    uint8_t *stt = (uint8_t *)(p + 5 * n4 + al(4 * ((int64_t)nb + 1)));
+    uint8_t *sel = stt + n1;
+    unsigned *cnt = (unsigned *)(sel + n1);
     hipError_t e = hipMemcpyAsync(d_perm, ph.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = launch_seed_init(g->row_ptr, d_perm, n, pos, stt, st);
@@ -1002,7 +998,7 @@ lcd_status lcd_seeds(const lcd_graph *g, int32_t rule, const int32_t *perm, int3
         unsigned undecided = 0;
         e = launch_zero_bytes(cnt, 4 * (int64_t)batch, st);
         for (int32_t k = 0; k < batch && e == hipSuccess; ++k)
-            e = launch_seed_round(rule, g->row_ptr, g->col, pos, stt, sel, n, k > 0 ? cnt + (k - 1) : nullptr,
+            e = launch_seed_round(rule, g->row_ptr, g->col, pos, stt, sel, flag, n, k > 0 ? cnt + (k - 1) : nullptr,
                                   cnt + k, st);
         rounds += batch;
         if (e == hipSuccess)
@@ -1020,7 +1016,6 @@ lcd_status lcd_seeds(const lcd_graph *g, int32_t rule, const int32_t *perm, int3
         e = hipMemcpyAsync(out_seeds, out, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
         e = hipStreamSynchronize(st);
-    release();
     if (e != hipSuccess)
         return fail(LCD_EDEVICE, "seed selection: %s", hipGetErrorString(e));
     if (!settled)

@@ -103,7 +103,7 @@ constexpr int kCursorWords = 2 + kStatWords * kMaxTiers;
 
 // The table size from which a growth call keeps its queue bucketed by rank.
 inline int32_t queue_min_of(const lcd_params &p) {
-    return p.queue_min_entries > 0 ? p.queue_min_entries : 8192;
+    return p.queue_min_entries > 0 ? p.queue_min_entries : 1024;
 }
 
 // One tier of the launch chain.
@@ -179,6 +179,9 @@ struct lcd_graph {
     // launch sizing chosen by lcd_tune() for this graph
     bool tuned = false;
     lcd_params tuned_prm{};
+    // lcd_seeds' device workspace, kept for the next call
+    char *seed_ws = nullptr;
+    int64_t seed_ws_bytes = 0;
 };
 
 static inline lcd::GraphDev graph_dev(const lcd_graph *g) {

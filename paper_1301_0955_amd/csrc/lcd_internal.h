@@ -200,8 +200,8 @@ hipError_t launch_exclusive_scan(const int32_t *in, int64_t n, int32_t *out, int
 hipError_t launch_seed_init(const int32_t *row_ptr, const int32_t *perm, int32_t n, int32_t *pos,
                             uint8_t *st, hipStream_t s);
 hipError_t launch_seed_round(int32_t rule, const int32_t *row_ptr, const int32_t *col, const int32_t *pos,
-                             uint8_t *st, uint8_t *sel, int32_t n, const unsigned *prev, unsigned *undecided,
-                             hipStream_t s);
+                             uint8_t *st, uint8_t *sel, int32_t *m1, int32_t n, const unsigned *prev,
+                             unsigned *undecided, hipStream_t s);
 hipError_t launch_seed_collect(const int32_t *perm, const uint8_t *st, int32_t n, int32_t *flag, int32_t *at,
                                int32_t *block_sums, int32_t *out, hipStream_t s);
 

@@ -2127,8 +2127,29 @@ __device__ bool team_toggle_records(const SweepArgs &A, const Tab &t, TeamSh &sh
     return true;
 }
 
+// Sort a[0..m) (global memory) through the LDS buffer lbuf when it fits:
+// the bitonic network's rounds then wait on LDS, not on memory.
+constexpr int kLdsSort = 2048;
+
+__device__ void team_sort_via(int32_t *a, int32_t m, const TeamId &id, int32_t *lbuf) {
+    if (m <= 1)
+        return;
+    if (!lbuf || m > kLdsSort) {
+        team_sort(a, m, id);
+        return;
+    }
+    for (int32_t i = id.tid; i < m; i += id.nt)
+        lbuf[i] = a[i];
+    __syncthreads();
+    team_sort(lbuf, m, id);
+    for (int32_t i = id.tid; i < m; i += id.nt)
+        a[i] = lbuf[i];
+    __syncthreads();
+}
+
+// lbuf: LDS sort buffer of kLdsSort entries (global tables), or nullptr.
 template <bool GLOBAL, bool PERSET>
-__device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh) {
+__device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh, int32_t *lbuf) {
     TeamId id;
     id.tid = (int)threadIdx.x;
     id.nt = (int)blockDim.x;
@@ -2309,8 +2330,8 @@ __device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh) {
                 }
                 __syncthreads();
                 const int32_t na = sh.m, nr = sh.m2;
-                team_sort(t.scr, na, id);
-                team_sort(t.scr + (t.cap - nr), nr, id);
+                team_sort_via(t.scr, na, id, lbuf);
+                team_sort_via(t.scr + (t.cap - nr), nr, id, lbuf);
                 if (id.tid == 0)
                     sh.off = atomicAdd(A.pool_cursor, (unsigned long long)(na + nr));
                 __syncthreads();
@@ -2343,7 +2364,7 @@ __device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh) {
                 }
                 __syncthreads();
                 const int32_t m = sh.m;
-                team_sort(t.scr, m, id);
+                team_sort_via(t.scr, m, id, lbuf);
                 if (id.tid == 0)
                     sh.off = atomicAdd(A.pool_cursor, (unsigned long long)m);
                 __syncthreads();
@@ -2444,32 +2465,35 @@ __device__ __forceinline__ void team_lds_entry(const SweepArgs &A) {
     extern __shared__ __align__(16) char smem[];
     __shared__ TeamSh sh;
     Tab t = carve(smem, A.cap, A.hbits);
-    run_team<false, PERSET>(A, t, sh);
+    run_team<false, PERSET>(A, t, sh, nullptr);
 }
 
 template <bool PERSET>
 __device__ __forceinline__ void team_global_entry(const SweepArgs &A) {
     __shared__ TeamSh sh;
+    __shared__ int32_t lsort[kLdsSort];
     const int slot = blockIdx.x;
     if (slot >= A.n_slots)
         return;
     Tab t = carve_global(A.gtab + (int64_t)slot * A.gtab_stride, A.cap, A.hbits);
-    run_team<true, PERSET>(A, t, sh);
+    run_team<true, PERSET>(A, t, sh, lsort);
 }
 
 // Register bounds: a workgroup steps through one community as a chain of
 // dependent scans, reductions and table updates, so more communities in
-// flight per CU is what hides the latency.  LDS tables of 1,024 entries
-// allow four workgroups per CU, so the LDS kernels take at most 128 VGPRs
-// (four waves per SIMD); the global-table kernels are not LDS-bound and take
-// at most 96 (five).  The values this pushes out of registers are
-// kernel-long constants, spilled once and reloaded per community or scale,
-// not per step.
+// flight per CU is what hides the latency, up to the point where spilled
+// values reloaded inside the steps cost more than the extra communities
+// win.  Both kinds take at most 128 VGPRs (four waves per SIMD): LDS tables
+// of 1,024 entries allow four workgroups per CU anyway, and for the
+// global-table kernels 96 VGPRs (five waves) spilled about 130 registers
+// into scratch that the steps reload (measured: 128 is 7 % faster on the
+// 100k- and 10M-node graphs, 1 % on the 1M one; 168 is slower on the 1M
+// one).
 #define LCD_TEAM_KERNEL(w) __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(w)))
 LCD_TEAM_KERNEL(4) sweep_team_lds_kernel(SweepArgs A) { team_lds_entry<false>(A); }
-LCD_TEAM_KERNEL(5) sweep_team_global_kernel(SweepArgs A) { team_global_entry<false>(A); }
+LCD_TEAM_KERNEL(4) sweep_team_global_kernel(SweepArgs A) { team_global_entry<false>(A); }
 LCD_TEAM_KERNEL(4) query_team_lds_kernel(SweepArgs A) { team_lds_entry<true>(A); }
-LCD_TEAM_KERNEL(5) query_team_global_kernel(SweepArgs A) { team_global_entry<true>(A); }
+LCD_TEAM_KERNEL(4) query_team_global_kernel(SweepArgs A) { team_global_entry<true>(A); }
 #undef LCD_TEAM_KERNEL
 
 // ---------------------------------------------------------------------------
@@ -2754,51 +2778,77 @@ __global__ void seed_init_kernel(const int32_t *row_ptr, const int32_t *perm, in
 
 // A round whose previous round counted no undecided candidate (*prev == 0)
 // does nothing, so that the host can queue many rounds and read the count
-// once.
-template <int R>
-__global__ void seed_select_kernel(const int32_t *row_ptr, const int32_t *col, const int32_t *pos,
-                                   const uint8_t *st, uint8_t *sel, int32_t n, const unsigned *prev,
-                                   unsigned *undecided) {
+// once.  A candidate comes first among the undecided candidates within R
+// hops iff the smallest visiting position of an undecided candidate in its
+// closed R-hop neighbourhood is its own.  That minimum is built one hop at a
+// time: m1[u] = min over the closed neighbourhood of u (undecided
+// candidates only), then, for rule 2, the min of m1 over the closed
+// neighbourhood of v: two passes over the edges instead of a walk over
+// every two-hop path.
+__global__ void seed_min1_kernel(const int32_t *row_ptr, const int32_t *col, const int32_t *pos,
+                                 const uint8_t *st, int32_t n, int32_t *m1, const unsigned *prev,
+                                 unsigned *undecided) {
     if (prev && *prev == 0u)
         return;
     unsigned cnt = 0;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
-        uint8_t ok = 0;
+        int32_t m = INT32_MAX;
         if (st[v] == 0) {
             cnt += 1;
-            ok = 1;
-            const int32_t pv = pos[v];
-            for (int32_t j = row_ptr[v]; j < row_ptr[v + 1] && ok; ++j) {
-                const int32_t u = col[j];
-                if (st[u] == 0 && pos[u] < pv)
-                    ok = 0;
-                if constexpr (R == 2) {
-                    for (int32_t q = row_ptr[u]; q < row_ptr[u + 1] && ok; ++q) {
-                        const int32_t w = col[q];
-                        if (w != v && st[w] == 0 && pos[w] < pv)
-                            ok = 0;
-                    }
-                }
-            }
+            m = pos[v];
         }
-        sel[v] = ok;
+        for (int32_t j = row_ptr[v]; j < row_ptr[v + 1]; ++j) {
+            const int32_t u = col[j];
+            if (st[u] == 0)
+                m = min(m, pos[u]);
+        }
+        m1[v] = m;
     }
     if (cnt)
         atomicAdd(undecided, cnt);
 }
 
-// Selected nodes are pairwise further apart than R hops, so every write
-// below is the same value from whichever thread makes it.
-template <int R>
-__global__ void seed_apply_kernel(const int32_t *row_ptr, const int32_t *col, const uint8_t *sel,
-                                  uint8_t *st, int32_t n, const unsigned *undecided) {
+// Rule 2: sel[v] for undecided v whose closed two-hop minimum is its own.
+__global__ void seed_min2_kernel(const int32_t *row_ptr, const int32_t *col, const int32_t *pos,
+                                 const uint8_t *st, const int32_t *m1, uint8_t *sel, int32_t n,
+                                 const unsigned *undecided) {
     if (*undecided == 0u)
-        return;   // the round found nothing to decide (and wrote no selection)
+        return;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
-        if (!sel[v])
-            continue;
+        uint8_t ok = 0;
+        if (st[v] == 0) {
+            const int32_t pv = pos[v];
+            ok = m1[v] == pv;
+            for (int32_t j = row_ptr[v]; j < row_ptr[v + 1] && ok; ++j)
+                ok = m1[col[j]] >= pv;
+        }
+        sel[v] = ok;
+    }
+}
+
+// The selected candidates become seeds and the candidates within R hops of
+// them are dropped.  Selected nodes are pairwise further apart than R hops,
+// so a selected node's flag is written by its own thread only, and every
+// other write is the same value from whichever thread makes it.  Rule 1
+// selects from m1 directly (a selected node has no selected neighbour, so
+// the flag it reads is the round's).
+template <int R>
+__global__ void seed_apply_kernel(const int32_t *row_ptr, const int32_t *col, const int32_t *pos,
+                                  const int32_t *m1, const uint8_t *sel, uint8_t *st, int32_t n,
+                                  const unsigned *undecided) {
+    if (*undecided == 0u)
+        return;   // the round found nothing to decide
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        if constexpr (R == 1) {
+            if (st[v] != 0 || m1[v] != pos[v])
+                continue;
+        } else {
+            if (!sel[v])
+                continue;
+        }
         st[v] = 1;
         for (int32_t j = row_ptr[v]; j < row_ptr[v + 1]; ++j) {
             const int32_t u = col[j];
@@ -3435,19 +3485,19 @@ hipError_t launch_seed_init(const int32_t *row_ptr, const int32_t *perm, int32_t
 }
 
 hipError_t launch_seed_round(int32_t rule, const int32_t *row_ptr, const int32_t *col, const int32_t *pos,
-                             uint8_t *st, uint8_t *sel, int32_t n, const unsigned *prev, unsigned *undecided,
-                             hipStream_t s) {
+                             uint8_t *st, uint8_t *sel, int32_t *m1, int32_t n, const unsigned *prev,
+                             unsigned *undecided, hipStream_t s) {
     if (n == 0)
         return hipSuccess;
-    const dim3 g(grid_for(n, 256)), b(256);
-    if (rule == 1) {
-        hipLaunchKernelGGL(seed_select_kernel<1>, g, b, 0, s, row_ptr, col, pos, st, sel, n, prev, undecided);
-        hipLaunchKernelGGL(seed_apply_kernel<1>, g, b, 0, s, row_ptr, col, sel, st, n, undecided);
-    } else if (rule == 2) {
-        hipLaunchKernelGGL(seed_select_kernel<2>, g, b, 0, s, row_ptr, col, pos, st, sel, n, prev, undecided);
-        hipLaunchKernelGGL(seed_apply_kernel<2>, g, b, 0, s, row_ptr, col, sel, st, n, undecided);
-    } else {
+    if (rule != 1 && rule != 2)
         return hipErrorInvalidValue;
+    const dim3 g(grid_for(n, 256)), b(256);
+    hipLaunchKernelGGL(seed_min1_kernel, g, b, 0, s, row_ptr, col, pos, st, n, m1, prev, undecided);
+    if (rule == 1) {
+        hipLaunchKernelGGL(seed_apply_kernel<1>, g, b, 0, s, row_ptr, col, pos, m1, sel, st, n, undecided);
+    } else {
+        hipLaunchKernelGGL(seed_min2_kernel, g, b, 0, s, row_ptr, col, pos, st, m1, sel, n, undecided);
+        hipLaunchKernelGGL(seed_apply_kernel<2>, g, b, 0, s, row_ptr, col, pos, m1, sel, st, n, undecided);
     }
     return hipGetLastError();
 }

@@ -687,7 +687,9 @@ lcd_status lcd_server_create(const lcd_graph *g, int64_t mem_budget, int32_t max
     //    slowest query, so a query that fits a small table never waits for
     //    one that needs a large table) and six lanes: one per LDS tier,
     //    three for the 16,384-entry tier (about a third of a query stream
-    //    ends there), one for the whole-graph tier.
+    //    ends there), one for the whole-graph tier; with 10 or more queues
+    //    five lanes for the 16,384-entry tier (eight in all), so that a
+    //    query leaving an earlier stage finds a free lane sooner.
     //  * fewer: tier 0, then all later tiers; four lanes, one for tier 0.
     int hw_queues = 4;
     if (const char *e = std::getenv("GPU_MAX_HW_QUEUES"))
@@ -703,11 +705,14 @@ lcd_status lcd_server_create(const lcd_graph *g, int64_t mem_budget, int32_t max
             S->stages[S->n_stages++] = Stage{1, S->tp.n};
     }
     static const int kPerTierLanes[6] = {0, 1, 2, 2, 2, 3};
+    static const int kPerTierWide[8] = {0, 1, 2, 2, 2, 2, 2, 3};
     static const int kTwoStageLanes[4] = {0, 1, 1, 1};
-    const int n_lanes = per_tier ? 6 : 4;
+    const bool wide = per_tier && hw_queues >= 10;
+    const int n_lanes = per_tier ? (wide ? 8 : 6) : 4;
     int lane_stage[kMaxLanes] = {0};
     for (int i = 0; i < n_lanes; ++i)
-        lane_stage[i] = std::min(per_tier ? kPerTierLanes[i] : kTwoStageLanes[i], S->n_stages - 1);
+        lane_stage[i] = std::min(per_tier ? (wide ? kPerTierWide[i] : kPerTierLanes[i]) : kTwoStageLanes[i],
+                                 S->n_stages - 1);
     const int32_t max_q = std::max<int32_t>(1, std::min<int32_t>(1024, max_slots));
     const int64_t max_seed = std::max<int64_t>(65536, (int64_t)g->n);
     const int64_t pool_cap = std::max<int64_t>((int64_t)g->n, 1 << 22);

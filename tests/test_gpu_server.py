@@ -58,11 +58,12 @@ def test_server_mix_equals_alone_and_oracle(L, graph):
     heavy = [(W.bfs_prefix(g, r, 256), 0.5) for r in (7, 911, 4242)]
     queries = heavy + list(zip(sets, alphas))
     o = oracle.Oracle.from_graph(g)
-    # both lane layouts: one stage per tier on six lanes (8 or more hardware
-    # queues), and tier 0 then the rest on four lanes (fewer queues); the
-    # server reads the queue count when it is created
+    # every lane layout: one stage per tier on eight lanes (10 or more
+    # hardware queues) or six (8 or 9), and tier 0 then the rest on four
+    # lanes (fewer queues); the server reads the queue count when it is
+    # created
     import os
-    for queues, cap in (("12", 1024), ("12", 256), ("4", 1024)):
+    for queues, cap in (("12", 1024), ("12", 256), ("8", 1024), ("4", 1024)):
         old_q = os.environ.get("GPU_MAX_HW_QUEUES")
         os.environ["GPU_MAX_HW_QUEUES"] = queues
         try:
@@ -73,7 +74,7 @@ def test_server_mix_equals_alone_and_oracle(L, graph):
             else:
                 os.environ["GPU_MAX_HW_QUEUES"] = old_q
         with srv:
-            assert srv.stats()["lanes"] == (6 if queues == "12" else 4)
+            assert srv.stats()["lanes"] == {"12": 8, "8": 6, "4": 4}[queues]
             tickets = [srv.submit(s, a) for s, a in queries]
             mix = [srv.result(t, 120_000) for t in tickets]
             st = srv.stats()
