@@ -166,25 +166,39 @@ class CpuBaseline:
                     parity_on_sample=("bit-exact members, K, V, counters; f within 1e-12" if ok else "MISMATCH"))
 
 
+# committed rocprofv3 summaries, per workload (a summary is used only while
+# the kernel source, the workload and the tier layout match the run)
+PROFILE_OF = {"medium": "sweep_lfr2-100k", "xl64": "sweep_lfr3-10M-share64"}
+
+
+def _profile_text(workload_name: str, kind: str):
+    import hashlib
+    import re
+    name = PROFILE_OF.get(workload_name)
+    if name is None:
+        return None
+    path = os.path.join(ROOT, "profiles", "%s_%s.md" % (name, kind))
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_sha = re.search(r"kernels_sha256:? ([0-9a-f]{64})", text)
+    src = os.path.join(ROOT, "paper_1301_0955_amd", "csrc", "lcd_kernels.hip")
+    if not m_sha or hashlib.sha256(open(src, "rb").read()).hexdigest() != m_sha.group(1):
+        return None
+    return text
+
+
 def profiled_traffic(kernel: str, tier_caps, workload_name: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, if it was taken on this workload, tier layout and kernel source;
     else None."""
-    import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "sweep_lfr2-100k_kernels.md")
-    if workload_name != "medium" or not os.path.exists(path):
+    text = _profile_text(workload_name, "kernels")
+    if text is None:
         return None
-    text = open(path).read()
-    m_sha = re.search(r"^kernels_sha256: ([0-9a-f]{64})", text, re.M)
     m_tr = re.search(r"^traffic_bytes_per_launch: (\{.*\})", text, re.M)
     m_caps = re.search(r"^profiled_tier_capacities: (\[.*\])", text, re.M)
-    if not (m_sha and m_tr and m_caps):
-        return None
-    src = os.path.join(ROOT, "paper_1301_0955_amd", "csrc", "lcd_kernels.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m_sha.group(1):
-        return None
-    if json.loads(m_caps.group(1)) != list(tier_caps):
+    if not (m_tr and m_caps) or json.loads(m_caps.group(1)) != list(tier_caps):
         return None
     return json.loads(m_tr.group(1)).get(kernel)
 
@@ -192,24 +206,18 @@ def profiled_traffic(kernel: str, tier_caps, workload_name: str):
 def profiled_utilisation(kernel: str, workload_name: str):
     """VALU-issue and FP64 fractions of `kernel` from the committed counter
     summary of this kernel source on this workload; else None."""
-    import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "sweep_lfr2-100k_utilisation.md")
-    if workload_name != "medium" or not os.path.exists(path):
+    text = _profile_text(workload_name, "utilisation")
+    if text is None:
         return None
-    text = open(path).read()
-    m_sha = re.search(r"kernels_sha256 ([0-9a-f]{64})", text)
     m_u = re.search(r"^utilisation: (\{.*\})", text, re.M)
-    if not (m_sha and m_u):
-        return None
-    src = os.path.join(ROOT, "paper_1301_0955_amd", "csrc", "lcd_kernels.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m_sha.group(1):
+    if not m_u:
         return None
     u = json.loads(m_u.group(1)).get(kernel)
     if u is None:
         return None
     return dict(valu_issue_frac=u["valu_issue_frac"], fp64_frac_upper=u["fp64_frac_upper"],
-                source="profiles/sweep_lfr2-100k_utilisation.md")
+                source="profiles/%s_utilisation.md" % PROFILE_OF[workload_name])
 
 
 def W_seed_perm(g):
@@ -414,9 +422,32 @@ def sweep_compare(lcd, G, g, sp, sn, sc, steps, prm):
 CPU_SETS_PER_CORE = {"small": 100, "medium": 300, "large": 40, "xl": 12}
 
 
-def medium_compare(lcd, steps):
+def seeds_bench(lcd, G, g, with_oracle: bool) -> dict:
+    """Seed selection (initialisation of Algorithm 2), rules 1 and 2, on the
+    device (whole call, two runs, the second timed) vs the oracle on one
+    host core; the seeds must be identical."""
+    perm = W_seed_perm(g)
+    info = {}
+    for rule in (1, 2):
+        lcd.lcd_seeds(G, perm, rule)
+        t0 = time.perf_counter()
+        dev = lcd.lcd_seeds(G, perm, rule)
+        t_dev = time.perf_counter() - t0
+        entry = dict(seeds=int(dev.size), ms_device_call=round(t_dev * 1e3, 3))
+        if with_oracle:
+            import oracle
+            t0 = time.perf_counter()
+            ref = oracle.Oracle.from_graph(g).seeds(perm, rule)
+            entry["ms_oracle_1core"] = round((time.perf_counter() - t0) * 1e3, 3)
+            entry["identical"] = bool(np.array_equal(dev, ref))
+        info["rule%d" % rule] = entry
+    return info
+
+
+def medium_compare(lcd, steps, with_seeds=False, with_oracle=True):
     """The 100k-node workload: autotuned persistent sweep vs the per-scale
-    launch loop (device time of each; identical counters and records)."""
+    launch loop (device time of each; identical counters and records), and
+    optionally seed selection on its graph."""
     from paper_1301_0955_amd import workloads as W
     g, sp, sn, sc = W.workload_medium()
     G = lcd.Graph.from_workload(g)
@@ -424,6 +455,8 @@ def medium_compare(lcd, steps):
     out["workload"] = ("lfr2-100k: 100,000-node 2-level LFR-style graph (degree exp 2.5, mean 20, max 100; "
                        "community sizes exp 1.5 on [20,200]; mixing 0.3; unweighted), rule-1 seeds (%d), "
                        "32 scales on [0.5,1]" % (sp.size - 1))
+    if with_seeds:
+        out["seed_selection"] = seeds_bench(lcd, G, g, with_oracle)
     G.free()
     return out
 
@@ -472,6 +505,8 @@ def main():
                     help="small | medium | large | xl[STRIDE] (the 10M-node graph with every STRIDE-th seed set, "
                          "default %d)" % XL_STRIDE)
     ap.add_argument("--lds-capacity", type=int, default=0)
+    ap.add_argument("--output", choices=("delta", "full"), default="delta",
+                    help="member pool layout of the timed sweep")
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--cpu-sets", type=int, default=0, help="oracle sample size (0 = sized per workload)")
@@ -489,6 +524,7 @@ def main():
     ap.add_argument("--no-merge", action="store_true", help="skip the check-and-merge runs")
     ap.add_argument("--no-nmi", action="store_true", help="skip the NMI analysis leg")
     ap.add_argument("--no-multigraph", action="store_true", help="skip the 64-graph batched sweep")
+    ap.add_argument("--no-hipgraph", action="store_true", help="skip the hipGraph replay of the timed sweep")
     ap.add_argument("--serve-qps", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--serve-warmup", type=float, default=2.0)
@@ -519,6 +555,7 @@ def main():
     t0 = time.perf_counter()
     g, sp, sn, sc, desc = workload(args.workload)
     wl_key = "xl" if args.workload.startswith("xl") else args.workload
+    prof_key = ("xl%d" % int(args.workload[2:] or XL_STRIDE)) if wl_key == "xl" else wl_key
     g_n, g_nnz = int(g.n), int(g.nnz)
     log("workload %s ready in %.1f s: n=%d nnz=%d sets=%d scales=%d"
         % (args.workload, time.perf_counter() - t0, g.n, g.nnz, sp.size - 1, sc.size))
@@ -545,6 +582,9 @@ def main():
     prm = dict(lds_capacity=args.lds_capacity, waves_per_block=args.waves_per_block,
                blocks_per_cu=args.blocks_per_cu)
     tuned = None
+    # the 10M-node share keeps the library's static sizing for graphs of
+    # millions of nodes (deterministic, so the committed counter profile of
+    # this configuration applies to every run)
     do_tune = not any(prm.values()) and not args.no_tune and (wl_key != "xl" or args.tune)
     if do_tune:
         t0 = time.perf_counter()
@@ -552,6 +592,9 @@ def main():
         log("autotuned in %.1f s: %s (sample of every %d-th set)"
             % (time.perf_counter() - t0, tuned["best"], tuned["sample_stride"]))
     torch.cuda.synchronize()
+    # member pool as deltas between scales (the sorted list only at a set's
+    # first scale), or whole lists at every changed scale
+    prm["output_mode"] = lcd.LCD_OUT_DELTA if args.output == "delta" else lcd.LCD_OUT_FULL
 
     # one result object; every step re-runs the whole sweep into it (inputs
     # and outputs stay on the device; the first call allocates and sizes the
@@ -577,16 +620,18 @@ def main():
     log("timed %d steps: %.2f ms/step wall" % (args.steps, ms_step))
 
     # the same sweep captured in a hipGraph and replayed (two replays)
-    rg = lcd.lcd_sweep(G, d_sc, d_sp, d_sn, use_graph=1, **prm)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(2):
-        rg.rerun()
-    torch.cuda.synchronize()
-    graph_ms = 1e3 * (time.perf_counter() - t0) / 2
-    graph_same = bool(np.array_equal(rg.counters(), totals))
-    rg.free()
-    log("hipGraph replay %.2f ms/step" % graph_ms)
+    graph_ms, graph_same = None, None
+    if not args.no_hipgraph:
+        rg = lcd.lcd_sweep(G, d_sc, d_sp, d_sn, use_graph=1, **prm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(2):
+            rg.rerun()
+        torch.cuda.synchronize()
+        graph_ms = 1e3 * (time.perf_counter() - t0) / 2
+        graph_same = bool(np.array_equal(rg.counters(), totals))
+        rg.free()
+        log("hipGraph replay %.2f ms/step" % graph_ms)
 
     gains = totals[0]
     ms_dev = float(np.mean([s["ms_total"] for s in stats]))
@@ -605,7 +650,7 @@ def main():
     all_bytes = (sum(gather_bytes(st0["tier"][k], weighted) for k in range(nt))
                  + output_bytes(int(totals[2]), int(sn.size), n_rec))
     scanned = [int(st0["tier"][k]["entries_scanned"]) for k in range(nt)]
-    traffic = profiled_traffic(kname, st0["tier_capacity"][:nt], wl_key)
+    traffic = profiled_traffic(kname, st0["tier_capacity"][:nt], prof_key)
     roofline = dict(bound="hbm", kernel=kname, tier=k_dom, achieved=round(achieved, 3), peak=HBM_PEAK_GBS,
                     unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 7), traffic=traffic,
                     traffic_GBs=None if traffic is None else round(traffic / (kms * 1e-3) / 1e9, 2),
@@ -620,7 +665,7 @@ def main():
                                    output_rule="4 B per member change between scales (at most seeds + moves) "
                                                "+ 24 B (K, V, f) per (set, scale)"),
                     scanned_entries=scanned, scanned_over_gains=round(sum(scanned) / max(gains, 1), 3),
-                    secondary=profiled_utilisation(kname, wl_key),
+                    secondary=profiled_utilisation(kname, prof_key),
                     tiers=[dict(kernel=KERNEL_OF_KIND[st0["tier_kind"][k]],
                                 table_entries=st0["tier_capacity"][k], ms=round(ms_tier[k], 3),
                                 sets_finished=st0["tier"][k]["sets_finished"],
@@ -650,29 +695,24 @@ def main():
     res.free()
 
     # seed selection (initialisation of Algorithm 2) on the device vs the oracle
+    # (on the 100k-node graph when the headline graph is the 10M one, whose
+    # rule-2 oracle run alone would take minutes)
     seeds_info = {}
     if wl_key != "xl":
-        perm = W_seed_perm(g)
-        for rule in (1, 2):
-            t0 = time.perf_counter()
-            dev = lcd.lcd_seeds(G, perm, rule)
-            t_dev = time.perf_counter() - t0
-            entry = dict(seeds=int(dev.size), ms_device_call=round(t_dev * 1e3, 3))
-            if not args.no_cpu_baseline:
-                import oracle
-                t0 = time.perf_counter()
-                ref = oracle.Oracle.from_graph(g).seeds(perm, rule)
-                entry["ms_oracle_1core"] = round((time.perf_counter() - t0) * 1e3, 3)
-                entry["identical"] = bool(np.array_equal(dev, ref))
-            seeds_info["rule%d" % rule] = entry
+        seeds_info = seeds_bench(lcd, G, g, not args.no_cpu_baseline)
+        seeds_info["graph"] = desc
         log("seed selection: %s" % seeds_info)
     G.free()
     del g
 
-    medium = None if (args.no_medium or wl_key == "medium") else medium_compare(lcd, 2)
+    medium = None if (args.no_medium or wl_key == "medium") else medium_compare(
+        lcd, 2, with_seeds=wl_key == "xl", with_oracle=not args.no_cpu_baseline)
     if medium:
         log("lfr2-100k sweep: %.1f ms device, per-scale loop %.1f ms"
             % (medium["sweep_ms_device"], medium["per_scale_loop_ms_device"]))
+        if "seed_selection" in medium:
+            seeds_info = dict(medium.pop("seed_selection"), graph="lfr2-100k")
+            log("seed selection (lfr2-100k): %s" % seeds_info)
 
     merge = None
     if not args.no_merge:
@@ -757,11 +797,11 @@ def main():
     out["config"] = {"workload": desc, "n": g_n, "nnz": g_nnz, "seed_sets": int(sp.size - 1), "scales": int(S),
                      "lds_capacity": st0["lds_capacity"], "waves_per_block": st0["waves_per_block"],
                      "grid_blocks": st0["grid_blocks"], "tiers": nt,
-                     "tier_capacity": st0["tier_capacity"][:nt],
+                     "tier_capacity": st0["tier_capacity"][:nt], "output": args.output,
                      "tuned": tuned["best"] if tuned else None}
     out.update({
         "sweep_ms_device": round(ms_dev, 4),
-        "hipgraph_ms_per_step": round(graph_ms, 4),
+        "hipgraph_ms_per_step": round(graph_ms, 4) if graph_ms is not None else None,
         "hipgraph_identical_counters": graph_same,
         "gains_per_step": int(gains),
         "counters": {"G": totals[0], "R": totals[1], "M": totals[2], "C": totals[3]},

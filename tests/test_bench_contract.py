@@ -2,6 +2,7 @@
 it reads its HBM traffic and utilisation from parse for the kernel source
 they were taken on (no GPU needed)."""
 import hashlib
+import json
 import os
 import re
 import subprocess
@@ -23,12 +24,12 @@ def test_profile_summaries_parse_for_their_kernel_source():
     import bench
     src = os.path.join(ROOT, "paper_1301_0955_amd", "csrc", "lcd_kernels.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    text = open(os.path.join(ROOT, "profiles", "sweep_lfr2-100k_kernels.md")).read()
+    text = open(os.path.join(ROOT, "profiles", "sweep_lfr3-10M-share64_kernels.md")).read()
     m = re.search(r"^kernels_sha256: ([0-9a-f]{64})", text, re.M)
     assert m
-    caps = [512, 1024, 16384, 131072]
-    t = bench.profiled_traffic("sweep_team_global_kernel", caps, "medium")
-    u = bench.profiled_utilisation("sweep_team_global_kernel", "medium")
+    caps = json.loads(re.search(r"^profiled_tier_capacities: (\[.*\])", text, re.M).group(1))
+    t = bench.profiled_traffic("sweep_team_global_kernel", caps, "xl64")
+    u = bench.profiled_utilisation("sweep_team_global_kernel", "xl64")
     if m.group(1) == sha:
         # taken on this source: both summaries give numbers for the dominant kernel
         assert t is not None and t > 0
@@ -38,4 +39,4 @@ def test_profile_summaries_parse_for_their_kernel_source():
         assert t is None and u is None
     # other workloads or tier layouts never borrow the numbers
     assert bench.profiled_traffic("sweep_team_global_kernel", caps, "large") is None
-    assert bench.profiled_traffic("sweep_team_global_kernel", [256, 1024, 16384, 131072], "medium") is None
+    assert bench.profiled_traffic("sweep_team_global_kernel", [256] + list(caps[1:]), "xl64") is None
