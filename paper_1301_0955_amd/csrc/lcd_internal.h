@@ -107,7 +107,8 @@ constexpr int kMaxTiers = 4;
 constexpr int kStatWords = 11;  // statistics words per tier
 constexpr int kTeamMaxThreads = 512;
 
-// Bytes per table entry (dense arrays + scratch) and per hash slot.
+// LDS tables: bytes per entry (one array per field + scratch) and per hash
+// slot.
 constexpr int kEntryBytes = 4 /*node*/ + 4 /*d|flags*/ + 4 /*k*/ + 8 /*rank*/ + 4 /*scratch*/;
 constexpr int kSlotBytes = 4;
 
@@ -115,13 +116,19 @@ __host__ __device__ constexpr int64_t table_bytes(int32_t cap, int32_t hbits) {
     return (int64_t)cap * kEntryBytes + ((int64_t)1 << hbits) * kSlotBytes;
 }
 
-// Tables in global memory also hold the workgroup kernel's rank-bucketed
-// queue and fresh list (one int32 entry index per table entry each), after
-// the hash slots.
+// Global tables hold the LDS layout plus the workgroup kernel's
+// rank-bucketed queue and fresh list (one int32 entry index per table entry
+// each); from kRecordMinEntries entries on, the fields of an entry are one
+// 32-byte record instead (d|flags, node, k, rank), since the steps on such
+// tables reach most entries at random through the queue.
+constexpr int kRecordBytes = 32;
+constexpr int32_t kRecordMinEntries = 65536;
 constexpr int kQueueBytes = 4 /*bucketed queue*/ + 4 /*fresh list*/;
 
 __host__ __device__ constexpr int64_t global_table_bytes(int32_t cap, int32_t hbits) {
-    return table_bytes(cap, hbits) + (int64_t)cap * kQueueBytes;
+    return cap >= kRecordMinEntries
+               ? (int64_t)cap * (kRecordBytes + 4 /*scratch*/ + kQueueBytes) + ((int64_t)1 << hbits) * kSlotBytes
+               : table_bytes(cap, hbits) + (int64_t)cap * kQueueBytes;
 }
 
 hipError_t launch_degrees(const int32_t *row_ptr, const uint8_t *w, int32_t *kdeg, int32_t n,
