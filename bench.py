@@ -42,6 +42,14 @@ SUMMARY_BYTES = 24        # per (set, scale): K, V, f (the survey's algorithmic 
 XL_STRIDE = 64            # default seed share of the 10M-node workload
 KERNEL_OF_KIND = {0: "sweep_lds_kernel", 1: "sweep_global_kernel", 2: "sweep_team_lds_kernel",
                   3: "sweep_team_global_kernel"}
+RECORD_MIN_ENTRIES = 65536   # workgroup tables this large run the record-layout kernel
+
+
+def kernel_of(kind: int, cap: int) -> str:
+    """Name of the kernel that runs a tier of this kind and table size."""
+    if kind == 3 and cap >= RECORD_MIN_ENTRIES:
+        return "sweep_team_global_rec_kernel"
+    return KERNEL_OF_KIND[kind]
 
 
 def log(msg):
@@ -411,7 +419,8 @@ def sweep_compare(lcd, G, g, sp, sn, sc, steps, prm):
     return dict(ms_per_sweep_wall=round(wall * 1e3, 3), sweep_ms_device=round(ms, 3),
                 ms_tier=[round(float(np.mean([x["ms_tier"][k] for x in sts])), 3)
                          for k in range(sts[0]["tiers"])],
-                tier_kernels=[KERNEL_OF_KIND[k] for k in sts[0]["tier_kind"][:sts[0]["tiers"]]],
+                tier_kernels=[kernel_of(k, c) for k, c in zip(sts[0]["tier_kind"][:sts[0]["tiers"]],
+                                                              sts[0]["tier_capacity"])],
                 tuned=tuned["best"],
                 gains=int(tot[0]), gains_per_s=tot[0] / (wall), spilled_sets=sts[0]["n_spilled"],
                 lds_capacity=sts[0]["lds_capacity"],
@@ -643,7 +652,7 @@ def main():
     k_dom = int(np.argmax(ms_tier))
     t_dom = st0["tier"][k_dom]
     kbytes = gather_bytes(t_dom, weighted)
-    kname = KERNEL_OF_KIND[st0["tier_kind"][k_dom]]
+    kname = kernel_of(st0["tier_kind"][k_dom], st0["tier_capacity"][k_dom])
     kms = ms_tier[k_dom]
     achieved = kbytes / (kms * 1e-3) / 1e9
     n_rec = (sp.size - 1) * S
@@ -666,7 +675,7 @@ def main():
                                                "+ 24 B (K, V, f) per (set, scale)"),
                     scanned_entries=scanned, scanned_over_gains=round(sum(scanned) / max(gains, 1), 3),
                     secondary=profiled_utilisation(kname, prof_key),
-                    tiers=[dict(kernel=KERNEL_OF_KIND[st0["tier_kind"][k]],
+                    tiers=[dict(kernel=kernel_of(st0["tier_kind"][k], st0["tier_capacity"][k]),
                                 table_entries=st0["tier_capacity"][k], ms=round(ms_tier[k], 3),
                                 sets_finished=st0["tier"][k]["sets_finished"],
                                 entries_scanned=scanned[k],

@@ -121,13 +121,17 @@ __host__ __device__ constexpr int64_t table_bytes(int32_t cap, int32_t hbits) {
 // each); from kRecordMinEntries entries on, the fields of an entry are one
 // 32-byte record instead (d|flags, node, k, rank), since the steps on such
 // tables reach most entries at random through the queue.
+// Their hash slots hold the node id beside the entry index (8 bytes), so a
+// lookup is one load.
 constexpr int kRecordBytes = 32;
 constexpr int32_t kRecordMinEntries = 65536;
+constexpr int kPairSlotBytes = 8;
 constexpr int kQueueBytes = 4 /*bucketed queue*/ + 4 /*fresh list*/;
 
 __host__ __device__ constexpr int64_t global_table_bytes(int32_t cap, int32_t hbits) {
     return cap >= kRecordMinEntries
-               ? (int64_t)cap * (kRecordBytes + 4 /*scratch*/ + kQueueBytes) + ((int64_t)1 << hbits) * kSlotBytes
+               ? (int64_t)cap * (kRecordBytes + kQueueBytes) + (((int64_t)cap * 4 /*scratch*/ + 7) & ~(int64_t)7) +
+                     ((int64_t)1 << hbits) * kPairSlotBytes
                : table_bytes(cap, hbits) + (int64_t)cap * kQueueBytes;
 }
 

@@ -120,7 +120,8 @@ struct Tab {
     __device__ __forceinline__ uint32_t &DV(int32_t i) const { return *(uint32_t *)(dvb + (uint32_t)i * dvs); }
     __device__ __forceinline__ int32_t &KV(int32_t i) const { return *(int32_t *)(kvb + (uint32_t)i * kvs); }
     int32_t *scr;
-    int32_t *hs;
+    int32_t *hs;      // hash slots: entry index (LDS and array-layout tables)
+    uint64_t *hp;     // hash slots: node id << 32 | entry index (record tables)
     int32_t *sq;      // global tables: rank-bucketed queue (entry indices)
     int32_t *fr;      // global tables: fresh list (entry indices)
     uint32_t hmask;
@@ -140,6 +141,7 @@ __device__ __forceinline__ Tab carve(char *base, int cap, int hbits) {
     t.nodes = t.dvs = t.kvs = 4;
     t.scr = (int32_t *)(base + (size_t)cap * 20);
     t.hs = (int32_t *)(base + (size_t)cap * 24);
+    t.hp = nullptr;
     t.sq = nullptr;
     t.fr = nullptr;
     t.hbits = hbits;
@@ -151,31 +153,42 @@ __device__ __forceinline__ Tab carve(char *base, int cap, int hbits) {
 // Global table: the LDS layout then the bucketed queue i32[cap] and the
 // fresh list i32[cap]; from kRecordMinEntries entries on, records
 // {d|flags u32, node i32, degree i32, -, rank f64, -} of kRecordBytes, then
-// scratch i32[cap], hash slots i32[2^hbits], queue and fresh list.
-__device__ __forceinline__ Tab carve_global(char *base, int cap, int hbits) {
-    if (cap < kRecordMinEntries) {
+// scratch i32[cap] (padded to 8 bytes), hash slots u64[2^hbits] of
+// node << 32 | index, queue and fresh list.
+template <bool REC>
+__device__ __forceinline__ Tab carve_global_as(char *base, int cap, int hbits) {
+    if constexpr (!REC) {
         Tab t = carve(base, cap, hbits);
         char *q = base + table_bytes(cap, hbits);
         t.sq = (int32_t *)q;
         t.fr = (int32_t *)(q + (size_t)cap * 4);
         return t;
+    } else {
+        Tab t;
+        t.dvb = base;
+        t.nodeb = base + 4;
+        t.kvb = base + 8;
+        t.rkb = base + 16;
+        t.rks = t.nodes = t.dvs = t.kvs = kRecordBytes;
+        char *p = base + (size_t)cap * kRecordBytes;
+        t.scr = (int32_t *)p;
+        const size_t scr_bytes = ((size_t)cap * 4 + 7) & ~(size_t)7;
+        t.hs = nullptr;
+        t.hp = (uint64_t *)(p + scr_bytes);
+        char *q = p + scr_bytes + ((size_t)1 << hbits) * kPairSlotBytes;
+        t.sq = (int32_t *)q;
+        t.fr = (int32_t *)(q + (size_t)cap * 4);
+        t.hbits = hbits;
+        t.hmask = (1u << hbits) - 1;
+        t.cap = cap;
+        return t;
     }
-    Tab t;
-    t.dvb = base;
-    t.nodeb = base + 4;
-    t.kvb = base + 8;
-    t.rkb = base + 16;
-    t.rks = t.nodes = t.dvs = t.kvs = kRecordBytes;
-    char *p = base + (size_t)cap * kRecordBytes;
-    t.scr = (int32_t *)p;
-    t.hs = (int32_t *)(p + (size_t)cap * 4);
-    char *q = p + (size_t)cap * 4 + ((size_t)1 << hbits) * kSlotBytes;
-    t.sq = (int32_t *)q;
-    t.fr = (int32_t *)(q + (size_t)cap * 4);
-    t.hbits = hbits;
-    t.hmask = (1u << hbits) - 1;
-    t.cap = cap;
-    return t;
+}
+
+// The layout a global table of cap entries has.
+__device__ __forceinline__ Tab carve_global(char *base, int cap, int hbits) {
+    return cap >= kRecordMinEntries ? carve_global_as<true>(base, cap, hbits)
+                                    : carve_global_as<false>(base, cap, hbits);
 }
 
 template <bool GLOBAL>
@@ -244,6 +257,7 @@ struct Ctx {
     const int32_t *kdeg;
     const double *logtab;
     int32_t logtab_last;   // largest valid index of logtab
+    int32_t n;             // nodes
 };
 
 // queue rank R(d, k) = L(2d) - alpha L(k); 2d <= 2k <= 2 max degree, so both
@@ -254,9 +268,25 @@ __device__ __forceinline__ double rank_of(const Ctx &c, int32_t d, int32_t k, do
     return c.logtab[i2] - alpha * c.logtab[ik];
 }
 
+constexpr uint64_t kEmptyPair = ~0ull;   // node -1, index -1
+
 template <bool GLOBAL>
 __device__ __forceinline__ int32_t tab_find(const Tab &t, int32_t u, uint32_t &err) {
     uint32_t p = hash_of(u, t.hbits);
+    if constexpr (GLOBAL) {
+        if (t.hp) {
+            for (uint32_t it = 0; it <= t.hmask; ++it) {
+                const uint64_t s = __hip_atomic_load(&t.hp[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (s == kEmptyPair)
+                    return -1;
+                if ((int32_t)(uint32_t)(s >> 32) == u)
+                    return (int32_t)(uint32_t)s;
+                p = (p + 1) & t.hmask;
+            }
+            err |= ERR_PROBE;
+            return -1;
+        }
+    }
     for (uint32_t it = 0; it <= t.hmask; ++it) {
         int32_t i = hs_load<GLOBAL>(&t.hs[p]);
         if (i < 0)
@@ -267,6 +297,50 @@ __device__ __forceinline__ int32_t tab_find(const Tab &t, int32_t u, uint32_t &e
     }
     err |= ERR_PROBE;
     return -1;
+}
+
+// Put entry idx of node u into its hash slot (linear probing).
+template <bool GLOBAL>
+__device__ __forceinline__ void tab_slot_insert(const Tab &t, int32_t u, int32_t idx, uint32_t &err) {
+    uint32_t p = hash_of(u, t.hbits);
+    uint32_t it = 0;
+    if (GLOBAL && t.hp) {
+        const uint64_t v = ((uint64_t)(uint32_t)u << 32) | (uint32_t)idx;
+        for (; it <= t.hmask; ++it) {
+            if (atomicCAS((unsigned long long *)&t.hp[p], (unsigned long long)kEmptyPair,
+                          (unsigned long long)v) == (unsigned long long)kEmptyPair)
+                break;
+            p = (p + 1) & t.hmask;
+        }
+    } else {
+        for (; it <= t.hmask; ++it) {
+            if (atomicCAS(&t.hs[p], -1, idx) == -1)
+                break;
+            p = (p + 1) & t.hmask;
+        }
+    }
+    if (it > t.hmask)
+        err |= ERR_PROBE;
+}
+
+// Empty the hash slot of entry i (global tables, before the slab's next
+// community).
+template <bool GLOBAL>
+__device__ __forceinline__ void tab_slot_clear(const Tab &t, int32_t i) {
+    uint32_t p = hash_of(t.NODE(i), t.hbits);
+    for (uint32_t it = 0; it <= t.hmask; ++it) {
+        if (t.hp) {
+            const uint64_t s = __hip_atomic_load(&t.hp[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((int32_t)(uint32_t)s == i) {
+                __hip_atomic_store(&t.hp[p], kEmptyPair, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return;
+            }
+        } else if (hs_load<GLOBAL>(&t.hs[p]) == i) {
+            hs_store<GLOBAL>(&t.hs[p], -1);
+            return;
+        }
+        p = (p + 1) & t.hmask;
+    }
 }
 
 // Dense index of u for every active lane, inserting absent ids.  All active
@@ -290,15 +364,7 @@ __device__ int32_t tab_ensure(const Tab &t, St &st, const Ctx &c, bool act, int3
         t.NODE(idx) = u;
         t.KV(idx) = c.kdeg[u];
         t.DV(idx) = 0u;
-        uint32_t p = hash_of(u, t.hbits);
-        uint32_t it = 0;
-        for (; it <= t.hmask; ++it) {
-            if (atomicCAS(&t.hs[p], -1, idx) == -1)
-                break;
-            p = (p + 1) & t.hmask;
-        }
-        if (it > t.hmask)
-            st.err |= ERR_PROBE;
+        tab_slot_insert<GLOBAL>(t, u, idx, st.err);
     }
     st.count += nn;
     wsync<GLOBAL>();
@@ -688,6 +754,7 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
     c.kdeg = A.g.kdeg;
     c.logtab = A.g.logtab;
     c.logtab_last = A.g.logtab_n - 1;
+    c.n = A.g.n;
     const uint32_t n_items = A.tier == 0 ? (uint32_t)A.n_sets : A.ctl->ovf_count[A.in_from];
     // What one item leaves for the device-wide counters is published by
     // lane 0 at the top of the next iteration, in the same lane-0 block that
@@ -985,16 +1052,8 @@ __device__ void run_wave(const SweepArgs &A, const Tab &t, int lane) {
         if constexpr (GLOBAL) {
             // leave the slab's hash empty for the next community
             wsync<GLOBAL>();
-            for (int32_t i = lane; i < st.count; i += 64) {
-                uint32_t p = hash_of(t.NODE(i), t.hbits);
-                for (uint32_t it = 0; it <= t.hmask; ++it) {
-                    if (hs_load<GLOBAL>(&t.hs[p]) == i) {
-                        hs_store<GLOBAL>(&t.hs[p], -1);
-                        break;
-                    }
-                    p = (p + 1) & t.hmask;
-                }
-            }
+            for (int32_t i = lane; i < st.count; i += 64)
+                tab_slot_clear<GLOBAL>(t, i);
             wsync<GLOBAL>();
         }
     }
@@ -1137,15 +1196,7 @@ __device__ int32_t team_ensure(const Tab &t, TeamSh &sh, St &st, const Ctx &c, b
             t.KV(idx) = c.kdeg[u];
             t.DV(idx) = 0u;
             st.inserted += 1;
-            uint32_t p = hash_of(u, t.hbits);
-            uint32_t it = 0;
-            for (; it <= t.hmask; ++it) {
-                if (atomicCAS(&t.hs[p], -1, idx) == -1)
-                    break;
-                p = (p + 1) & t.hmask;
-            }
-            if (it > t.hmask)
-                st.err |= ERR_PROBE;
+            tab_slot_insert<GLOBAL>(t, u, idx, st.err);
         }
     }
     __syncthreads();
@@ -1257,6 +1308,21 @@ __device__ __forceinline__ void team_pick_max(TeamSh &sh, const TeamId &id, cons
         k = t.KV(i);
     }
     __syncthreads();
+}
+
+// Workgroup minimum of v (every thread gets it).
+__device__ __forceinline__ int32_t team_min_i32(TeamSh &sh, const TeamId &id, int32_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v = min(v, __shfl_xor(v, off));
+    if (id.lane == 0)
+        sh.u[id.wid] = v;
+    __syncthreads();
+    v = sh.u[0];
+    for (int w = 1; w < id.nw; ++w)
+        v = min(v, sh.u[w]);
+    __syncthreads();
+    return v;
 }
 
 __device__ __forceinline__ void team_pick_min(TeamSh &sh, const TeamId &id, const Tab &t, int32_t &u,
@@ -1877,44 +1943,119 @@ __device__ bool bq_additions(const Tab &t, TeamSh &sh, St &st, const Ctx &c, con
 }
 
 // Removal passes of one growth call over a list of the members gathered
-// once (global tables), same order and decisions as removal_scan.
+// once (global tables), same order and decisions as removal_scan.  Record
+// tables of more than by_id_min entries (16 queue_min: 16,384 at the default)
+// sort the list into kBuckets ranges of node id (the queue's bucket arrays
+// are free once the additions are over), so that a search for the smallest
+// removable id above the cursor walks whole buckets from the cursor's one
+// and stops at the first that holds one; smaller tables scan their whole
+// list per search, which costs less than the sort and the extra barriers
+// there.
 template <bool GLOBAL>
 __device__ bool removal_members(const Tab &t, TeamSh &sh, St &st, const Ctx &c, const TeamId &id,
-                                uint32_t k_prune, int64_t &moves) {
-    // a list of the members (in the scratch array)
-    if (id.tid == 0)
-        sh.m = 0;
-    __syncthreads();
-    for (int32_t i = id.tid; i < st.count; i += id.nt) {
-        if (t.DV(i) & kMember)
-            t.scr[atomicAdd(&sh.m, 1)] = i;
+                                uint32_t k_prune, int32_t by_id_min, int64_t &moves) {
+    // record tables only (their lists run to tens of thousands of members);
+    // the same in all threads
+    const bool by_id = t.hp != nullptr && st.count > by_id_min;
+    const int shift = max(0, (32 - __builtin_clz((uint32_t)max(c.n - 1, 1))) - 8);
+    int32_t ml;
+    if (by_id) {
+        for (int32_t b = id.tid; b < kBuckets; b += id.nt)
+            sh.fill[b] = 0u;
+        __syncthreads();
+        for (int32_t i = id.tid; i < st.count; i += id.nt) {
+            if (t.DV(i) & kMember)
+                atomicAdd(&sh.fill[t.NODE(i) >> shift], 1u);
+        }
+        __syncthreads();
+        if (id.wid == 0) {
+            const int32_t b0 = 4 * id.lane;
+            uint32_t c4[4];
+            uint32_t sum = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                c4[j] = sh.fill[b0 + j];
+                sum += c4[j];
+            }
+            uint32_t incl = sum;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t x = __shfl_up(incl, off);
+                if (id.lane >= off)
+                    incl += x;
+            }
+            uint32_t run = incl - sum;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                sh.bstart[b0 + j] = (int32_t)run;
+                sh.fill[b0 + j] = run;
+                run += c4[j];
+            }
+            if (id.lane == 63)
+                sh.bstart[kBuckets] = (int32_t)incl;
+        }
+        __syncthreads();
+        for (int32_t i = id.tid; i < st.count; i += id.nt) {
+            if (t.DV(i) & kMember)
+                t.scr[atomicAdd(&sh.fill[t.NODE(i) >> shift], 1u)] = i;
+        }
+        __syncthreads();
+        ml = sh.bstart[kBuckets];
+        st.scanned += 2 * (uint64_t)st.count;
+    } else {
+        if (id.tid == 0)
+            sh.m = 0;
+        __syncthreads();
+        for (int32_t i = id.tid; i < st.count; i += id.nt) {
+            if (t.DV(i) & kMember)
+                t.scr[atomicAdd(&sh.m, 1)] = i;
+        }
+        __syncthreads();
+        ml = sh.m;
+        st.scanned += (uint64_t)st.count;
     }
-    __syncthreads();
-    const int32_t ml = sh.m;
-    st.scanned += (uint64_t)st.count;
     for (uint32_t pass = 0; k_prune == 0 || pass < k_prune; ++pass) {
         st.Gu += (uint64_t)st.nmem;
         int32_t cursor = -1;
         bool removed = false;
+        int32_t pos = 0;   // list positions before pos hold only ids at or below the cursor
         for (;;) {
             int32_t cu = INT32_MAX;
             int32_t ci = -1;
-            st.scanned += (uint64_t)ml;
-            for (int32_t j0 = id.tid; j0 < ml; j0 += kScanAhead * id.nt) {
-                Batch b;
-                load_batch(t, t.scr, j0, ml, id.nt, b);
+            // windows of whole buckets from pos until one holds a removable
+            // id (unsorted: one window, the whole list)
+            while (pos < ml) {
+                int32_t end = ml;
+                if (by_id) {
+                    const int32_t b0 = bucket_at(sh, 0, kBuckets - 1, pos);
+                    int32_t b1 = bucket_at(sh, b0, kBuckets, pos + kScanAhead * id.nt);
+                    if (b1 <= b0)
+                        b1 = b0 + 1;
+                    end = sh.bstart[b1];
+                }
+                st.scanned += (uint64_t)(end - pos);
+                for (int32_t j0 = pos + id.tid; j0 < end; j0 += kScanAhead * id.nt) {
+                    Batch b;
+                    load_batch(t, t.scr, j0, end, id.nt, b);
 #pragma unroll
-                for (int x = 0; x < kScanAhead; ++x) {
-                    if (b.i[x] < 0 || !(b.v[x] & kMember))
-                        continue;
-                    const int32_t u = b.u[x];
-                    if (u <= cursor || u >= cu)
-                        continue;
-                    if (improves_remove(st, (int32_t)(b.v[x] & kDMask), b.k[x])) {
-                        cu = u;
-                        ci = b.i[x];
+                    for (int x = 0; x < kScanAhead; ++x) {
+                        if (b.i[x] < 0 || !(b.v[x] & kMember))
+                            continue;
+                        const int32_t u = b.u[x];
+                        if (u <= cursor || u >= cu)
+                            continue;
+                        if (improves_remove(st, (int32_t)(b.v[x] & kDMask), b.k[x])) {
+                            cu = u;
+                            ci = b.i[x];
+                        }
                     }
                 }
+                if (end >= ml)
+                    break;   // the last window: the pick below decides
+                const int32_t found = team_min_i32(sh, id, ci < 0 ? INT32_MAX : cu);
+                if (found != INT32_MAX)
+                    break;
+                pos = end;
             }
             uint32_t vm = 0;
             int32_t km = 0;
@@ -1933,6 +2074,7 @@ __device__ bool removal_members(const Tab &t, TeamSh &sh, St &st, const Ctx &c, 
             team_row<GLOBAL, ROW_REMOVE>(t, sh, st, c, id, cu);
             removed = true;
             cursor = cu;
+            pos = by_id ? sh.bstart[cu >> shift] : 0;
             if ((int64_t)st.M > st.move_limit) {
                 st.err |= ERR_LIMIT;
                 return false;
@@ -2062,7 +2204,8 @@ __device__ int64_t team_grow(const Tab &t, TeamSh &sh, St &st, const Ctx &c, con
         return 0;
     if constexpr (GLOBAL) {
         if (bucketed) {
-            removal_members<GLOBAL>(t, sh, st, c, id, k_prune, moves);
+            const int32_t by_id_min = (int32_t)min<int64_t>(16 * (int64_t)queue_min, INT32_MAX);
+            removal_members<GLOBAL>(t, sh, st, c, id, k_prune, by_id_min, moves);
             return moves;
         }
     }
@@ -2197,6 +2340,7 @@ __device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh, int32_t *
     c.kdeg = A.g.kdeg;
     c.logtab = A.g.logtab;
     c.logtab_last = A.g.logtab_n - 1;
+    c.n = A.g.n;
     const uint32_t n_items = A.tier == 0 ? (uint32_t)A.n_sets : A.ctl->ovf_count[A.in_from];
     for (;;) {
         __syncthreads();
@@ -2480,16 +2624,8 @@ __device__ void run_team(const SweepArgs &A, const Tab &t, TeamSh &sh, int32_t *
         if constexpr (GLOBAL) {
             // leave the slab's hash empty for the next community
             const int32_t cnt = min(sh.count, t.cap);
-            for (int32_t i = id.tid; i < cnt; i += id.nt) {
-                uint32_t p = hash_of(t.NODE(i), t.hbits);
-                for (uint32_t it = 0; it <= t.hmask; ++it) {
-                    if (hs_load<GLOBAL>(&t.hs[p]) == i) {
-                        hs_store<GLOBAL>(&t.hs[p], -1);
-                        break;
-                    }
-                    p = (p + 1) & t.hmask;
-                }
-            }
+            for (int32_t i = id.tid; i < cnt; i += id.nt)
+                tab_slot_clear<GLOBAL>(t, i);
         }
     }
 }
@@ -2502,14 +2638,16 @@ __device__ __forceinline__ void team_lds_entry(const SweepArgs &A) {
     run_team<false, PERSET>(A, t, sh, nullptr);
 }
 
-template <bool PERSET>
+// REC: the tables are of the record layout (cap >= kRecordMinEntries); one
+// kernel per layout, so that each is compiled with its own strides.
+template <bool PERSET, bool REC>
 __device__ __forceinline__ void team_global_entry(const SweepArgs &A) {
     __shared__ TeamSh sh;
     __shared__ int32_t lsort[kLdsSort];
     const int slot = blockIdx.x;
     if (slot >= A.n_slots)
         return;
-    Tab t = carve_global(A.gtab + (int64_t)slot * A.gtab_stride, A.cap, A.hbits);
+    Tab t = carve_global_as<REC>(A.gtab + (int64_t)slot * A.gtab_stride, A.cap, A.hbits);
     run_team<true, PERSET>(A, t, sh, lsort);
 }
 
@@ -2525,9 +2663,11 @@ __device__ __forceinline__ void team_global_entry(const SweepArgs &A) {
 // one).
 #define LCD_TEAM_KERNEL(w) __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(w)))
 LCD_TEAM_KERNEL(4) sweep_team_lds_kernel(SweepArgs A) { team_lds_entry<false>(A); }
-LCD_TEAM_KERNEL(4) sweep_team_global_kernel(SweepArgs A) { team_global_entry<false>(A); }
+LCD_TEAM_KERNEL(4) sweep_team_global_kernel(SweepArgs A) { team_global_entry<false, false>(A); }
+LCD_TEAM_KERNEL(4) sweep_team_global_rec_kernel(SweepArgs A) { team_global_entry<false, true>(A); }
 LCD_TEAM_KERNEL(4) query_team_lds_kernel(SweepArgs A) { team_lds_entry<true>(A); }
-LCD_TEAM_KERNEL(4) query_team_global_kernel(SweepArgs A) { team_global_entry<true>(A); }
+LCD_TEAM_KERNEL(4) query_team_global_kernel(SweepArgs A) { team_global_entry<true, false>(A); }
+LCD_TEAM_KERNEL(4) query_team_global_rec_kernel(SweepArgs A) { team_global_entry<true, true>(A); }
 #undef LCD_TEAM_KERNEL
 
 // ---------------------------------------------------------------------------
@@ -3382,7 +3522,11 @@ hipError_t launch_sweep(const SweepArgs &a, int32_t blocks, int32_t waves_per_bl
     case TIER_TEAM_GLOBAL:
         if (waves_per_block < 1 || 64 * waves_per_block > kTeamMaxThreads || a.gtab == nullptr)
             return hipErrorInvalidValue;
-        hipLaunchKernelGGL(q ? query_team_global_kernel : sweep_team_global_kernel, grid, block, 0, st, a);
+        if (a.cap >= kRecordMinEntries)
+            hipLaunchKernelGGL(q ? query_team_global_rec_kernel : sweep_team_global_rec_kernel, grid, block, 0, st,
+                               a);
+        else
+            hipLaunchKernelGGL(q ? query_team_global_kernel : sweep_team_global_kernel, grid, block, 0, st, a);
         break;
     default:
         return hipErrorInvalidValue;

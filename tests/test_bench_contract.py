@@ -28,8 +28,8 @@ def test_profile_summaries_parse_for_their_kernel_source():
     m = re.search(r"^kernels_sha256: ([0-9a-f]{64})", text, re.M)
     assert m
     caps = json.loads(re.search(r"^profiled_tier_capacities: (\[.*\])", text, re.M).group(1))
-    t = bench.profiled_traffic("sweep_team_global_kernel", caps, "xl64")
-    u = bench.profiled_utilisation("sweep_team_global_kernel", "xl64")
+    t = bench.profiled_traffic("sweep_team_global_rec_kernel", caps, "xl64")
+    u = bench.profiled_utilisation("sweep_team_global_rec_kernel", "xl64")
     if m.group(1) == sha:
         # taken on this source: both summaries give numbers for the dominant kernel
         assert t is not None and t > 0
@@ -38,5 +38,5 @@ def test_profile_summaries_parse_for_their_kernel_source():
         # a profile of another source is never reported
         assert t is None and u is None
     # other workloads or tier layouts never borrow the numbers
-    assert bench.profiled_traffic("sweep_team_global_kernel", caps, "large") is None
-    assert bench.profiled_traffic("sweep_team_global_kernel", [256] + list(caps[1:]), "xl64") is None
+    assert bench.profiled_traffic("sweep_team_global_rec_kernel", caps, "large") is None
+    assert bench.profiled_traffic("sweep_team_global_rec_kernel", [256] + list(caps[1:]), "xl64") is None
