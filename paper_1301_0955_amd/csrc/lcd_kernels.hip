@@ -1444,8 +1444,9 @@ __device__ bool removal_scan(const Tab &t, TeamSh &sh, St &st, const Ctx &c, con
 //     candidate; a window with no improving entry ranked above the fresh
 //     candidate is popped whole), so it pops exactly the entries the
 //     sequential queue pops;
-//   * the queue is rebuilt (three table passes) when the fresh list grows
-//     past max(512, entries / 16).
+//   * the queue is rebuilt (three table passes, read in order) when the
+//     fresh list grows past max(512, entries / 32): a rebuild costs fewer
+//     bytes than the random reads of a longer fresh list.
 // Removal passes walk a list of the members instead of the whole table.
 // Same decisions, counters and results as the scan-driven additions.
 // ---------------------------------------------------------------------------
@@ -1909,7 +1910,7 @@ template <bool GLOBAL>
 __device__ bool bq_additions(const Tab &t, TeamSh &sh, St &st, const Ctx &c, const TeamId &id, BQ &q,
                              int64_t &moves) {
     for (;;) {
-        if (sh.flen > max(512, st.count >> 4))
+        if (sh.flen > max(512, st.count >> 5))
             bq_rebuild(t, sh, st, id, q);
         double br;
         int32_t bu;
@@ -2942,11 +2943,12 @@ __global__ void overlap_count_kernel(const int32_t *members, int64_t total, int3
 // ---------------------------------------------------------------------------
 
 __global__ void seed_init_kernel(const int32_t *row_ptr, const int32_t *perm, int32_t n, int32_t *pos,
-                                 uint8_t *st) {
+                                 uint8_t *st, uint8_t *act) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         pos[perm[i]] = (int32_t)i;
         st[i] = (row_ptr[i + 1] - row_ptr[i]) >= 2 ? 0 : 2;
+        act[i] = 1;
     }
 }
 
@@ -2958,15 +2960,19 @@ __global__ void seed_init_kernel(const int32_t *row_ptr, const int32_t *perm, in
 // time: m1[u] = min over the closed neighbourhood of u (undecided
 // candidates only), then, for rule 2, the min of m1 over the closed
 // neighbourhood of v: two passes over the edges instead of a walk over
-// every two-hop path.
+// every two-hop path.  Candidates never become undecided again, so a node
+// whose closed neighbourhood holds none keeps m1 = INT32_MAX for good and
+// is skipped from then on (act[v] = 0).
 __global__ void seed_min1_kernel(const int32_t *row_ptr, const int32_t *col, const int32_t *pos,
-                                 const uint8_t *st, int32_t n, int32_t *m1, const unsigned *prev,
+                                 const uint8_t *st, uint8_t *act, int32_t n, int32_t *m1, const unsigned *prev,
                                  unsigned *undecided) {
     if (prev && *prev == 0u)
         return;
     unsigned cnt = 0;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
+        if (!act[v])
+            continue;
         int32_t m = INT32_MAX;
         if (st[v] == 0) {
             cnt += 1;
@@ -2978,6 +2984,8 @@ __global__ void seed_min1_kernel(const int32_t *row_ptr, const int32_t *col, con
                 m = min(m, pos[u]);
         }
         m1[v] = m;
+        if (m == INT32_MAX)
+            act[v] = 0;
     }
     if (cnt)
         atomicAdd(undecided, cnt);
@@ -3655,22 +3663,22 @@ hipError_t launch_exclusive_scan(const int32_t *in, int64_t n, int32_t *out, int
 }
 
 hipError_t launch_seed_init(const int32_t *row_ptr, const int32_t *perm, int32_t n, int32_t *pos,
-                            uint8_t *st, hipStream_t s) {
+                            uint8_t *st, uint8_t *act, hipStream_t s) {
     if (n == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(seed_init_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, row_ptr, perm, n, pos, st);
+    hipLaunchKernelGGL(seed_init_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, row_ptr, perm, n, pos, st, act);
     return hipGetLastError();
 }
 
 hipError_t launch_seed_round(int32_t rule, const int32_t *row_ptr, const int32_t *col, const int32_t *pos,
-                             uint8_t *st, uint8_t *sel, int32_t *m1, int32_t n, const unsigned *prev,
-                             unsigned *undecided, hipStream_t s) {
+                             uint8_t *st, uint8_t *sel, uint8_t *act, int32_t *m1, int32_t n,
+                             const unsigned *prev, unsigned *undecided, hipStream_t s) {
     if (n == 0)
         return hipSuccess;
     if (rule != 1 && rule != 2)
         return hipErrorInvalidValue;
     const dim3 g(grid_for(n, 256)), b(256);
-    hipLaunchKernelGGL(seed_min1_kernel, g, b, 0, s, row_ptr, col, pos, st, n, m1, prev, undecided);
+    hipLaunchKernelGGL(seed_min1_kernel, g, b, 0, s, row_ptr, col, pos, st, act, n, m1, prev, undecided);
     if (rule == 1) {
         hipLaunchKernelGGL(seed_apply_kernel<1>, g, b, 0, s, row_ptr, col, pos, m1, sel, st, n, undecided);
     } else {

@@ -456,6 +456,32 @@ def lfr_hierarchical_fast(n: int, tau_deg: float, mean_deg: float, max_deg: int,
 
 
 # ---------------------------------------------------------------------------
+# Block graphs with communities of tens of thousands of nodes
+# ---------------------------------------------------------------------------
+
+def block_graph(n_blocks: int, size: int, deg_in: int, deg_out: int, weighted: bool, seed: int,
+                wmax: int = 16) -> Graph:
+    """n_blocks blocks of `size` consecutive node ids; every node draws
+    deg_in partners uniformly inside its block and deg_out uniformly over the
+    whole graph (duplicates and self-pairs dropped).  Sparse, so blocks of
+    tens of thousands of nodes cost O(n) memory: a community that grows over
+    a block holds tens of thousands of table entries."""
+    rng = _rng(seed)
+    n = n_blocks * size
+    node = np.arange(n, dtype=np.int64)
+    base = (node // size) * size
+    u_in = np.repeat(node, deg_in)
+    v_in = np.repeat(base, deg_in) + rng.integers(0, size, size=u_in.size)
+    u_out = np.repeat(node, deg_out)
+    v_out = rng.integers(0, n, size=u_out.size)
+    u = np.concatenate([u_in, u_out])
+    v = np.concatenate([v_in, v_out])
+    w = rng.integers(1, wmax + 1, size=u.size).astype(np.uint8) if weighted else None
+    return csr_from_edges(n, u, v, w, dict(kind="blocks", n_blocks=n_blocks, size=size, deg_in=deg_in,
+                                           deg_out=deg_out, weighted=weighted, seed=seed))
+
+
+# ---------------------------------------------------------------------------
 # Tiny random graphs for exhaustive checks
 # ---------------------------------------------------------------------------
 
