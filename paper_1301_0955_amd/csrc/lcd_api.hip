@@ -962,10 +962,11 @@ lcd_status lcd_seeds(const lcd_graph *g, int32_t rule, const int32_t *perm, int3
     const int nb = (int)(((int64_t)n + 1023) / 1024);
     // one device workspace per graph, allocated on the first call: perm,
     // pos, flag (also the round's one-hop minima), at, block sums, out
-    // (int32), state, selection and activity (uint8), the round counters
+    // (int32), state, selection, activity and two-hop marks (uint8), the
+    // round counters
     auto al = [](int64_t x) { return (x + 255) / 256 * 256; };
     const int64_t n4 = al(4 * (int64_t)n), n1 = al((int64_t)n);
-    const int64_t ws = 5 * n4 + al(4 * ((int64_t)nb + 1)) + 3 * n1 + al(4 * (int64_t)kSeedBatch);
+    const int64_t ws = 5 * n4 + al(4 * ((int64_t)nb + 1)) + 4 * n1 + al(4 * (int64_t)kSeedBatch);
     lcd_graph *gw = const_cast<lcd_graph *>(g);
     if (gw->seed_ws_bytes < ws) {
         dev_free(gw->seed_ws);
@@ -983,7 +984,8 @@ lcd_status lcd_seeds(const lcd_graph *g, int32_t rule, const int32_t *perm, int3
     uint8_t *stt = (uint8_t *)(p + 5 * n4 + al(4 * ((int64_t)nb + 1)));
     uint8_t *sel = stt + n1;
     uint8_t *act = sel + n1;
-    unsigned *cnt = (unsigned *)(act + n1);
+    uint8_t *near = act + n1;
+    unsigned *cnt = (unsigned *)(near + n1);
     hipError_t e = hipMemcpyAsync(d_perm, ph.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = launch_seed_init(g->row_ptr, d_perm, n, pos, stt, act, st);
@@ -999,7 +1001,7 @@ lcd_status lcd_seeds(const lcd_graph *g, int32_t rule, const int32_t *perm, int3
         unsigned undecided = 0;
         e = launch_zero_bytes(cnt, 4 * (int64_t)batch, st);
         for (int32_t k = 0; k < batch && e == hipSuccess; ++k)
-            e = launch_seed_round(rule, g->row_ptr, g->col, pos, stt, sel, act, flag, n,
+            e = launch_seed_round(rule, g->row_ptr, g->col, pos, stt, sel, act, near, flag, n,
                                   k > 0 ? cnt + (k - 1) : nullptr, cnt + k, st);
         rounds += batch;
         if (e == hipSuccess)

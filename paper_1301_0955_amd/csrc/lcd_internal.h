@@ -208,11 +208,12 @@ hipError_t launch_exclusive_scan(const int32_t *in, int64_t n, int32_t *out, int
 // seed selection: pos/st/act setup, one selection round (adds the number of
 // undecided candidates at its start to *undecided; does nothing when prev
 // is non-null and *prev is 0), and the ordered output.  act[v] = 0 once no
-// undecided candidate is left within one hop of v (it stays so).
+// undecided candidate is left within one hop of v (it stays so); near is
+// rule 2's per-round scratch (n bytes).
 hipError_t launch_seed_init(const int32_t *row_ptr, const int32_t *perm, int32_t n, int32_t *pos,
                             uint8_t *st, uint8_t *act, hipStream_t s);
 hipError_t launch_seed_round(int32_t rule, const int32_t *row_ptr, const int32_t *col, const int32_t *pos,
-                             uint8_t *st, uint8_t *sel, uint8_t *act, int32_t *m1, int32_t n,
+                             uint8_t *st, uint8_t *sel, uint8_t *act, uint8_t *near, int32_t *m1, int32_t n,
                              const unsigned *prev, unsigned *undecided, hipStream_t s);
 hipError_t launch_seed_collect(const int32_t *perm, const uint8_t *st, int32_t n, int32_t *flag, int32_t *at,
                                int32_t *block_sums, int32_t *out, hipStream_t s);

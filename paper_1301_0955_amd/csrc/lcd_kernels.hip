@@ -3010,40 +3010,68 @@ __global__ void seed_min2_kernel(const int32_t *row_ptr, const int32_t *col, con
     }
 }
 
-// The selected candidates become seeds and the candidates within R hops of
-// them are dropped.  Selected nodes are pairwise further apart than R hops,
-// so a selected node's flag is written by its own thread only, and every
-// other write is the same value from whichever thread makes it.  Rule 1
-// selects from m1 directly (a selected node has no selected neighbour, so
-// the flag it reads is the round's).
-template <int R>
-__global__ void seed_apply_kernel(const int32_t *row_ptr, const int32_t *col, const int32_t *pos,
-                                  const int32_t *m1, const uint8_t *sel, uint8_t *st, int32_t n,
-                                  const unsigned *undecided) {
+// Rule 1: the selected candidates (m1 == own position) become seeds and
+// their undecided neighbours are dropped.  Selected nodes are pairwise
+// further apart than one hop, so a selected node's flag is written by its
+// own thread only, and every other write is the same value from whichever
+// thread makes it.
+__global__ void seed_apply1_kernel(const int32_t *row_ptr, const int32_t *col, const int32_t *pos,
+                                   const int32_t *m1, uint8_t *st, int32_t n, const unsigned *undecided) {
     if (*undecided == 0u)
         return;   // the round found nothing to decide
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
-        if constexpr (R == 1) {
-            if (st[v] != 0 || m1[v] != pos[v])
-                continue;
-        } else {
-            if (!sel[v])
-                continue;
-        }
+        if (st[v] != 0 || m1[v] != pos[v])
+            continue;
         st[v] = 1;
         for (int32_t j = row_ptr[v]; j < row_ptr[v + 1]; ++j) {
             const int32_t u = col[j];
             if (st[u] == 0)
                 st[u] = 2;
-            if constexpr (R == 2) {
-                for (int32_t q = row_ptr[u]; q < row_ptr[u + 1]; ++q) {
-                    const int32_t w = col[q];
-                    if (w != v && st[w] == 0)
-                        st[w] = 2;
-                }
-            }
         }
+    }
+}
+
+// Rule 2 in two one-hop passes instead of a walk over the two-hop paths of
+// each selected node (one thread per selected node walked up to max-degree
+// squared entries in turn): near[v] = some selected node in the closed
+// neighbourhood of v; an undecided candidate then becomes a seed if
+// selected, and is dropped if some node of its closed neighbourhood is
+// near a selected one, i.e. if a selected node lies within two hops.
+// Nodes with no undecided candidate within one hop (act[v] = 0) are never
+// read by the second pass and are skipped.
+__global__ void seed_near_kernel(const int32_t *row_ptr, const int32_t *col, const uint8_t *sel,
+                                 const uint8_t *act, int32_t n, uint8_t *near, const unsigned *undecided) {
+    if (*undecided == 0u)
+        return;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        if (!act[v])
+            continue;
+        uint8_t x = sel[v];
+        for (int32_t j = row_ptr[v]; j < row_ptr[v + 1] && !x; ++j)
+            x = sel[col[j]];
+        near[v] = x;
+    }
+}
+
+__global__ void seed_apply2_kernel(const int32_t *row_ptr, const int32_t *col, const uint8_t *sel,
+                                   const uint8_t *near, uint8_t *st, int32_t n, const unsigned *undecided) {
+    if (*undecided == 0u)
+        return;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        if (st[v] != 0)
+            continue;
+        if (sel[v]) {
+            st[v] = 1;
+            continue;
+        }
+        uint8_t x = near[v];
+        for (int32_t j = row_ptr[v]; j < row_ptr[v + 1] && !x; ++j)
+            x = near[col[j]];
+        if (x)
+            st[v] = 2;
     }
 }
 
@@ -3671,7 +3699,7 @@ hipError_t launch_seed_init(const int32_t *row_ptr, const int32_t *perm, int32_t
 }
 
 hipError_t launch_seed_round(int32_t rule, const int32_t *row_ptr, const int32_t *col, const int32_t *pos,
-                             uint8_t *st, uint8_t *sel, uint8_t *act, int32_t *m1, int32_t n,
+                             uint8_t *st, uint8_t *sel, uint8_t *act, uint8_t *near, int32_t *m1, int32_t n,
                              const unsigned *prev, unsigned *undecided, hipStream_t s) {
     if (n == 0)
         return hipSuccess;
@@ -3680,10 +3708,11 @@ hipError_t launch_seed_round(int32_t rule, const int32_t *row_ptr, const int32_t
     const dim3 g(grid_for(n, 256)), b(256);
     hipLaunchKernelGGL(seed_min1_kernel, g, b, 0, s, row_ptr, col, pos, st, act, n, m1, prev, undecided);
     if (rule == 1) {
-        hipLaunchKernelGGL(seed_apply_kernel<1>, g, b, 0, s, row_ptr, col, pos, m1, sel, st, n, undecided);
+        hipLaunchKernelGGL(seed_apply1_kernel, g, b, 0, s, row_ptr, col, pos, m1, st, n, undecided);
     } else {
         hipLaunchKernelGGL(seed_min2_kernel, g, b, 0, s, row_ptr, col, pos, st, m1, sel, n, undecided);
-        hipLaunchKernelGGL(seed_apply_kernel<2>, g, b, 0, s, row_ptr, col, pos, m1, sel, st, n, undecided);
+        hipLaunchKernelGGL(seed_near_kernel, g, b, 0, s, row_ptr, col, sel, act, n, near, undecided);
+        hipLaunchKernelGGL(seed_apply2_kernel, g, b, 0, s, row_ptr, col, sel, near, st, n, undecided);
     }
     return hipGetLastError();
 }
