@@ -331,11 +331,12 @@ lcd_status lcd_graph_untune(lcd_graph *g);
  * choice, drawn by the caller); a visited node that is still a candidate
  * becomes a seed and drops its neighbours (rule 1) or every node within two
  * hops (rule 2) from the candidates.  out_seeds (int32[n], mem_kind memory)
- * receives the seeds in order of selection, *n_seeds their number; seed j
- * is the singleton seed set j of a sweep.  Computed in parallel rounds that
- * give exactly the sequential result.  LCD_EINVAL if perm is not a
- * permutation.  The graph keeps the call's device workspace (about 22 bytes
- * per node) for the next call, so calls on one graph must not overlap.
+ * receives the seeds in order of selection, *n_seeds their number (entries
+ * past it are not written); seed j is the singleton seed set j of a sweep.
+ * Computed in parallel rounds that give exactly the sequential result.
+ * LCD_EINVAL if perm is not a permutation.  The graph keeps the call's
+ * device workspace (about 24 bytes per node) for the next call, so calls on
+ * one graph must not overlap.
  * Blocking.
  */
 lcd_status lcd_seeds(const lcd_graph *g, int32_t rule, const int32_t *perm, int32_t mem_kind, void *stream,

@@ -946,14 +946,23 @@ lcd_status lcd_seeds(const lcd_graph *g, int32_t rule, const int32_t *perm, int3
         return fail(LCD_EINVAL, "unknown mem_kind %d", mem_kind);
     hipStream_t st = (hipStream_t)stream;
     const int32_t n = g->n;
+    if (n > 0 && !perm)
+        return fail(LCD_EINVAL, "null input array");
+    // the permutation is checked on the host: in place when it is host
+    // memory, from a copy when it is device memory
     std::vector<int32_t> ph;
-    CHK(fetch(ph, perm, (size_t)n, mem_kind, st));
+    const int32_t *hp = perm;
+    if (mem_kind == LCD_MEM_DEVICE) {
+        CHK(fetch(ph, perm, (size_t)n, mem_kind, st));
+        hp = ph.data();
+    }
     {
-        std::vector<uint8_t> seen((size_t)std::max(n, 1), 0);
+        std::vector<uint64_t> seen(((size_t)std::max(n, 1) + 63) / 64, 0);
         for (int32_t i = 0; i < n; ++i) {
-            if (ph[i] < 0 || ph[i] >= n || seen[ph[i]])
+            const int32_t v = hp[i];
+            if (v < 0 || v >= n || (seen[v >> 6] >> (v & 63) & 1u))
                 return fail(LCD_EINVAL, "perm is not a permutation of the node ids (entry %d)", i);
-            seen[ph[i]] = 1;
+            seen[v >> 6] |= (uint64_t)1 << (v & 63);
         }
     }
     *n_seeds = 0;
@@ -986,7 +995,8 @@ lcd_status lcd_seeds(const lcd_graph *g, int32_t rule, const int32_t *perm, int3
     uint8_t *act = sel + n1;
     uint8_t *near = act + n1;
     unsigned *cnt = (unsigned *)(near + n1);
-    hipError_t e = hipMemcpyAsync(d_perm, ph.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st);
+    hipError_t e = hipMemcpyAsync(d_perm, perm, sizeof(int32_t) * (size_t)n,
+                                  mem_kind == LCD_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = launch_seed_init(g->row_ptr, d_perm, n, pos, stt, act, st);
     // each round settles at least the first undecided candidate in visiting
@@ -1015,10 +1025,14 @@ lcd_status lcd_seeds(const lcd_graph *g, int32_t rule, const int32_t *perm, int3
         e = launch_seed_collect(d_perm, stt, n, flag, at, bs, out, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(&total, bs + nb, sizeof(int32_t), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess && mem_kind == LCD_MEM_HOST)
-        e = hipMemcpyAsync(out_seeds, out, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
         e = hipStreamSynchronize(st);
+    // host output: the seeds only, not all n slots
+    if (e == hipSuccess && mem_kind == LCD_MEM_HOST && total > 0) {
+        e = hipMemcpyAsync(out_seeds, out, sizeof(int32_t) * (size_t)total, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+    }
     if (e != hipSuccess)
         return fail(LCD_EDEVICE, "seed selection: %s", hipGetErrorString(e));
     if (!settled)

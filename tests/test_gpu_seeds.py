@@ -53,3 +53,31 @@ def test_seeds_reject_non_permutation(L):
     assert e.value.status == L.LCD_EINVAL
     with pytest.raises(L.LcdError):
         L.lcd_seeds(G, np.arange(g.n), 3)
+
+
+@pytest.mark.parametrize("rule", [1, 2])
+def test_seeds_device_memory(L, rule):
+    """perm and out_seeds in device memory (LCD_MEM_DEVICE) through the C
+    ABI: the same seeds as the oracle; out_seeds past the count untouched."""
+    import ctypes
+    import torch
+    g = W.workload_small()[0]
+    G = L.Graph.from_workload(g)
+    perm = W.seed_permutation(g, 1)
+    d_perm = torch.as_tensor(perm, dtype=torch.int32, device="cuda")
+    d_out = torch.full((g.n,), -7, dtype=torch.int32, device="cuda")
+    k = ctypes.c_int32()
+    st = L.library().lcd_seeds(G._h, rule, L._ptr(d_perm), L.LCD_MEM_DEVICE, L._stream(), L._ptr(d_out),
+                               ctypes.byref(k))
+    assert st == L.LCD_OK
+    torch.cuda.synchronize()
+    out = d_out.cpu().numpy()
+    ref = oracle.Oracle.from_graph(g).seeds(perm, rule)
+    assert k.value == ref.size
+    assert np.array_equal(out[:k.value], ref)
+    assert (out[k.value:] == -7).all()
+    bad = d_perm.clone()
+    bad[3] = bad[4]
+    st = L.library().lcd_seeds(G._h, rule, L._ptr(bad), L.LCD_MEM_DEVICE, L._stream(), L._ptr(d_out),
+                               ctypes.byref(k))
+    assert st == L.LCD_EINVAL
