@@ -40,3 +40,16 @@ def test_profile_summaries_parse_for_their_kernel_source():
     # other workloads or tier layouts never borrow the numbers
     assert bench.profiled_traffic("sweep_team_global_rec_kernel", caps, "large") is None
     assert bench.profiled_traffic("sweep_team_global_rec_kernel", [256] + list(caps[1:]), "xl64") is None
+
+
+def test_kernel_names_follow_the_table_layout():
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.kernel_of(3, 131072) == "sweep_team_global_rec_kernel"
+    assert bench.kernel_of(3, 65536) == "sweep_team_global_rec_kernel"
+    assert bench.kernel_of(3, 16384) == "sweep_team_global_kernel"
+    assert bench.kernel_of(0, 512) == "sweep_lds_kernel"
+    # the record layout starts where the library's does
+    hdr = open(os.path.join(ROOT, "paper_1301_0955_amd", "csrc", "lcd_internal.h")).read()
+    m = re.search(r"kRecordMinEntries = (\d+);", hdr)
+    assert m and int(m.group(1)) == bench.RECORD_MIN_ENTRIES
