@@ -299,6 +299,7 @@ def serve_bench(lcd, G, g, qps, seconds, warmup_s, oracle_sample, seed=1):
         batches=int(batches), mean_batch=round((st["completed"] - st0["completed"]) / max(batches, 1), 2),
         max_batch=st["max_batch"], max_lanes_busy=st["max_lanes_busy"], lanes=st["lanes"],
         stage_lanes=st["spill_lanes"], forwarded=st["forwarded"] - st0["forwarded"],
+        routed=st["routed"] - st0["routed"],
         later_stage_batches=st["spill_batches"] - st0["spill_batches"],
         requeued=st["requeued"], failed=st["failed"], server_mem_bytes=st["mem_held"],
         spill_tables=list(st["spill_tables"]))

@@ -568,6 +568,9 @@ typedef struct {
     int32_t spill_tables[2];  /* global-memory tables per spill lane, per global tier */
     int32_t pad;
     int64_t cancelled;        /* queries withdrawn by lcd_server_cancel */
+    int64_t routed;           /* queries queued straight to a later stage: their
+                                 seeds and the seeds' neighbours alone
+                                 already overflow the earlier stages' tables */
 } lcd_server_stats;
 
 /*
@@ -580,6 +583,10 @@ typedef struct {
  * starts).  With 8 or more the server runs one stage per table tier on six
  * lanes (a query moves to the next stage's lane when it outgrows its
  * stage's table), otherwise tier 0 on one lane and the later tiers on three.
+ * A query whose seeds and their neighbours outnumber a stage's table starts
+ * at the first stage whose table holds them (graphs of up to 2^28 adjacency
+ * entries, whose CSR the server keeps a host copy of; the stage never
+ * changes a result).
  *   max_slots   queries admitted and unfinished at once (0 = 1024)
  *   params      k_prune, lds_capacity, waves_per_block, watchdog_ms used;
  *               NULL for defaults

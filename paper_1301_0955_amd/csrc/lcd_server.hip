@@ -218,6 +218,10 @@ struct lcd_server {
     bool stop = false;
     std::thread worker;
     lcd_server_stats stats{};
+    // start-stage routing: host copy of the CSR and each stage's table size
+    bool route = false;
+    std::vector<int32_t> h_row_ptr, h_col;
+    int32_t stage_cap[kMaxStages] = {0};
 };
 
 namespace {
@@ -572,7 +576,14 @@ void worker_main(lcd_server *S) {
         if (any)
             S->cv_work.wait_for(lk, std::chrono::microseconds(20));
         else
-            S->cv_work.wait(lk, [S] { return S->stop || !S->pending.empty(); });
+            S->cv_work.wait(lk, [S] {
+                // new work: a submitted query, or one queued straight to a
+                // later stage
+                bool later = false;
+                for (int k = 1; k < S->n_stages; ++k)
+                    later |= !S->forwarded[k].empty();
+                return S->stop || !S->pending.empty() || later;
+            });
     }
     // fail whatever is still queued
     for (Query *q : S->pending) {
@@ -780,6 +791,28 @@ lcd_status lcd_server_create(const lcd_graph *g, int64_t mem_budget, int32_t max
     S->stats.mem_held = S->mem_held;
     S->stats.spill_tables[0] = slots[0];
     S->stats.spill_tables[1] = slots[1];
+    // start-stage routing needs the adjacency on the host: kept for graphs
+    // of up to 2^28 entries (1 GiB)
+    for (int k = 0; k < S->n_stages; ++k)
+        S->stage_cap[k] = S->tp.t[S->stages[k].first].cap;
+    if (S->n_stages >= 2 && g->nnz <= ((int64_t)1 << 28)) {
+        try {
+            S->h_row_ptr.resize((size_t)g->n + 1);
+            S->h_col.resize((size_t)std::max<int64_t>(g->nnz, 1));
+        } catch (...) {
+            server_release(S);
+            return fail(LCD_ENOMEM, "host allocation failed");
+        }
+        hipError_t e = hipMemcpy(S->h_row_ptr.data(), g->row_ptr, sizeof(int32_t) * ((size_t)g->n + 1),
+                                 hipMemcpyDeviceToHost);
+        if (e == hipSuccess && g->nnz > 0)
+            e = hipMemcpy(S->h_col.data(), g->col, sizeof(int32_t) * (size_t)g->nnz, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            server_release(S);
+            return fail(LCD_EDEVICE, "copying the graph to the host: %s", hipGetErrorString(e));
+        }
+        S->route = true;
+    }
     try {
         S->worker = std::thread(worker_main, S);
     } catch (...) {
@@ -788,6 +821,44 @@ lcd_status lcd_server_create(const lcd_graph *g, int64_t mem_budget, int32_t max
     }
     *out = S;
     return LCD_OK;
+}
+
+// The first stage whose table holds the query's initial table (its seeds
+// and their neighbours): every earlier stage would overflow at once.
+// Counting stops past the largest table that leaves a later stage.
+static int start_stage(const lcd_server *S, const std::vector<int32_t> &seeds) {
+    if (!S->route || S->n_stages < 2)
+        return 0;
+    const int32_t n = S->g->n;
+    thread_local std::vector<uint32_t> stamp;
+    thread_local uint32_t epoch = 0;
+    if ((int32_t)stamp.size() != n) {
+        stamp.assign((size_t)n, 0u);
+        epoch = 0;
+    }
+    if (++epoch == 0) {
+        std::fill(stamp.begin(), stamp.end(), 0u);
+        epoch = 1;
+    }
+    const int64_t limit = S->stage_cap[S->n_stages - 2];
+    int64_t cnt = 0;
+    auto see = [&](int32_t v) {
+        if (stamp[v] != epoch) {
+            stamp[v] = epoch;
+            ++cnt;
+        }
+    };
+    for (int32_t v : seeds) {
+        see(v);
+        for (int32_t j = S->h_row_ptr[v]; j < S->h_row_ptr[v + 1] && cnt <= limit; ++j)
+            see(S->h_col[j]);
+        if (cnt > limit)
+            break;
+    }
+    int k = 0;
+    while (k + 1 < S->n_stages && cnt > S->stage_cap[k])
+        ++k;
+    return k;
 }
 
 lcd_status lcd_server_submit(lcd_server *S, const int32_t *seeds, int32_t n, double alpha,
@@ -817,6 +888,7 @@ lcd_status lcd_server_submit(lcd_server *S, const int32_t *seeds, int32_t n, dou
     q->alpha = alpha;
     q->reserve = std::min<int64_t>(S->lanes[0].pool_cap, 4 * (int64_t)n + 2048);
     q->info.t_submit_ns = now_ns();
+    const int start = start_stage(S, q->seeds);
     {
         std::lock_guard<std::mutex> lk(S->mu);
         if (S->stop) {
@@ -825,7 +897,14 @@ lcd_status lcd_server_submit(lcd_server *S, const int32_t *seeds, int32_t n, dou
         }
         q->ticket = S->next_ticket++;
         S->tickets[q->ticket] = q;
-        S->pending.push_back(q);
+        if (start > 0 && S->in_flight < S->max_slots) {
+            // admitted here, as a query forwarded to that stage would be
+            S->in_flight += 1;
+            S->forwarded[start].push_back(q);
+            S->stats.routed += 1;
+        } else {
+            S->pending.push_back(q);
+        }
         S->stats.submitted += 1;
         *ticket = q->ticket;
     }

@@ -100,7 +100,7 @@ class lcd_server_stats(ctypes.Structure):
                 ("lanes", ctypes.c_int32), ("spill_lanes", ctypes.c_int32),
                 ("max_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
                 ("max_lanes_busy", ctypes.c_int32), ("spill_tables", ctypes.c_int32 * 2),
-                ("pad", ctypes.c_int32), ("cancelled", ctypes.c_int64)]
+                ("pad", ctypes.c_int32), ("cancelled", ctypes.c_int64), ("routed", ctypes.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("spill_tables", "pad")}
