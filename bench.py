@@ -38,7 +38,7 @@ if int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0) < 12:
 METRIC = ("candidate-node gains/s + full multi-scale sweep time; "
           "p50/p99 seed-query latency")
 HBM_PEAK_GBS = 8000.0
-SUMMARY_BYTES = 24        # per (set, scale): K, V, f (the survey's algorithmic output unit)
+SUMMARY_BYTES = 24        # per (set, scale): K, V, f (the algorithmic output unit)
 XL_STRIDE = 64            # default seed share of the 10M-node workload
 KERNEL_OF_KIND = {0: "sweep_lds_kernel", 1: "sweep_global_kernel", 2: "sweep_team_lds_kernel",
                   3: "sweep_team_global_kernel"}
@@ -86,7 +86,7 @@ def workload(name: str):
 
 
 def gather_bytes(t: dict, weighted: bool) -> int:
-    """Algorithmic input bytes of one tier (the survey's measurement rules):
+    """Algorithmic input bytes of one tier (the measurement rules):
     per CSR row that a move or a seed-set member gathers, its two offsets and
     its entries (id, plus weight); one degree read per table entry created
     for a committed scale.  Rows that a set resumed from a record gathers
@@ -548,7 +548,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(asked for --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
 
